@@ -1,0 +1,933 @@
+/*
+ * lbref.c -- FP64 CPU oracle of the coupled lattice Boltzmann freezing step
+ * of arXiv 2511.09422 (Huang, Chai, Liu, Huang).  TEST INFRASTRUCTURE ONLY:
+ * only tests, the smoke check and the benchmark's CPU-baseline leg load it.
+ *
+ * One time step, in the order the paper's Sec. 3 implies:
+ *   1. closure       phi0 = sum f, E0 = sum h, C = sum l; enthalpy map (Eq. Hfl)
+ *                    with a liquid-fraction weight psi; phase-change source
+ *                    mdot (Eq. NS1); phi from the phase-field moment equation
+ *                    (Sec. 3.1) with div u = mdot; property interpolation
+ *                    (end of Sec. 2).
+ *   2. stencils      isotropic gradient / Laplacian (end of Sec. 3.4).
+ *   3. forces        chemical potential, capillary + Marangoni force (Eq. Fs),
+ *                    equation of state for sigma, solid drag (Sec. 3.2).
+ *   4. collisions    flow BGK (Sec. 3.2), phase-field BGK (Sec. 3.1),
+ *                    enthalpy TRT (Sec. 3.3), solute BGK (Sec. 3.4).
+ *   5. streaming     pull streaming on two arrays; periodic axes, half-way
+ *                    bounce-back walls, anti-bounce-back Dirichlet temperature
+ *                    walls (Sec. 4.5 names both schemes).
+ *
+ * Readings where the paper is silent, garbled or inconsistent are marked
+ * "Reading:" at the place they act.  Plain loops, no blocking, no fusion.
+ */
+#include "lbref.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define CS2 (1.0 / 3.0)
+#define QMAX 19
+
+typedef struct {
+  int q;
+  int c[QMAX][3];
+  double w[QMAX];
+  int opp[QMAX];
+} lat_t;
+
+/* Lattices.  Sec. 3 fixes cs = c/sqrt(3) for every equation but does not name
+ * the velocity sets.  Reading: flow D2Q9 / D3Q19; phase field, enthalpy and
+ * solute D2Q5 / D3Q7.  D2Q5 weights (1/3, 1/6) and D3Q7 weights (0, 1/6) are
+ * the ones that give sum w c c = cs^2 I with cs^2 = 1/3. */
+static void lat_init(lat_t* L, int dim, int flow) {
+  memset(L, 0, sizeof(*L));
+  if (dim == 2) {
+    static const int c9[9][2] = {{0, 0},  {1, 0},  {0, 1},   {-1, 0}, {0, -1},
+                                 {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+    L->q = flow ? 9 : 5;
+    for (int i = 0; i < L->q; ++i) {
+      L->c[i][0] = c9[i][0];
+      L->c[i][1] = c9[i][1];
+      L->c[i][2] = 0;
+    }
+    if (flow) {
+      L->w[0] = 4.0 / 9.0;
+      for (int i = 1; i < 5; ++i) L->w[i] = 1.0 / 9.0;
+      for (int i = 5; i < 9; ++i) L->w[i] = 1.0 / 36.0;
+    } else {
+      L->w[0] = 1.0 / 3.0;
+      for (int i = 1; i < 5; ++i) L->w[i] = 1.0 / 6.0;
+    }
+  } else {
+    int n = 0;
+    L->c[n][0] = L->c[n][1] = L->c[n][2] = 0;
+    ++n;
+    for (int a = 0; a < 3; ++a)
+      for (int s = 1; s >= -1; s -= 2) {
+        L->c[n][0] = L->c[n][1] = L->c[n][2] = 0;
+        L->c[n][a] = s;
+        ++n;
+      }
+    if (flow) {
+      for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b)
+          for (int sa = 1; sa >= -1; sa -= 2)
+            for (int sb = 1; sb >= -1; sb -= 2) {
+              L->c[n][0] = L->c[n][1] = L->c[n][2] = 0;
+              L->c[n][a] = sa;
+              L->c[n][b] = sb;
+              ++n;
+            }
+    }
+    L->q = n;
+    if (flow) {
+      L->w[0] = 1.0 / 3.0;
+      for (int i = 1; i < 7; ++i) L->w[i] = 1.0 / 18.0;
+      for (int i = 7; i < 19; ++i) L->w[i] = 1.0 / 36.0;
+    } else {
+      L->w[0] = 0.0;
+      for (int i = 1; i < 7; ++i) L->w[i] = 1.0 / 6.0;
+    }
+  }
+  for (int i = 0; i < L->q; ++i)
+    for (int j = 0; j < L->q; ++j)
+      if (L->c[j][0] == -L->c[i][0] && L->c[j][1] == -L->c[i][1] &&
+          L->c[j][2] == -L->c[i][2])
+        L->opp[i] = j;
+}
+
+struct lbref_state {
+  lbref_params P;
+  int N;
+  lat_t Lg, Ls;
+  double *f, *g, *h, *l;     /* populations at time n, [q][N] */
+  double *f2, *g2, *h2, *l2; /* post-collision / streaming buffers */
+  /* time level n-1: solid fraction, pressure, velocity [3][N], phi, C */
+  double *fs_prev, *p_prev, *u_prev, *phi_prev, *C_prev;
+  uint8_t* mask;
+  double mpc;  /* accumulated sum_x phi div u (phase-field source) */
+  double qacc; /* accumulated sum_x Q (enthalpy source) */
+  int64_t step;
+  /* per-step work arrays */
+  double *phi, *T, *C, *fs, *fl, *mdot, *E, *Q, *rho, *rhocp, *divu;
+  double *grad; /* [5][3][N]: phi, T, C, f_s, p^{n-1} */
+  double *lapphi;
+  double *u;  /* [3][N] */
+  double *pn; /* p^n */
+};
+
+int lbref_q(int dim, int which) {
+  if (dim == 2) return which == 1 ? 9 : 5;
+  return which == 1 ? 19 : 7;
+}
+
+/* ---------------------------------------------------------------- geometry */
+
+static int wall_axis(const lbref_params* P) { return P->dim - 1; }
+
+static void coords(const lbref_params* P, int n, int* x, int* y, int* z) {
+  *x = n % P->nx;
+  *y = (n / P->nx) % P->ny;
+  *z = n / (P->nx * P->ny);
+}
+
+static int node_index(const lbref_params* P, int x, int y, int z) {
+  return (z * P->ny + y) * P->nx + x;
+}
+
+static int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+/* Low-wall temperature at tangential coordinate x (Dirichlet walls). */
+static double wall_T_lo(const lbref_params* P, int x) {
+  return P->T_lo + P->T_lo_amp * cos(2.0 * M_PI * (double)x / (double)P->nx);
+}
+
+/* Neighbour value of a scalar field for the isotropic stencils.
+ * kind 0 (phi, C, f_s, p): across a wall the ghost mirrors the first fluid
+ *   node (zero normal derivative; for phi this is the 90-degree contact
+ *   angle).  An obstacle neighbour takes the centre node's value.
+ * kind 1 (T): across a Dirichlet wall the ghost is 2 T_w - T(mirror), across
+ *   an adiabatic wall it mirrors; obstacle nodes conduct, so their own T is
+ *   used. */
+static double nb_value(const lbref_params* P, const uint8_t* mask, const double* fld,
+                       int n, const int* c, int kind) {
+  int x, y, z;
+  coords(P, n, &x, &y, &z);
+  int v[3] = {x + c[0], y + c[1], z + c[2]};
+  int dims[3] = {P->nx, P->ny, P->nz};
+  int wa = wall_axis(P);
+  int ghost_side = 0; /* -1 low, +1 high */
+  for (int a = 0; a < P->dim; ++a) {
+    if (P->walls && a == wa) {
+      if (v[a] < 0) {
+        ghost_side = -1;
+        v[a] = -1 - v[a];
+      } else if (v[a] >= dims[a]) {
+        ghost_side = 1;
+        v[a] = 2 * dims[a] - 1 - v[a];
+      }
+    } else {
+      v[a] = wrap(v[a], dims[a]);
+    }
+  }
+  int m = node_index(P, v[0], v[1], P->dim == 3 ? v[2] : 0);
+  if (ghost_side != 0) {
+    double val = fld[m];
+    if (kind == 1) {
+      if (ghost_side < 0 && P->t_lo_dirichlet) return 2.0 * wall_T_lo(P, v[0]) - val;
+      if (ghost_side > 0 && P->t_hi_dirichlet) return 2.0 * P->T_hi - val;
+    }
+    return val;
+  }
+  if (kind == 0 && mask && mask[m]) return fld[n];
+  return fld[m];
+}
+
+static void grad_lap_impl(const lbref_params* P, const lat_t* L, const uint8_t* mask,
+                          int N, const double* fld, int kind, double* grad, double* lap) {
+  int nt = P->threads > 0 ? P->threads : 1;
+#pragma omp parallel for num_threads(nt) schedule(static)
+  for (int n = 0; n < N; ++n) {
+    double gx = 0, gy = 0, gz = 0, lp = 0;
+    for (int i = 1; i < L->q; ++i) {
+      double v = nb_value(P, mask, fld, n, L->c[i], kind);
+      gx += L->w[i] * L->c[i][0] * v;
+      gy += L->w[i] * L->c[i][1] * v;
+      gz += L->w[i] * L->c[i][2] * v;
+      lp += 2.0 * L->w[i] * (v - fld[n]);
+    }
+    grad[0 * N + n] = gx / CS2;
+    grad[1 * N + n] = gy / CS2;
+    grad[2 * N + n] = gz / CS2;
+    if (lap) lap[n] = lp / CS2;
+  }
+}
+
+/* Isotropic second-order gradient and Laplacian with the flow-lattice weights
+ * (end of Sec. 3.4).  Reading: the weights are those of D2Q9 / D3Q19. */
+void lbref_grad_lap(const lbref_params* p, const double* field, int kind, double* grad,
+                    double* lap) {
+  lat_t L;
+  lat_init(&L, p->dim, 1);
+  int N = p->nx * p->ny * p->nz;
+  grad_lap_impl(p, &L, NULL, N, field, kind, grad, lap);
+}
+
+/* ----------------------------------------------------------- pointwise math */
+
+/* Enthalpy -> (T, f_l) map, Eq. (Hfl).  Reading: the paper writes the map
+ * with global rho_s H_s, rho_l H_l, which would label gas as solid; here the
+ * heat capacities and the latent heat are weighted by the phase-change
+ * material fraction psi = (1 + phi)/2, and f_s = psi (1 - f_l).  At psi = 1
+ * this is Eq. (Hfl) exactly. */
+void lbref_enthalpy_map(const lbref_params* P, double E, double psi, double* T, double* fl,
+                        double* fs) {
+  double rcs = psi * P->rho_s * P->cp_s + (1.0 - psi) * P->rho_g * P->cp_g;
+  double rcl = psi * P->rho_l * P->cp_l + (1.0 - psi) * P->rho_g * P->cp_g;
+  double Es = rcs * P->T_sol;
+  double El = rcl * P->T_liq + psi * P->rho_l * P->latent;
+  double f;
+  if (E < Es) {
+    f = 0.0;
+    *T = E / rcs;
+  } else if (E > El) {
+    f = 1.0;
+    *T = P->T_liq + (E - El) / rcl;
+  } else {
+    double d = El - Es;
+    f = (d <= 1e-12 * fmax(1.0, fabs(E))) ? 1.0 : (E - Es) / d;
+    *T = P->T_sol + f * (P->T_liq - P->T_sol);
+  }
+  *fl = f;
+  *fs = psi * (1.0 - f);
+}
+
+/* Property interpolation (end of Sec. 2): zeta = phi/2 (z_l - z_g) +
+ * f_s (z_s - z_l) + (z_l + z_g)/2. */
+static double interp(double phi, double fs, double zl, double zg, double zs) {
+  return 0.5 * phi * (zl - zg) + fs * (zs - zl) + 0.5 * (zl + zg);
+}
+
+static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
+
+static double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* Flow equilibrium, Sec. 3.2: g_0 = p/cs2 (w_0 - 1) + rho s_0(u),
+ * g_i = p/cs2 w_i + rho s_i(u). */
+void lbref_feq_g(int dim, double pr, double rho, const double* u, double* out) {
+  lat_t L;
+  lat_init(&L, dim, 1);
+  double uu = dot3(u, u);
+  for (int i = 0; i < L.q; ++i) {
+    double c[3] = {L.c[i][0], L.c[i][1], L.c[i][2]};
+    double cu = dot3(c, u);
+    double s = L.w[i] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    out[i] = pr / CS2 * (i == 0 ? L.w[i] - 1.0 : L.w[i]) + rho * s;
+  }
+}
+
+/* Flow forcing term, Sec. 3.2: G_i = w_i [S + c_i.(F + rho f)/cs2 +
+ * (u Ft + Ft u):(c_i c_i - cs2 I)/(2 cs2^2)]; Ff = F + rho f, Ft = F-tilde. */
+void lbref_src_g(int dim, double S, const double* Ff, const double* u, const double* Ft,
+                 double* out) {
+  lat_t L;
+  lat_init(&L, dim, 1);
+  double uFt = dot3(u, Ft);
+  for (int i = 0; i < L.q; ++i) {
+    double c[3] = {L.c[i][0], L.c[i][1], L.c[i][2]};
+    double cu = dot3(c, u), cFt = dot3(c, Ft), cFf = dot3(c, Ff);
+    /* (u Ft + Ft u) : (c c - cs2 I) = 2 (c.u)(c.Ft) - 2 cs2 (u.Ft) */
+    double quad = (2.0 * cu * cFt - 2.0 * CS2 * uFt) / (2.0 * CS2 * CS2);
+    out[i] = L.w[i] * (S + cFf / CS2 + quad);
+  }
+}
+
+/* Enthalpy equilibrium, Sec. 3.3.  Reading: "rho C_p,ref" in the rest
+ * component and "rho_ref C_p,ref" are one constant (rho C)_ref, which is what
+ * makes sum_i h_i^eq = rho H. */
+void lbref_heq(const lbref_params* P, double E, double T, double rhocp, const double* u,
+               double* out) {
+  lat_t L;
+  lat_init(&L, P->dim, 0);
+  double uu = dot3(u, u);
+  for (int i = 0; i < L.q; ++i) {
+    double c[3] = {L.c[i][0], L.c[i][1], L.c[i][2]};
+    double cu = dot3(c, u);
+    if (i == 0)
+      out[i] = E - P->rhoc_ref * T + L.w[0] * (P->rhoc_ref * T - rhocp * T * uu / (2.0 * CS2));
+    else
+      out[i] = L.w[i] * (P->rhoc_ref * T +
+                         rhocp * T * (cu / CS2 + (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2)));
+  }
+}
+
+/* --------------------------------------------------------------- lifecycle */
+
+static int valid_params(const lbref_params* P) {
+  if (!P) return 0;
+  if (P->dim != 2 && P->dim != 3) return 0;
+  if (P->nx < 1 || P->ny < 1 || P->nz < 1) return 0;
+  if (P->dim == 2 && P->nz != 1) return 0;
+  if (P->tau_phi <= 0.5 || P->tau_h <= 0.5 || P->tau_c <= 0.5 || P->nu <= 0.0) return 0;
+  if (P->eps <= 0.0 || P->rhoc_ref <= 0.0) return 0;
+  if (P->rho_l <= 0 || P->rho_g <= 0 || P->rho_s <= 0) return 0;
+  return 1;
+}
+
+void lbref_destroy(lbref_state* s) {
+  if (!s) return;
+  double* bufs[] = {s->f,   s->g,   s->h,      s->l,    s->f2,   s->g2,      s->h2,
+                    s->l2,  s->fs_prev, s->p_prev, s->u_prev, s->phi_prev, s->C_prev, s->phi,
+                    s->divu,
+                    s->T,   s->C,   s->fs,     s->fl,   s->mdot, s->E,       s->Q,
+                    s->rho, s->rhocp, s->grad, s->lapphi, s->u,  s->pn};
+  for (size_t k = 0; k < sizeof(bufs) / sizeof(bufs[0]); ++k) free(bufs[k]);
+  free(s->mask);
+  free(s);
+}
+
+int lbref_create(const lbref_params* P, const double* phi_in, const double* T_in,
+                 const double* C_in, const uint8_t* mask_in, lbref_state** out) {
+  if (!out || !valid_params(P) || !phi_in || !T_in || !C_in) return -1;
+  *out = NULL;
+  lbref_state* s = (lbref_state*)calloc(1, sizeof(lbref_state));
+  if (!s) return -2;
+  s->P = *P;
+  if (s->P.threads < 1) s->P.threads = 1;
+  int N = P->nx * P->ny * P->nz;
+  s->N = N;
+  lat_init(&s->Lg, P->dim, 1);
+  lat_init(&s->Ls, P->dim, 0);
+  int qg = s->Lg.q, qs = s->Ls.q;
+#define ALLOC(ptr, cnt)                                  \
+  do {                                                   \
+    (ptr) = (double*)calloc((size_t)(cnt), sizeof(double)); \
+    if (!(ptr)) {                                        \
+      lbref_destroy(s);                                  \
+      return -2;                                         \
+    }                                                    \
+  } while (0)
+  ALLOC(s->f, qs * N);
+  ALLOC(s->g, qg * N);
+  ALLOC(s->h, qs * N);
+  ALLOC(s->l, qs * N);
+  ALLOC(s->f2, qs * N);
+  ALLOC(s->g2, qg * N);
+  ALLOC(s->h2, qs * N);
+  ALLOC(s->l2, qs * N);
+  ALLOC(s->fs_prev, N);
+  ALLOC(s->p_prev, N);
+  ALLOC(s->u_prev, 3 * N);
+  ALLOC(s->phi_prev, N);
+  ALLOC(s->C_prev, N);
+  ALLOC(s->divu, N);
+  ALLOC(s->phi, N);
+  ALLOC(s->T, N);
+  ALLOC(s->C, N);
+  ALLOC(s->fs, N);
+  ALLOC(s->fl, N);
+  ALLOC(s->mdot, N);
+  ALLOC(s->E, N);
+  ALLOC(s->Q, N);
+  ALLOC(s->rho, N);
+  ALLOC(s->rhocp, N);
+  ALLOC(s->grad, 15 * N);
+  ALLOC(s->lapphi, N);
+  ALLOC(s->u, 3 * N);
+  ALLOC(s->pn, N);
+#undef ALLOC
+  if (mask_in) {
+    s->mask = (uint8_t*)malloc((size_t)N);
+    if (!s->mask) {
+      lbref_destroy(s);
+      return -2;
+    }
+    for (int n = 0; n < N; ++n) s->mask[n] = mask_in[n] ? 1 : 0;
+  }
+  for (int n = 0; n < N; ++n)
+    if (!isfinite(phi_in[n]) || !isfinite(T_in[n]) || !isfinite(C_in[n])) {
+      lbref_destroy(s);
+      return -1;
+    }
+  /* Initial state: u = 0, p = 0, f_l = 1; every population at equilibrium.
+   * Reading: the enthalpy starts on the liquid branch, E = (rho C)_lb T +
+   * psi rho_l L, so that the first closure returns the given T wherever
+   * T >= T_liq. */
+  double zero[3] = {0, 0, 0};
+  for (int n = 0; n < N; ++n) {
+    int ob = s->mask && s->mask[n];
+    double phi = ob ? -1.0 : phi_in[n];
+    double C = ob ? 0.0 : C_in[n];
+    double psi = clamp01(0.5 * (1.0 + phi));
+    double rcl = psi * P->rho_l * P->cp_l + (1.0 - psi) * P->rho_g * P->cp_g;
+    double E = rcl * T_in[n] + psi * P->rho_l * P->latent;
+    double heq[QMAX];
+    lbref_heq(&s->P, E, T_in[n], 0.0, zero, heq);
+    for (int i = 0; i < qs; ++i) {
+      s->h[i * N + n] = heq[i];
+      s->f[i * N + n] = ob ? 0.0 : s->Ls.w[i] * phi;
+      s->l[i * N + n] = ob ? 0.0 : s->Ls.w[i] * C;
+    }
+    for (int i = 0; i < qg; ++i) s->g[i * N + n] = 0.0;
+  }
+  *out = s;
+  return 0;
+}
+
+/* ----------------------------------------------------------------- the step */
+
+/* Velocity of the previous time level at a stencil neighbour.  Across a
+ * no-slip wall (half-way, at +-1/2) the ghost is the negated mirror value, so
+ * that u vanishes on the wall; an obstacle neighbour likewise gives the
+ * negated centre value. */
+static double nb_u(const lbref_state* s, int n, const int* c, int comp) {
+  const lbref_params* P = &s->P;
+  int N = s->N;
+  int x, y, z;
+  coords(P, n, &x, &y, &z);
+  int v[3] = {x + c[0], y + c[1], z + c[2]};
+  int dims[3] = {P->nx, P->ny, P->nz};
+  int wa = wall_axis(P);
+  int ghost = 0;
+  for (int a = 0; a < P->dim; ++a) {
+    if (P->walls && a == wa) {
+      if (v[a] < 0) {
+        ghost = 1;
+        v[a] = -1 - v[a];
+      } else if (v[a] >= dims[a]) {
+        ghost = 1;
+        v[a] = 2 * dims[a] - 1 - v[a];
+      }
+    } else {
+      v[a] = wrap(v[a], dims[a]);
+    }
+  }
+  int m = node_index(P, v[0], v[1], P->dim == 3 ? v[2] : 0);
+  if (ghost) return -s->u_prev[comp * N + m];
+  if (s->mask && s->mask[m]) return -s->u_prev[comp * N + n];
+  return s->u_prev[comp * N + m];
+}
+
+/* div u of the previous time level by the isotropic gradient stencil (end of
+ * Sec. 3.4).  Reading: wherever Sec. 3.1 and Sec. 3.3 write div u (phase-field
+ * source and moment, enthalpy source and moment) it is the divergence of the
+ * flow field itself, lagged one step because the current velocity needs the
+ * current phi.  It equals mdot where the flow scheme's mass source acts and
+ * also carries the compression of the surrounding fluid, which is what keeps
+ * the phase-change material's volume consistent with Eq. NS1 in a closed box. */
+static void divergence_all(lbref_state* s) {
+  const lbref_params* P = &s->P;
+  const lat_t* L = &s->Lg;
+  int N = s->N;
+  int nt = P->threads;
+#pragma omp parallel for num_threads(nt) schedule(static)
+  for (int n = 0; n < N; ++n) {
+    if (s->mask && s->mask[n]) {
+      s->divu[n] = 0.0;
+      continue;
+    }
+    double d = 0.0;
+    for (int i = 1; i < L->q; ++i)
+      for (int a = 0; a < P->dim; ++a)
+        if (L->c[i][a]) d += L->w[i] * L->c[i][a] * nb_u(s, n, L->c[i], a);
+    s->divu[n] = d / CS2;
+  }
+}
+
+/* Pointwise closure for every node (Sec. 3.1, 3.3, 3.4 moment equations,
+ * Eq. NS1, Eq. Hfl, property interpolation). */
+static void closure_all(lbref_state* s) {
+  const lbref_params* P = &s->P;
+  int N = s->N, qs = s->Ls.q;
+  int nt = P->threads;
+#pragma omp parallel for num_threads(nt) schedule(static)
+  for (int n = 0; n < N; ++n) {
+    double phi0 = 0, E0 = 0, C = 0;
+    for (int i = 0; i < qs; ++i) {
+      phi0 += s->f[i * N + n];
+      E0 += s->h[i * N + n];
+      C += s->l[i * N + n];
+    }
+    if (s->mask && s->mask[n]) {
+      double T, fl, fs;
+      lbref_enthalpy_map(P, E0, 0.0, &T, &fl, &fs);
+      s->phi[n] = -1.0;
+      s->C[n] = 0.0;
+      s->T[n] = T;
+      s->fl[n] = 1.0;
+      s->fs[n] = 0.0;
+      (void)fl;
+      s->mdot[n] = 0.0;
+      s->Q[n] = 0.0;
+      s->E[n] = E0;
+      s->rho[n] = P->rho_g;
+      s->rhocp[n] = P->rho_g * P->cp_g;
+      continue;
+    }
+    double psi = clamp01(0.5 * (1.0 + phi0));
+    double ratio = 1.0 - P->rho_s / P->rho_l;
+    double D = s->divu[n];
+    /* Sec. 3.1: phi = sum f + dt/2 phi div u, solved exactly for phi. */
+    double phi = phi0 / (1.0 - 0.5 * D);
+    /* Sec. 3.3: rho H = sum h + dt/2 rho C_p T div u is implicit in T through
+     * the enthalpy map.  Reading: one predictor (from E0) and one corrector;
+     * the predictor's source Q is the one the collision adds as well. */
+    double T0, fl0, fs0;
+    lbref_enthalpy_map(P, E0, psi, &T0, &fl0, &fs0);
+    double rhocp0 = interp(phi, fs0, P->rho_l, P->rho_g, P->rho_s) *
+                    interp(phi, fs0, P->cp_l, P->cp_g, P->cp_s);
+    double Q = rhocp0 * T0 * D;
+    double E = E0 + 0.5 * Q;
+    double T, fl, fs;
+    lbref_enthalpy_map(P, E, psi, &T, &fl, &fs);
+    /* Eq. NS1 with a backward difference in time for d f_s / dt. */
+    double mdot = ratio * (fs - s->fs_prev[n]);
+    double rho = interp(phi, fs, P->rho_l, P->rho_g, P->rho_s);
+    double cp = interp(phi, fs, P->cp_l, P->cp_g, P->cp_s);
+    s->phi[n] = phi;
+    s->C[n] = C;
+    s->T[n] = T;
+    /* reported liquid fraction: 1 - f_s, so that gas (f_s = 0) reads 1 */
+    s->fl[n] = 1.0 - fs;
+    (void)fl;
+    s->fs[n] = fs;
+    s->mdot[n] = mdot;
+    s->Q[n] = Q;
+    s->E[n] = E;
+    s->rho[n] = rho;
+    s->rhocp[n] = rho * cp;
+  }
+}
+
+static void gradients_all(lbref_state* s) {
+  int N = s->N;
+  const double* flds[5] = {s->phi, s->T, s->C, s->fs, s->p_prev};
+  int kinds[5] = {0, 1, 0, 0, 0};
+  for (int k = 0; k < 5; ++k)
+    grad_lap_impl(&s->P, &s->Lg, s->mask, N, flds[k], kinds[k], s->grad + 3 * k * N,
+                  k == 0 ? s->lapphi : NULL);
+}
+
+/* Interface force, velocity and pressure at node n (Eq. Fs, Sec. 3.2).
+ * Writes u[3], the total force F[3], drag acceleration fd[3], S, F-tilde[3],
+ * the interface normal nvec[3], and returns p^n. */
+static double forces_node(const lbref_state* s, int n, double* u, double* F, double* fd,
+                          double* Sout, double* Ft, double* nvec) {
+  const lbref_params* P = &s->P;
+  int N = s->N;
+  const lat_t* Lg = &s->Lg;
+  double gphi[3], gT[3], gC[3], gfs[3], gp[3];
+  for (int a = 0; a < 3; ++a) {
+    gphi[a] = s->grad[(0 * 3 + a) * N + n];
+    gT[a] = s->grad[(1 * 3 + a) * N + n];
+    gC[a] = s->grad[(2 * 3 + a) * N + n];
+    gfs[a] = s->grad[(3 * 3 + a) * N + n];
+    gp[a] = s->grad[(4 * 3 + a) * N + n];
+  }
+  double phi = s->phi[n], fs = s->fs[n], rho = s->rho[n];
+  double grho[3];
+  for (int a = 0; a < 3; ++a)
+    grho[a] = 0.5 * (P->rho_l - P->rho_g) * gphi[a] + (P->rho_s - P->rho_l) * gfs[a];
+  double ng = sqrt(dot3(gphi, gphi));
+  /* Reading: n = grad phi / |grad phi| is taken as 0 where |grad phi| < 1e-10. */
+  for (int a = 0; a < 3; ++a) nvec[a] = ng >= 1e-10 ? gphi[a] / ng : 0.0;
+  /* Chemical potential with phi1 = 1, phi2 = -1, k = 1, beta = 1/(4 eps^2). */
+  double mu = phi * (phi * phi - 1.0) / (P->eps * P->eps) - s->lapphi[n];
+  double sigma = P->sigma0 + P->sigma_T * (s->T[n] - P->T_ref) + P->sigma_c * (s->C[n] - P->c_ref);
+  double gsig[3];
+  for (int a = 0; a < 3; ++a) gsig[a] = P->sigma_T * gT[a] + P->sigma_c * gC[a];
+  double alpha = 3.0 * sqrt(2.0) * P->eps / 4.0;
+  double gsdp = dot3(gsig, gphi);
+  /* Reading of Eq. Fs: the capillary part is alpha sigma mu_phi grad phi; the
+   * printed extra 1/eps^2 would double-count the 1/eps^2 already inside mu_phi
+   * (beta = 1/(4 eps^2)) and break the Laplace law. */
+  double wst = P->surface_tension_mode == 0 ? (1.0 - fs) : 1.0;
+  for (int a = 0; a < 3; ++a) {
+    double FsC = alpha * sigma * mu * gphi[a];
+    double FsM = alpha * (ng * ng * gsig[a] - gsdp * gphi[a]);
+    F[a] = wst * (FsC + FsM) + P->body_force[a];
+  }
+  double mom[3] = {0, 0, 0};
+  for (int i = 0; i < Lg->q; ++i)
+    for (int a = 0; a < 3; ++a) mom[a] += Lg->c[i][a] * s->g[i * N + n];
+  double ustar[3];
+  for (int a = 0; a < 3; ++a) {
+    ustar[a] = (mom[a] + 0.5 * F[a]) / rho;
+    fd[a] = -fs * ustar[a]; /* f = f_s (u_s - u*) / dt with u_s = 0 */
+    u[a] = ustar[a] + 0.5 * fd[a];
+  }
+  double S = rho * s->mdot[n] + dot3(u, grho);
+  /* Reading: F-tilde = F - grad p + cs2 grad rho; the printed extra
+   * "cs2 div S" (divergence of a scalar) is dropped, and grad p is the
+   * gradient of the previous step's pressure. */
+  for (int a = 0; a < 3; ++a) Ft[a] = F[a] - gp[a] + CS2 * grho[a];
+  *Sout = S;
+  double Ff[3];
+  for (int a = 0; a < 3; ++a) Ff[a] = F[a] + rho * fd[a];
+  double G[QMAX];
+  lbref_src_g(P->dim, S, Ff, u, Ft, G);
+  double sum_nz = 0.0;
+  for (int i = 1; i < Lg->q; ++i) sum_nz += s->g[i * N + n];
+  double tau_g = P->nu / CS2 + 0.5;
+  double s0 = Lg->w[0] * (-dot3(u, u) / (2.0 * CS2));
+  /* Sec. 3.2 pressure, with the literal tau dt G_0 term. */
+  return CS2 / (1.0 - Lg->w[0]) * (sum_nz + 0.5 * S + tau_g * G[0] + rho * s0);
+}
+
+static void collide_all(lbref_state* s) {
+  const lbref_params* P = &s->P;
+  int N = s->N;
+  const lat_t* Lg = &s->Lg;
+  const lat_t* Ls = &s->Ls;
+  int qg = Lg->q, qs = Ls->q;
+  double tau_g = P->nu / CS2 + 0.5;
+  double tau_f = P->tau_phi;
+  double tau_a = P->tau_h;                  /* antisymmetric */
+  double tau_s = tau_a / (2.0 * tau_a - 1.0); /* 1/tau_s + 1/tau_a = 2 */
+  double Dl = CS2 * (P->tau_c - 0.5);
+  double Ds = P->Ds_over_Dl * Dl;
+  double isq = 1.0 / (sqrt(2.0) * P->eps);
+  int nt = P->threads;
+#pragma omp parallel for num_threads(nt) schedule(static)
+  for (int n = 0; n < N; ++n) {
+    double zero[3] = {0, 0, 0};
+    if (s->mask && s->mask[n]) {
+      /* obstacle: pure conduction of h at rest, no source */
+      double heq[QMAX];
+      lbref_heq(P, s->E[n], s->T[n], s->rhocp[n], zero, heq);
+      for (int i = 0; i < qs; ++i) {
+        int o = Ls->opp[i];
+        double hi = s->h[i * N + n], ho = s->h[o * N + n];
+        double hs = 0.5 * (hi + ho), ha = 0.5 * (hi - ho);
+        double es = 0.5 * (heq[i] + heq[o]), ea = 0.5 * (heq[i] - heq[o]);
+        s->h2[i * N + n] = hi - (hs - es) / tau_s - (ha - ea) / tau_a;
+      }
+      for (int i = 0; i < qs; ++i) s->f2[i * N + n] = s->l2[i * N + n] = 0.0;
+      for (int i = 0; i < qg; ++i) s->g2[i * N + n] = 0.0;
+      for (int a = 0; a < 3; ++a) s->u[a * N + n] = 0.0;
+      s->pn[n] = 0.0;
+      continue;
+    }
+    double u[3], F[3], fd[3], S, Ft[3], nv[3];
+    double pn = forces_node(s, n, u, F, fd, &S, Ft, nv);
+    for (int a = 0; a < 3; ++a) s->u[a * N + n] = u[a];
+    s->pn[n] = pn;
+    double phi = s->phi[n], rho = s->rho[n], C = s->C[n], fs = s->fs[n];
+    /* flow BGK (Sec. 3.2) */
+    double geq[QMAX], G[QMAX], Ff[3];
+    lbref_feq_g(P->dim, pn, rho, u, geq);
+    for (int a = 0; a < 3; ++a) Ff[a] = F[a] + rho * fd[a];
+    lbref_src_g(P->dim, S, Ff, u, Ft, G);
+    for (int i = 0; i < qg; ++i) {
+      double gi = s->g[i * N + n];
+      s->g2[i * N + n] = gi - (gi - geq[i]) / tau_g + (1.0 - 0.5 / tau_g) * G[i];
+    }
+    /* phase field BGK (Sec. 3.1), d/dt (phi u) by a backward difference */
+    double Bf[3];
+    for (int a = 0; a < 3; ++a)
+      Bf[a] = (phi * u[a] - s->phi_prev[n] * s->u_prev[a * N + n]) +
+              CS2 * nv[a] * (1.0 - phi * phi) * isq;
+    for (int i = 0; i < qs; ++i) {
+      double c[3] = {Ls->c[i][0], Ls->c[i][1], Ls->c[i][2]};
+      double Fi = Ls->w[i] * dot3(c, Bf) / CS2 + Ls->w[i] * phi * s->divu[n];
+      double feq = Ls->w[i] * phi * (1.0 + dot3(c, u) / CS2);
+      double fi = s->f[i * N + n];
+      s->f2[i * N + n] = fi - (fi - feq) / tau_f + (1.0 - 0.5 / tau_f) * Fi;
+    }
+    /* enthalpy TRT (Sec. 3.3).  Reading: the source is w_i Q with
+     * Q = rho C_p T div u, weighted by (1 - 1/(2 tau_s)) of the symmetric
+     * relaxation time, so that sum h gains exactly Q per step. */
+    double heq[QMAX];
+    lbref_heq(P, s->E[n], s->T[n], s->rhocp[n], u, heq);
+    for (int i = 0; i < qs; ++i) {
+      int o = Ls->opp[i];
+      double hi = s->h[i * N + n], ho = s->h[o * N + n];
+      double hs = 0.5 * (hi + ho), ha = 0.5 * (hi - ho);
+      double es = 0.5 * (heq[i] + heq[o]), ea = 0.5 * (heq[i] - heq[o]);
+      s->h2[i * N + n] = hi - (hs - es) / tau_s - (ha - ea) / tau_a +
+                         (1.0 - 0.5 / tau_s) * Ls->w[i] * s->Q[n];
+    }
+    /* solute BGK (Sec. 3.4), with the relaxation time from D_e and k_eff */
+    double keff = 1.0 - fs * (1.0 - P->k_p);
+    double De = fs * P->k_p * Ds + (1.0 - fs) * Dl;
+    double tau_l = De / (CS2 * keff) + 0.5;
+    double gfs[3], Bl[3];
+    for (int a = 0; a < 3; ++a) gfs[a] = s->grad[(3 * 3 + a) * N + n];
+    for (int a = 0; a < 3; ++a) {
+      double R = (1.0 - phi) * C * nv[a] * isq + (P->k_p - 1.0) * C * gfs[a] / keff;
+      Bl[a] = (C * u[a] - s->C_prev[n] * s->u_prev[a * N + n]) + CS2 * R;
+    }
+    for (int i = 0; i < qs; ++i) {
+      double c[3] = {Ls->c[i][0], Ls->c[i][1], Ls->c[i][2]};
+      double Li = Ls->w[i] * dot3(c, Bl) / CS2;
+      double leq = Ls->w[i] * C * (1.0 + dot3(c, u) / CS2);
+      double li = s->l[i * N + n];
+      s->l2[i * N + n] = li - (li - leq) / tau_l + (1.0 - 0.5 / tau_l) * Li;
+    }
+  }
+}
+
+/* Pull streaming from the post-collision arrays (f2, g2, h2, l2) into
+ * (f, g, h, l).  A link whose source lies beyond a wall is closed by half-way
+ * bounce-back, or for h at a Dirichlet wall by anti-bounce-back
+ * h_i(x, t+1) = -h*_opp(x) + 2 w_i (rho C)_ref T_w.  A link whose source is an
+ * obstacle node is bounced back for f, g, l; h streams through obstacles. */
+static void stream_set(const lbref_state* s, const lat_t* L, const double* post, double* dst,
+                       int is_h) {
+  const lbref_params* P = &s->P;
+  int N = s->N;
+  int dims[3] = {P->nx, P->ny, P->nz};
+  int wa = wall_axis(P);
+  int nt = P->threads;
+#pragma omp parallel for num_threads(nt) schedule(static)
+  for (int n = 0; n < N; ++n) {
+    int x, y, z;
+    coords(P, n, &x, &y, &z);
+    int here_ob = s->mask && s->mask[n];
+    if (here_ob && !is_h) {
+      for (int i = 0; i < L->q; ++i) dst[i * N + n] = 0.0;
+      continue;
+    }
+    for (int i = 0; i < L->q; ++i) {
+      int v[3] = {x - L->c[i][0], y - L->c[i][1], z - L->c[i][2]};
+      int side = 0;
+      for (int a = 0; a < P->dim; ++a) {
+        if (P->walls && a == wa) {
+          if (v[a] < 0) side = -1;
+          else if (v[a] >= dims[a]) side = 1;
+        } else {
+          v[a] = wrap(v[a], dims[a]);
+        }
+      }
+      int o = L->opp[i];
+      if (side != 0) {
+        double val = post[o * N + n];
+        if (is_h && side < 0 && P->t_lo_dirichlet)
+          val = -val + 2.0 * L->w[i] * P->rhoc_ref * wall_T_lo(P, x);
+        else if (is_h && side > 0 && P->t_hi_dirichlet)
+          val = -val + 2.0 * L->w[i] * P->rhoc_ref * P->T_hi;
+        dst[i * N + n] = val;
+        continue;
+      }
+      int m = node_index(P, v[0], v[1], P->dim == 3 ? v[2] : 0);
+      if (!is_h && s->mask && s->mask[m]) {
+        dst[i * N + n] = post[o * N + n];
+        continue;
+      }
+      dst[i * N + n] = post[i * N + m];
+    }
+  }
+}
+
+static void step_once(lbref_state* s) {
+  int N = s->N;
+  divergence_all(s);
+  closure_all(s);
+  gradients_all(s);
+  collide_all(s);
+  stream_set(s, &s->Ls, s->f2, s->f, 0);
+  stream_set(s, &s->Lg, s->g2, s->g, 0);
+  stream_set(s, &s->Ls, s->h2, s->h, 1);
+  stream_set(s, &s->Ls, s->l2, s->l, 0);
+  /* time-level state for the next step, and the phase-change mass budget */
+  double acc = 0.0, qa = 0.0;
+  for (int n = 0; n < N; ++n) {
+    int ob = s->mask && s->mask[n];
+    s->fs_prev[n] = ob ? 0.0 : s->fs[n];
+    s->p_prev[n] = s->pn[n];
+    s->phi_prev[n] = s->phi[n];
+    s->C_prev[n] = s->C[n];
+    for (int a = 0; a < 3; ++a) s->u_prev[a * N + n] = s->u[a * N + n];
+    if (!ob) acc += s->phi[n] * s->divu[n];
+    qa += s->Q[n];
+  }
+  s->mpc += acc;
+  s->qacc += qa;
+  s->step += 1;
+}
+
+int lbref_step(lbref_state* s, int64_t nsteps) {
+  if (!s || nsteps < 0) return -1;
+  for (int64_t k = 0; k < nsteps; ++k) step_once(s);
+  return 0;
+}
+
+/* Dry evaluation of the macroscopic fields at the current time level. */
+static void evaluate_fields(lbref_state* s) {
+  divergence_all(s);
+  closure_all(s);
+  gradients_all(s);
+  int N = s->N;
+  int nt = s->P.threads;
+#pragma omp parallel for num_threads(nt) schedule(static)
+  for (int n = 0; n < N; ++n) {
+    if (s->mask && s->mask[n]) {
+      for (int a = 0; a < 3; ++a) s->u[a * N + n] = 0.0;
+      s->pn[n] = 0.0;
+      continue;
+    }
+    double u[3], F[3], fd[3], S, Ft[3], nv[3];
+    double pn = forces_node(s, n, u, F, fd, &S, Ft, nv);
+    for (int a = 0; a < 3; ++a) s->u[a * N + n] = u[a];
+    s->pn[n] = pn;
+  }
+}
+
+int lbref_fields(lbref_state* s, double* phi, double* fl, double* T, double* C, double* ux,
+                 double* uy, double* uz, double* p, double* rho) {
+  if (!s) return -1;
+  evaluate_fields(s);
+  int N = s->N;
+  for (int n = 0; n < N; ++n) {
+    if (phi) phi[n] = s->phi[n];
+    if (fl) fl[n] = s->fl[n];
+    if (T) T[n] = s->T[n];
+    if (C) C[n] = s->C[n];
+    if (ux) ux[n] = s->u[0 * N + n];
+    if (uy) uy[n] = s->u[1 * N + n];
+    if (uz) uz[n] = s->u[2 * N + n];
+    if (p) p[n] = s->pn[n];
+    if (rho) rho[n] = s->rho[n];
+  }
+  return 0;
+}
+
+int lbref_totals(lbref_state* s, double out[9]) {
+  if (!s || !out) return -1;
+  int N = s->N, qs = s->Ls.q, qg = s->Lg.q;
+  divergence_all(s);
+  closure_all(s);
+  double sf = 0, sl = 0, sh = 0, vs = 0, vsl = 0, bad = 0;
+  for (int n = 0; n < N; ++n) {
+    int ob = s->mask && s->mask[n];
+    int nonfinite = 0;
+    for (int i = 0; i < qs; ++i) {
+      if (!ob) {
+        sf += s->f[i * N + n];
+        sl += s->l[i * N + n];
+      }
+      sh += s->h[i * N + n];
+      if (!isfinite(s->f[i * N + n]) || !isfinite(s->h[i * N + n]) ||
+          !isfinite(s->l[i * N + n]))
+        nonfinite = 1;
+    }
+    for (int i = 0; i < qg; ++i)
+      if (!isfinite(s->g[i * N + n])) nonfinite = 1;
+    if (!ob) {
+      vs += s->fs[n];
+      vsl += clamp01(0.5 * (1.0 + s->phi[n]));
+    }
+    bad += nonfinite;
+  }
+  out[0] = sf;
+  out[1] = sl;
+  out[2] = sh;
+  out[3] = s->mpc;
+  out[4] = vs;
+  out[5] = vsl;
+  out[6] = (double)s->step;
+  out[7] = bad;
+  out[8] = s->qacc;
+  return 0;
+}
+
+int lbref_get_pops(lbref_state* s, int which, double* dst) {
+  if (!s || !dst || which < 0 || which > 3) return -1;
+  double* src[4] = {s->f, s->g, s->h, s->l};
+  int q = which == 1 ? s->Lg.q : s->Ls.q;
+  memcpy(dst, src[which], sizeof(double) * (size_t)q * (size_t)s->N);
+  return 0;
+}
+
+int lbref_set_pops(lbref_state* s, int which, const double* srcp) {
+  if (!s || !srcp || which < 0 || which > 3) return -1;
+  double* dst[4] = {s->f, s->g, s->h, s->l};
+  int q = which == 1 ? s->Lg.q : s->Ls.q;
+  memcpy(dst[which], srcp, sizeof(double) * (size_t)q * (size_t)s->N);
+  return 0;
+}
+
+static double* state_ptr(lbref_state* s, int which) {
+  int N = s->N;
+  switch (which) {
+    case 0: return s->fs_prev;
+    case 1: return s->p_prev;
+    case 2: case 3: case 4: return s->u_prev + (which - 2) * N;
+    case 5: return s->phi_prev;
+    case 6: return s->C_prev;
+    default: return NULL;
+  }
+}
+
+int lbref_get_state(lbref_state* s, int which, double* dst) {
+  if (!s || !dst) return -1;
+  double* p = state_ptr(s, which);
+  if (!p) return -1;
+  memcpy(dst, p, sizeof(double) * (size_t)s->N);
+  return 0;
+}
+
+int lbref_set_state(lbref_state* s, int which, const double* src) {
+  if (!s || !src) return -1;
+  double* p = state_ptr(s, which);
+  if (!p) return -1;
+  memcpy(p, src, sizeof(double) * (size_t)s->N);
+  return 0;
+}
+
+int lbref_lattice(int dim, int which, int* c, double* w, int* opp) {
+  if (dim != 2 && dim != 3) return -1;
+  lat_t L;
+  lat_init(&L, dim, which == 1);
+  for (int i = 0; i < L.q; ++i) {
+    if (c)
+      for (int a = 0; a < 3; ++a) c[3 * i + a] = L.c[i][a];
+    if (w) w[i] = L.w[i];
+    if (opp) opp[i] = L.opp[i];
+  }
+  return L.q;
+}

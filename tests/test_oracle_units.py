@@ -1,0 +1,209 @@
+"""Pins of the FP64 oracle's pointwise pieces against properties the paper
+fixes: lattice moment identities (Sec. 3 equilibria and forcing terms),
+exactness of the isotropic stencils (end of Sec. 3.4) and the enthalpy map
+(Eq. Hfl)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lbref
+from paper_2511_09422_amd.workloads import base_params
+
+CS2 = 1.0 / 3.0
+
+
+@pytest.mark.parametrize("dim,which,q", [(2, 1, 9), (2, 0, 5), (3, 1, 19), (3, 0, 7)])
+def test_lattice_tables(dim, which, q):
+    c, w, opp = lbref.lattice(dim, which)
+    assert c.shape == (q, 3)
+    assert abs(w.sum() - 1.0) < 1e-15
+    # isotropy up to second order: sum w c = 0, sum w c c = cs^2 I
+    assert np.allclose((w[:, None] * c).sum(0), 0.0, atol=1e-15)
+    M2 = np.einsum("i,ia,ib->ab", w, c, c)
+    I = np.eye(3)
+    I[dim:, dim:] = 0
+    assert np.allclose(M2, CS2 * I, atol=1e-15)
+    # third moment vanishes, opposite directions are consistent
+    assert np.allclose(np.einsum("i,ia,ib,ic->abc", w, c, c, c), 0.0, atol=1e-15)
+    for i in range(q):
+        assert np.array_equal(c[opp[i]], -c[i])
+    assert np.array_equal(c[0], [0, 0, 0])
+    if which == 1:
+        # fourth-order isotropy of the flow lattices (needed by the g moments)
+        M4 = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+        iso = (np.einsum("ab,cd->abcd", I, I) + np.einsum("ac,bd->abcd", I, I)
+               + np.einsum("ad,bc->abcd", I, I)) * CS2 ** 2
+        assert np.allclose(M4, iso, atol=1e-15)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_flow_equilibrium_moments(dim):
+    rng = np.random.default_rng(1)
+    c, w, _ = lbref.lattice(dim, 1)
+    for _ in range(20):
+        p = rng.normal() * 1e-2
+        rho = rng.uniform(0.1, 1.0)
+        u = np.zeros(3)
+        u[:dim] = rng.normal(size=dim) * 0.05
+        g = lbref.feq_g(dim, p, rho, u)
+        # Sec. 3.2: sum g = 0, sum c g = rho u, sum c c g = p I + rho u u
+        assert abs(g.sum()) < 1e-15
+        assert np.allclose(c.T @ g, rho * u, atol=1e-15)
+        I = np.eye(3)
+        I[dim:, dim:] = 0
+        assert np.allclose(np.einsum("i,ia,ib->ab", g, c, c), p * I + rho * np.outer(u, u),
+                           atol=1e-15)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_flow_forcing_moments(dim):
+    rng = np.random.default_rng(2)
+    c, w, _ = lbref.lattice(dim, 1)
+    I = np.eye(3)
+    I[dim:, dim:] = 0
+    for _ in range(20):
+        S = rng.normal() * 1e-3
+        Ff, u, Ft = (np.r_[rng.normal(size=dim), np.zeros(3 - dim)] * 1e-2 for _ in range(3))
+        G = lbref.src_g(dim, S, Ff, u, Ft)
+        # sum G = S, sum c G = F + rho f, sum c c G = cs2 S I + u Ft + Ft u
+        assert abs(G.sum() - S) < 1e-15
+        assert np.allclose(c.T @ G, Ff, atol=1e-15)
+        assert np.allclose(np.einsum("i,ia,ib->ab", G, c, c),
+                           CS2 * S * I + np.outer(u, Ft) + np.outer(Ft, u), atol=1e-15)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_enthalpy_equilibrium_moments(dim):
+    rng = np.random.default_rng(3)
+    cfg = base_params(dim=dim, rhoc_ref=0.37)
+    c, w, _ = lbref.lattice(dim, 0)
+    for _ in range(20):
+        E, T, rc = rng.normal(), rng.normal(), rng.uniform(0.1, 1)
+        u = np.r_[rng.normal(size=dim) * 0.05, np.zeros(3 - dim)]
+        h = lbref.heq(cfg, E, T, rc, u)
+        # sum h_eq = rho H (Sec. 3.3), sum e h_eq = rho C_p T u
+        assert abs(h.sum() - E) < 1e-14
+        assert np.allclose(c.T @ h, rc * T * u, atol=1e-15)
+        # the diffusive (second) moment at rest is (rho C)_ref T cs2 I
+        h0 = lbref.heq(cfg, E, T, rc, np.zeros(3))
+        I = np.eye(3)
+        I[dim:, dim:] = 0
+        assert np.allclose(np.einsum("i,ia,ib->ab", h0, c, c), 0.37 * T * CS2 * I, atol=1e-14)
+
+
+def _poly_field(shape, coef, cubic=False):
+    ny, nx = shape
+    y, x = np.meshgrid(np.arange(ny, dtype=float), np.arange(nx, dtype=float), indexing="ij")
+    a, b, cc, d, e, f, g, h = coef
+    val = a + b * x + cc * y + d * x * x + e * x * y + f * y * y
+    if cubic:
+        val = val + g * x ** 3 + h * x * y * y
+    return x, y, val
+
+
+def test_stencil_exact_on_polynomials_2d():
+    cfg = base_params(nx=16, ny=12, walls=0)
+    rng = np.random.default_rng(4)
+    coef = rng.normal(size=8)
+    x, y, q2 = _poly_field((12, 16), coef)
+    g, lp = lbref.grad_lap(cfg, q2)
+    a, b, cc, d, e, f, _, _ = coef
+    inner = (slice(1, -1), slice(1, -1))   # stencil stays off the periodic seam
+    assert np.allclose(g[0][inner], (b + 2 * d * x + e * y)[inner], rtol=0, atol=1e-11)
+    assert np.allclose(g[1][inner], (cc + e * x + 2 * f * y)[inner], rtol=0, atol=1e-11)
+    assert np.allclose(lp[inner], 2 * d + 2 * f, atol=1e-10)
+    # the Laplacian is also exact on cubics
+    _, _, q3 = _poly_field((12, 16), coef, cubic=True)
+    _, lp3 = lbref.grad_lap(cfg, q3)
+    assert np.allclose(lp3[inner], (2 * d + 2 * f + 6 * coef[6] * x + 2 * coef[7] * x)[inner],
+                       atol=1e-9)
+
+
+def test_stencil_exact_on_polynomials_3d():
+    cfg = base_params(dim=3, nx=8, ny=7, nz=6, walls=0)
+    rng = np.random.default_rng(5)
+    A = rng.normal(size=(3, 3))
+    A = A + A.T
+    b = rng.normal(size=3)
+    z, y, x = np.meshgrid(np.arange(6.), np.arange(7.), np.arange(8.), indexing="ij")
+    X = np.stack([x, y, z])
+    q = 0.5 * np.einsum("aijk,ab,bijk->ijk", X, A, X) + np.einsum("a,aijk->ijk", b, X)
+    g, lp = lbref.grad_lap(cfg, q)
+    inner = (slice(1, -1),) * 3
+    exact_g = np.einsum("ab,bijk->aijk", A, X) + b[:, None, None, None]
+    for a_ in range(3):
+        assert np.allclose(g[a_][inner], exact_g[a_][inner], atol=1e-10)
+    assert np.allclose(lp[inner], np.trace(A), atol=1e-10)
+
+
+def test_stencil_wall_ghosts():
+    # mirror ghosts are exact for fields even about the wall plane y = -1/2,
+    # the Dirichlet temperature ghost is exact for a field linear in y that
+    # takes T_w on the wall.
+    cfg = base_params(nx=8, ny=10, walls=1, t_lo_dirichlet=1, t_hi_dirichlet=1, T_lo=-0.7,
+                      T_hi=0.3)
+    y, x = np.meshgrid(np.arange(10.), np.arange(8.), indexing="ij")
+    # a field with zero normal derivative at both walls: cos(pi (y+1/2)/10)
+    fld = np.cos(np.pi * (y + 0.5) / 10.0)
+    g, lp = lbref.grad_lap(cfg, fld, kind=0)
+    # compare against the same stencil applied to the exact even extension
+    ext = np.cos(np.pi * (np.arange(-1, 11) + 0.5) / 10.0)
+    gy_ext = (ext[2:] - ext[:-2]) * (1 / 9 + 2 / 36) / CS2
+    assert np.allclose(g[1][:, 0], gy_ext, atol=1e-14)
+    # Dirichlet: T linear between T_lo at y=-1/2 and T_hi at y=9.5 -> exact gradient
+    slope = (0.3 - (-0.7)) / 10.0
+    T = -0.7 + slope * (y + 0.5)
+    gT, lT = lbref.grad_lap(cfg, T, kind=1)
+    assert np.allclose(gT[1], slope, atol=1e-13)
+    assert np.allclose(lT, 0.0, atol=1e-12)
+
+
+def test_enthalpy_map_reduces_to_eq_hfl():
+    """At psi = 1 the map is Eq. (Hfl) of the paper, including its density
+    difference between the solidus and liquidus branches."""
+    cfg = base_params(rho_s=0.8, rho_l=1.0, cp_s=0.7, cp_l=1.3, latent=2.0, T_sol=-0.2,
+                      T_liq=0.3)
+    rHs = 0.8 * 0.7 * (-0.2)               # rho_s H_s at the solidus (f_l = 0)
+    rHl = 1.0 * (1.3 * 0.3 + 2.0)          # rho_l H_l at the liquidus (f_l = 1)
+    for E in np.linspace(-2, 4, 301):
+        T, fl, fs = lbref.enthalpy_map(cfg, E, 1.0)
+        if E < rHs:
+            Tx, flx = E / (0.8 * 0.7), 0.0
+        elif E > rHl:
+            Tx, flx = 0.3 + (E - rHl) / (1.0 * 1.3), 1.0
+        else:
+            flx = (E - rHs) / (rHl - rHs)
+            Tx = -0.2 + flx * 0.5
+        assert abs(T - Tx) < 1e-14 and abs(fl - flx) < 1e-15 and abs(fs - (1 - flx)) < 1e-15
+
+
+def test_enthalpy_map_continuity_and_gas():
+    cfg = base_params(rho_s=0.9, latent=1.5, T_sol=-0.1, T_liq=0.05)
+    for psi in (0.0, 1e-9, 0.2, 0.5, 0.93, 1.0):
+        Es = (psi * 0.9 + (1 - psi) * 0.1) * (-0.1)
+        El = (psi * 1.0 + (1 - psi) * 0.1) * 0.05 + psi * 1.5
+        for Ek in (Es, El):
+            lo = lbref.enthalpy_map(cfg, Ek - 1e-12, psi)
+            hi = lbref.enthalpy_map(cfg, Ek + 1e-12, psi)
+            assert abs(lo[0] - hi[0]) < 1e-9        # T continuous
+            assert abs(lo[2] - hi[2]) < 1e-9        # f_s continuous
+        # T is non-decreasing in E, f_s is non-increasing, f_s in [0, psi]
+        Es_ = np.linspace(-3, 3, 601)
+        out = np.array([lbref.enthalpy_map(cfg, E, psi) for E in Es_])
+        assert np.all(np.diff(out[:, 0]) >= -1e-15)
+        assert np.all(np.diff(out[:, 2]) <= 1e-15)
+        assert np.all((out[:, 2] >= 0) & (out[:, 2] <= psi + 1e-15))
+    # pure gas (psi = 0) never holds solid
+    for E in np.linspace(-3, 3, 61):
+        assert lbref.enthalpy_map(cfg, E, 0.0)[2] == 0.0
+
+
+def test_alpha_normalises_delta():
+    """alpha = 3 sqrt(2) eps / 4 makes the interface delta alpha |grad phi|^2
+    integrate to one across the equilibrium tanh profile (Sec. 2)."""
+    eps = math.sqrt(2.0)
+    x = np.linspace(-60, 60, 200001)
+    dphi = (1.0 / (math.sqrt(2) * eps)) / np.cosh(x / (math.sqrt(2) * eps)) ** 2
+    integral = np.trapezoid(3 * math.sqrt(2) * eps / 4 * dphi ** 2, x)
+    assert abs(integral - 1.0) < 1e-8
