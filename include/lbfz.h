@@ -1,0 +1,163 @@
+/*
+ * lbfz.h -- C ABI of the MI355X (gfx950) coupled lattice Boltzmann freezing
+ * step: one time step of the diffuse-interface scheme of Huang, Chai, Liu,
+ * Huang, "Diffuse-interface modeling and simulation of the freezing of binary
+ * fluids with the Marangoni effect" (arXiv 2511.09422), Sec. 3:
+ *   - conservative Allen-Cahn phase field f (BGK, D2Q5 / D3Q7), Sec. 3.1;
+ *   - pressure-based flow g with the phase-change mass source (BGK,
+ *     D2Q9 / D3Q19), capillary + Marangoni force (Eq. Fs) and solid drag,
+ *     Sec. 3.2;
+ *   - total enthalpy h (TRT, D2Q5 / D3Q7) with the enthalpy -> (T, f_l) map of
+ *     Eq. (Hfl), Sec. 3.3;
+ *   - constrained solute l (BGK, D2Q5 / D3Q7) with the pseudo-potential
+ *     rejection flux, Sec. 3.4;
+ *   - isotropic gradient / Laplacian stencils, end of Sec. 3.4;
+ *   - half-way bounce-back and anti-bounce-back walls, Sec. 4.5.
+ *
+ * Conventions (all calls):
+ *   - Lattice units, dx = dt = 1, cs^2 = 1/3.
+ *   - Scalar fields are C-order [nz][ny][nx] (2D: nz = 1).  With walls != 0
+ *     the last axis (y in 2D, z in 3D) is bounded by walls at -1/2 and n-1/2
+ *     (cell-centred nodes); every other axis is periodic.
+ *   - Device memory: the library never allocates.  The caller provides one
+ *     device workspace of at least lbfz_workspace_bytes() bytes (256-byte
+ *     aligned) and a HIP stream (passed as void*, NULL = default stream); the
+ *     handle keeps both until lbfz_destroy.  The handle itself is host memory
+ *     owned by the library.
+ *   - All device work is enqueued on that stream.  lbfz_step does not
+ *     synchronise; lbfz_fields (to host) and lbfz_totals synchronise it.
+ *   - One handle per stream; a handle is not thread-safe.
+ *   - Every int-returning call returns LBFZ_OK (0) or a negative LBFZ_E* code;
+ *     nothing aborts and no C++ exception crosses the ABI.
+ */
+#ifndef LBFZ_H
+#define LBFZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBFZ_OK = 0,
+  LBFZ_EINVAL = -1,     /* bad argument or parameter (tau <= 1/2, sizes, ...) */
+  LBFZ_ENOMEM = -2,     /* workspace too small or misaligned                 */
+  LBFZ_EHIP = -3,       /* a HIP runtime call failed                         */
+  LBFZ_ENONFINITE = -4, /* non-finite input field                            */
+  LBFZ_EUNSUPPORTED = -5
+};
+
+/* Population storage of the step. */
+enum { LBFZ_STORE_F32 = 0, LBFZ_STORE_F16 = 1, LBFZ_STORE_BF16 = 2 };
+
+/* Field selector bits for lbfz_fields. */
+enum {
+  LBFZ_PHI = 1u << 0, /* order parameter phi (Sec. 3.1 moment)              */
+  LBFZ_FL = 1u << 1,  /* liquid fraction reported as 1 - f_s                */
+  LBFZ_T = 1u << 2,   /* temperature (Eq. Hfl)                              */
+  LBFZ_C = 1u << 3,   /* solute concentration (Sec. 3.4 moment)             */
+  LBFZ_UX = 1u << 4,  /* velocity (Sec. 3.2, corrected by the solid drag)   */
+  LBFZ_UY = 1u << 5,
+  LBFZ_UZ = 1u << 6,
+  LBFZ_P = 1u << 7,   /* pressure (Sec. 3.2)                                */
+  LBFZ_RHO = 1u << 8  /* interpolated density (end of Sec. 2)               */
+};
+#define LBFZ_NFIELDS 9
+
+/* Physical and numerical parameters (lattice units).  Sec. references are
+ * to the paper. */
+typedef struct lbfz_params {
+  int32_t dim, nx, ny, nz;       /* dim 2 or 3; nz = 1 in 2D                   */
+  int32_t walls;                 /* 0 all periodic; 1 walls on the last axis   */
+  int32_t t_lo_dirichlet;        /* low wall: 1 Dirichlet T (anti-bounce-back), 0 adiabatic */
+  int32_t t_hi_dirichlet;        /* high wall: same                            */
+  int32_t surface_tension_mode;  /* 0: (1 - f_s) F_s (Sec. 4.5), 1: F_s        */
+  int32_t storage;               /* LBFZ_STORE_*                               */
+  int32_t contact_angle_deg;     /* wetting: only 90 is supported              */
+  double rho_l, rho_g, rho_s;    /* end-member densities (end of Sec. 2)       */
+  double nu;                     /* kinematic viscosity, tau_g = nu/cs^2 + 1/2 */
+  double tau_phi;                /* phase field: mobility M = cs^2 (tau - 1/2) */
+  double tau_h;                  /* enthalpy antisymmetric tau; lambda = (rho C)_ref cs^2 (tau - 1/2) */
+  double tau_c;                  /* solute: D_l = cs^2 (tau - 1/2)             */
+  double eps;                    /* interface thickness parameter (Eq. 3)      */
+  double sigma0, sigma_T, sigma_c, T_ref, c_ref; /* linear equation of state (Sec. 2) */
+  double cp_l, cp_s, cp_g;       /* specific heats                             */
+  double rhoc_ref;               /* (rho C_p)_ref of the enthalpy equilibrium  */
+  double latent, T_sol, T_liq;   /* latent heat, solidus, liquidus (Eq. Hfl)   */
+  double k_p, Ds_over_Dl;        /* partition coefficient, D_s / D_l (Eq. c)   */
+  double T_lo, T_hi, T_lo_amp;   /* wall T; low wall T_lo + T_lo_amp cos(2 pi x / nx) */
+  double body_force[3];          /* F_b                                        */
+} lbfz_params;
+
+typedef struct lbfz_totals_t {
+  double sum_f;     /* sum over nodes and directions of f (phase field)        */
+  double sum_l;     /* sum of l (solute)                                       */
+  double sum_h;     /* sum of h (enthalpy)                                     */
+  double mpc;       /* accumulated sum over steps and nodes of phi div u: the
+                       phase-field source, so sum_f - sum_f(0) - mpc = 0      */
+  double vol_solid; /* sum of f_s at the current time level                    */
+  double vol_sl;    /* sum of clamp((1 + phi) / 2, 0, 1)                       */
+  int64_t step;     /* steps taken                                             */
+  int64_t nonfinite;/* nodes with a non-finite population or field             */
+} lbfz_totals_t;
+
+typedef struct lbfz_handle lbfz_handle;
+
+/* Bytes of device workspace the configuration needs (>= 256-byte aligned
+ * base required).  Errors: LBFZ_EINVAL for invalid parameters. */
+int lbfz_workspace_bytes(const lbfz_params* p, size_t* bytes);
+
+/* Create a solver state from initial host fields (FP64, C-order, N values
+ * each): phi, T, C, and an optional uint8 obstacle mask (3D only, NULL for
+ * none; nonzero = obstacle).  u = 0, p = 0, f_l = 1 and every population at
+ * its equilibrium (Sec. 3).  d_workspace / ws_bytes: caller-owned device
+ * memory; stream: a hipStream_t or NULL.  Synchronises the stream once.
+ * Errors: LBFZ_EINVAL (parameters: tau <= 1/2, eps <= 0, dims, contact angle
+ * != 90, mask in 2D), LBFZ_ENOMEM (workspace), LBFZ_ENONFINITE (inputs),
+ * LBFZ_EHIP. */
+int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const double* C,
+                const uint8_t* mask, void* d_workspace, size_t ws_bytes, void* stream,
+                lbfz_handle** out);
+
+/* Advance nsteps >= 0 time steps (Sec. 3: closure, stencils, forces, the four
+ * collisions, streaming).  Asynchronous on the handle's stream. */
+int lbfz_step(lbfz_handle* h, int64_t nsteps);
+
+/* Macroscopic fields at the current time level, FP32, N values each, for every
+ * bit set in field_mask (bit k -> dst[k]; dst entries of unset bits are
+ * ignored).  dst_is_device != 0: dst are device pointers (asynchronous);
+ * else host pointers (synchronises). */
+int lbfz_fields(lbfz_handle* h, uint32_t field_mask, float* const* dst, int dst_is_device);
+
+/* Conservation totals at the current time level (FP64 reductions in a fixed
+ * order, so repeated calls agree bit for bit).  Synchronises the stream. */
+int lbfz_totals(lbfz_handle* h, lbfz_totals_t* out);
+
+/* Raw solver state, for checkpoint / restart and for step-by-step checks:
+ * FP32 planes of N values, in this order: the populations of the current
+ * time level (f: Q_s planes, g: Q_g, h: Q_s, l: Q_s; D2Q5/D2Q9 order
+ * (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1); D3Q7/D3Q19 order
+ * rest, +x, -x, +y, -y, +z, -z, then the 12 edge links (+-x+-y, +-x+-z,
+ * +-y+-z)), then the previous time level's f_s, p, u (dim planes), phi, C.
+ * 2D: 30 planes, 3D: 47 planes.  lbfz_state_floats gives the count; get and
+ * set copy to / from host memory and synchronise the stream.  The phase-field
+ * source accumulator and the step counter are not part of the state. */
+int lbfz_state_floats(lbfz_handle* h, size_t* nfloats);
+int lbfz_get_state(lbfz_handle* h, float* host_dst);
+int lbfz_set_state(lbfz_handle* h, const float* host_src);
+
+/* Blocks until the handle's stream is idle. */
+int lbfz_sync(lbfz_handle* h);
+
+/* Release the handle (not the workspace or the stream, which the caller owns). */
+void lbfz_destroy(lbfz_handle* h);
+
+/* Static text for an error code. */
+const char* lbfz_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBFZ_H */

@@ -1,0 +1,406 @@
+// lbfz_api.hip -- the C ABI declared in include/lbfz.h: parameter checks,
+// workspace layout, launches on the caller's stream, FP64 fixed-order
+// reductions for the conservation totals.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbfz.h"
+#include "lbfz_common.hpp"
+#include "lbfz_kernels.hpp"
+
+using namespace lbfz;
+
+struct lbfz_handle {
+  lbfz_params prm;
+  KParams kp;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  float* pop[2];
+  float* p[2];
+  float* u[2];
+  float *fs, *phiP, *CP;
+  double* mpc_part;
+  double* tot_part;
+  double* red;
+  float* stage;
+  uint8_t* mask;
+  int cur;
+  int64_t step;
+  int ntiles;
+  int npop;
+};
+
+namespace {
+
+struct Layout {
+  size_t pop, p, u, scal, mpc, tot, red, stage, mask, total;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool valid_params(const lbfz_params* p) {
+  if (!p) return false;
+  if (p->dim != 2) return false;  // 3D is declared but reported unsupported below
+  if (p->nx < 2 || p->ny < 2 || p->nz != 1) return false;
+  if ((long long)p->nx * p->ny > (1ll << 26)) return false;
+  if (!(p->tau_phi > 0.5 && p->tau_h > 0.5 && p->tau_c > 0.5 && p->nu > 0.0)) return false;
+  if (!(p->eps > 0.0 && p->rhoc_ref > 0.0)) return false;
+  if (!(p->rho_l > 0 && p->rho_g > 0 && p->rho_s > 0)) return false;
+  if (!(p->cp_l > 0 && p->cp_s > 0 && p->cp_g > 0)) return false;
+  if (p->contact_angle_deg != 90) return false;
+  if (p->walls != 0 && p->walls != 1) return false;
+  if (p->surface_tension_mode != 0 && p->surface_tension_mode != 1) return false;
+  if (!(p->k_p > 0.0 && p->Ds_over_Dl >= 0.0)) return false;
+  return true;
+}
+
+int check_support(const lbfz_params* p) {
+  if (p && p->dim == 3) return LBFZ_EUNSUPPORTED;
+  if (p && p->storage != LBFZ_STORE_F32) return LBFZ_EUNSUPPORTED;
+  return LBFZ_OK;
+}
+
+Layout layout(const lbfz_params* p, int ntiles, int npop) {
+  const size_t N = (size_t)p->nx * p->ny * p->nz;
+  Layout L;
+  L.pop = align256(N * npop * sizeof(float));
+  L.p = align256(N * sizeof(float));
+  L.u = align256(N * p->dim * sizeof(float));
+  L.scal = align256(N * sizeof(float));
+  L.mpc = align256((size_t)ntiles * sizeof(double));
+  L.tot = align256((size_t)ntiles * 8 * sizeof(double));
+  L.red = 256;
+  L.stage = align256(std::max(N * LBFZ_NFIELDS * sizeof(float), N * 3 * sizeof(double)));
+  L.mask = p->dim == 3 ? align256(N) : 0;
+  L.total = 2 * L.pop + 2 * L.p + 2 * L.u + 3 * L.scal + L.mpc + L.tot + L.red + L.stage + L.mask;
+  return L;
+}
+
+KParams make_kparams(const lbfz_params* p, int nbx, int nby) {
+  KParams k;
+  std::memset(&k, 0, sizeof(k));
+  k.nx = p->nx;
+  k.ny = p->ny;
+  k.nz = p->nz;
+  k.N = p->nx * p->ny * p->nz;
+  k.walls = p->walls;
+  k.tlo_dir = p->t_lo_dirichlet;
+  k.thi_dir = p->t_hi_dirichlet;
+  k.st_mode = p->surface_tension_mode;
+  k.nblk_x = nbx;
+  k.nblk_y = nby;
+  k.nblk_z = 1;
+  k.nblk = nbx * nby;
+  k.rho_l = (float)p->rho_l;
+  k.rho_g = (float)p->rho_g;
+  k.rho_s = (float)p->rho_s;
+  k.cp_l = (float)p->cp_l;
+  k.cp_s = (float)p->cp_s;
+  k.cp_g = (float)p->cp_g;
+  k.rc_l = (float)(p->rho_l * p->cp_l);
+  k.rc_s = (float)(p->rho_s * p->cp_s);
+  k.rc_g = (float)(p->rho_g * p->cp_g);
+  k.rhoc_ref = (float)p->rhoc_ref;
+  k.rho_l_latent = (float)(p->rho_l * p->latent);
+  k.T_sol = (float)p->T_sol;
+  k.T_liq = (float)p->T_liq;
+  k.ratio = (float)(1.0 - p->rho_s / p->rho_l);
+  const double cs2 = 1.0 / 3.0;
+  const double tau_g = p->nu / cs2 + 0.5;
+  k.tau_g = (float)tau_g;
+  k.itau_g = (float)(1.0 / tau_g);
+  k.wg = (float)(1.0 - 0.5 / tau_g);
+  k.itau_f = (float)(1.0 / p->tau_phi);
+  k.wf = (float)(1.0 - 0.5 / p->tau_phi);
+  const double tau_a = p->tau_h, tau_s = tau_a / (2.0 * tau_a - 1.0);  // 1/ts + 1/ta = 2
+  k.itau_a = (float)(1.0 / tau_a);
+  k.itau_s = (float)(1.0 / tau_s);
+  k.ws = (float)(1.0 - 0.5 / tau_s);
+  const double Dl = cs2 * (p->tau_c - 0.5);
+  k.Dl = (float)Dl;
+  k.Ds = (float)(p->Ds_over_Dl * Dl);
+  k.k_p = (float)p->k_p;
+  k.alpha = (float)(3.0 * std::sqrt(2.0) * p->eps / 4.0);
+  k.ieps2 = (float)(1.0 / (p->eps * p->eps));
+  k.isq = (float)(1.0 / (std::sqrt(2.0) * p->eps));
+  k.sigma0 = (float)p->sigma0;
+  k.sigma_T = (float)p->sigma_T;
+  k.sigma_c = (float)p->sigma_c;
+  k.T_ref = (float)p->T_ref;
+  k.c_ref = (float)p->c_ref;
+  k.bfx = (float)p->body_force[0];
+  k.bfy = (float)p->body_force[1];
+  k.bfz = (float)p->body_force[2];
+  k.T_lo = (float)p->T_lo;
+  k.T_hi = (float)p->T_hi;
+  k.T_lo_amp = (float)p->T_lo_amp;
+  k.kwall = (float)(2.0 * M_PI / p->nx);
+  return k;
+}
+
+__global__ void k_zero_f64(double* a, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    a[i] = 0.0;
+}
+
+// Fixed-order FP64 reduction of the per-tile totals (6 values) and the
+// per-tile phase-field source accumulators into out[0..6].
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ tot,
+                                                const double* __restrict__ mpc, int ntiles,
+                                                double* __restrict__ out) {
+  __shared__ double sm[256];
+  for (int k = 0; k < 7; ++k) {
+    double s = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += 256) s += k < 6 ? tot[(long)t * 8 + k] : mpc[t];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sm[0];
+    __syncthreads();
+  }
+}
+
+#define HIPCHK(x)                        \
+  do {                                   \
+    if ((x) != hipSuccess) return LBFZ_EHIP; \
+  } while (0)
+
+StepArgs base_args(lbfz_handle* h) {
+  StepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const int c = h->cur;
+  a.src = h->pop[c];
+  a.dst = h->pop[1 - c];
+  a.p_old = h->p[c];
+  a.p_new = h->p[1 - c];
+  a.u_old = h->u[c];
+  a.u_new = h->u[1 - c];
+  a.fs = h->fs;
+  a.phiP = h->phiP;
+  a.CP = h->CP;
+  a.mask = h->mask;
+  a.mpc_part = h->mpc_part;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbfz_workspace_bytes(const lbfz_params* p, size_t* bytes) {
+  if (!bytes || !valid_params(p)) return p && p->dim == 3 ? LBFZ_EUNSUPPORTED : LBFZ_EINVAL;
+  int nbx, nby;
+  const int nt = tiles2d(p->nx, p->ny, &nbx, &nby);
+  *bytes = layout(p, nt, 24).total;
+  return LBFZ_OK;
+}
+
+int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const double* C,
+                const uint8_t* mask, void* d_workspace, size_t ws_bytes, void* stream,
+                lbfz_handle** out) {
+  if (!out) return LBFZ_EINVAL;
+  *out = nullptr;
+  const int sup = check_support(p);
+  if (sup != LBFZ_OK) return sup;
+  if (!valid_params(p) || !phi || !T || !C || !d_workspace) return LBFZ_EINVAL;
+  if (mask && p->dim == 2) return LBFZ_EINVAL;
+  if (((uintptr_t)d_workspace & 255) != 0) return LBFZ_ENOMEM;
+  const size_t N = (size_t)p->nx * p->ny * p->nz;
+  for (size_t n = 0; n < N; ++n)
+    if (!std::isfinite(phi[n]) || !std::isfinite(T[n]) || !std::isfinite(C[n]))
+      return LBFZ_ENONFINITE;
+  int nbx, nby;
+  const int ntiles = tiles2d(p->nx, p->ny, &nbx, &nby);
+  const int npop = 24;
+  const Layout L = layout(p, ntiles, npop);
+  if (ws_bytes < L.total) return LBFZ_ENOMEM;
+
+  lbfz_handle* h = new (std::nothrow) lbfz_handle;
+  if (!h) return LBFZ_ENOMEM;
+  std::memset(h, 0, sizeof(*h));
+  h->prm = *p;
+  h->kp = make_kparams(p, nbx, nby);
+  h->stream = (hipStream_t)stream;
+  h->ws = (char*)d_workspace;
+  h->ws_bytes = ws_bytes;
+  h->ntiles = ntiles;
+  h->npop = npop;
+  char* q = h->ws;
+  h->pop[0] = (float*)q; q += L.pop;
+  h->pop[1] = (float*)q; q += L.pop;
+  h->p[0] = (float*)q; q += L.p;
+  h->p[1] = (float*)q; q += L.p;
+  h->u[0] = (float*)q; q += L.u;
+  h->u[1] = (float*)q; q += L.u;
+  h->fs = (float*)q; q += L.scal;
+  h->phiP = (float*)q; q += L.scal;
+  h->CP = (float*)q; q += L.scal;
+  h->mpc_part = (double*)q; q += L.mpc;
+  h->tot_part = (double*)q; q += L.tot;
+  h->red = (double*)q; q += L.red;
+  h->stage = (float*)q; q += L.stage;
+  h->mask = nullptr;
+  h->cur = 0;
+  h->step = 0;
+
+  double* st = (double*)h->stage;
+  int rc = LBFZ_OK;
+  do {
+    if (hipMemcpyAsync(st, phi, N * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(st + N, T, N * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(st + 2 * N, C, N * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess) {
+      rc = LBFZ_EHIP;
+      break;
+    }
+    StateArgs S{h->p[0], h->p[1], h->u[0], h->u[1], h->fs, h->phiP, h->CP};
+    if (launch_init2d(h->kp, st, st + N, st + 2 * N, h->pop[0], S, h->stream) != hipSuccess) {
+      rc = LBFZ_EHIP;
+      break;
+    }
+    hipLaunchKernelGGL(k_zero_f64, dim3(64), dim3(256), 0, h->stream, h->mpc_part, ntiles);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
+      rc = LBFZ_EHIP;
+  } while (0);
+  if (rc != LBFZ_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return LBFZ_OK;
+}
+
+int lbfz_step(lbfz_handle* h, int64_t nsteps) {
+  if (!h || nsteps < 0) return LBFZ_EINVAL;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    StepArgs a = base_args(h);
+    HIPCHK(launch_step2d(h->kp, a, false, h->stream));
+    h->cur ^= 1;
+    h->step += 1;
+  }
+  return LBFZ_OK;
+}
+
+int lbfz_fields(lbfz_handle* h, uint32_t field_mask, float* const* dst, int dst_is_device) {
+  if (!h || !dst) return LBFZ_EINVAL;
+  const size_t N = (size_t)h->kp.N;
+  StepArgs a = base_args(h);
+  for (int k = 0; k < LBFZ_NFIELDS; ++k) {
+    a.out[k] = nullptr;
+    if (field_mask & (1u << k)) {
+      if (!dst[k]) return LBFZ_EINVAL;
+      a.out[k] = dst_is_device ? dst[k] : h->stage + (size_t)k * N;
+    }
+  }
+  HIPCHK(launch_step2d(h->kp, a, true, h->stream));
+  if (!dst_is_device) {
+    for (int k = 0; k < LBFZ_NFIELDS; ++k)
+      if (field_mask & (1u << k))
+        HIPCHK(hipMemcpyAsync(dst[k], h->stage + (size_t)k * N, N * sizeof(float),
+                              hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  return LBFZ_OK;
+}
+
+int lbfz_totals(lbfz_handle* h, lbfz_totals_t* out) {
+  if (!h || !out) return LBFZ_EINVAL;
+  StepArgs a = base_args(h);
+  for (int k = 0; k < LBFZ_NFIELDS; ++k) a.out[k] = nullptr;
+  a.tot_part = h->tot_part;
+  HIPCHK(launch_step2d(h->kp, a, true, h->stream));
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, h->stream, h->tot_part, h->mpc_part,
+                     h->ntiles, h->red);
+  HIPCHK(hipGetLastError());
+  double r[8];
+  HIPCHK(hipMemcpyAsync(r, h->red, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  out->sum_f = r[0];
+  out->sum_l = r[1];
+  out->sum_h = r[2];
+  out->vol_solid = r[3];
+  out->vol_sl = r[4];
+  out->nonfinite = (int64_t)std::llround(r[5]);
+  out->mpc = r[6];
+  out->step = h->step;
+  return LBFZ_OK;
+}
+
+namespace {
+// Device planes of the exported state, in the documented order.
+int state_planes(lbfz_handle* h, std::vector<float*>& planes) {
+  const size_t N = (size_t)h->kp.N;
+  planes.clear();
+  float* pop = h->pop[h->cur];
+  for (int q = 0; q < h->npop; ++q) planes.push_back(pop + q * N);
+  planes.push_back(h->fs);
+  planes.push_back(h->p[h->cur]);
+  for (int a = 0; a < h->prm.dim; ++a) planes.push_back(h->u[h->cur] + a * N);
+  planes.push_back(h->phiP);
+  planes.push_back(h->CP);
+  return (int)planes.size();
+}
+}  // namespace
+
+int lbfz_state_floats(lbfz_handle* h, size_t* nfloats) {
+  if (!h || !nfloats) return LBFZ_EINVAL;
+  std::vector<float*> planes;
+  *nfloats = (size_t)state_planes(h, planes) * (size_t)h->kp.N;
+  return LBFZ_OK;
+}
+
+int lbfz_get_state(lbfz_handle* h, float* host_dst) {
+  if (!h || !host_dst) return LBFZ_EINVAL;
+  const size_t N = (size_t)h->kp.N;
+  std::vector<float*> planes;
+  const int np = state_planes(h, planes);
+  for (int k = 0; k < np; ++k)
+    HIPCHK(hipMemcpyAsync(host_dst + k * N, planes[k], N * sizeof(float), hipMemcpyDeviceToHost,
+                          h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBFZ_OK;
+}
+
+int lbfz_set_state(lbfz_handle* h, const float* host_src) {
+  if (!h || !host_src) return LBFZ_EINVAL;
+  const size_t N = (size_t)h->kp.N;
+  std::vector<float*> planes;
+  const int np = state_planes(h, planes);
+  for (int k = 0; k < np; ++k)
+    HIPCHK(hipMemcpyAsync(planes[k], host_src + k * N, N * sizeof(float), hipMemcpyHostToDevice,
+                          h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBFZ_OK;
+}
+
+int lbfz_sync(lbfz_handle* h) {
+  if (!h) return LBFZ_EINVAL;
+  return hipStreamSynchronize(h->stream) == hipSuccess ? LBFZ_OK : LBFZ_EHIP;
+}
+
+void lbfz_destroy(lbfz_handle* h) { delete h; }
+
+const char* lbfz_strerror(int code) {
+  switch (code) {
+    case LBFZ_OK: return "ok";
+    case LBFZ_EINVAL: return "invalid argument or parameter";
+    case LBFZ_ENOMEM: return "device workspace too small or misaligned";
+    case LBFZ_EHIP: return "HIP runtime error";
+    case LBFZ_ENONFINITE: return "non-finite input field";
+    case LBFZ_EUNSUPPORTED: return "configuration not supported by this build";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// lbfz_common.hpp -- device-side parameters and pointwise physics shared by
+// the 2D and 3D step kernels of the coupled LB freezing scheme
+// (arXiv 2511.09422, Sec. 2-3).  FP32 arithmetic; FP64 only in reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbfz {
+
+constexpr float kCs2 = 1.0f / 3.0f;
+constexpr float kInvCs2 = 3.0f;
+
+// Kernel parameter block: every constant the step needs, derived once on the
+// host from lbfz_params and passed by value.
+struct KParams {
+  int nx, ny, nz, N;
+  int walls, tlo_dir, thi_dir, st_mode;
+  int nblk_x, nblk_y, nblk_z, nblk;  // tile grid (logical)
+  // property end members (end of Sec. 2)
+  float rho_l, rho_g, rho_s, cp_l, cp_s, cp_g;
+  float rc_l, rc_s, rc_g;  // rho * c_p of each phase
+  float rhoc_ref, rho_l_latent, T_sol, T_liq;
+  float ratio;  // 1 - rho_s / rho_l (Eq. NS1)
+  // relaxation (Sec. 3.1-3.4)
+  float tau_g, itau_g, wg;  // wg = 1 - 1/(2 tau)
+  float itau_f, wf;
+  float itau_a, itau_s, ws;  // enthalpy TRT: antisymmetric / symmetric
+  float Dl, Ds, k_p;
+  // interface and forces (Sec. 2, Eq. Fs)
+  float alpha, ieps2, isq;  // isq = 1/(sqrt(2) eps)
+  float sigma0, sigma_T, sigma_c, T_ref, c_ref;
+  float bfx, bfy, bfz;
+  // walls
+  float T_lo, T_hi, T_lo_amp, kwall;  // kwall = 2 pi / nx
+};
+
+__device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
+
+// Property interpolation, end of Sec. 2.
+__device__ __forceinline__ float interp(float phi, float fs, float zl, float zg, float zs) {
+  return 0.5f * phi * (zl - zg) + fs * (zs - zl) + 0.5f * (zl + zg);
+}
+
+// Enthalpy -> (T, f_s) map of Eq. (Hfl) with the heat capacities and the
+// latent heat weighted by the phase-change-material fraction psi; f_s =
+// psi (1 - f_l).  At psi = 1 this is Eq. (Hfl).
+__device__ __forceinline__ void enthalpy_map(const KParams& P, float E, float psi, float& T,
+                                             float& fs) {
+  const float rcs = psi * P.rc_s + (1.0f - psi) * P.rc_g;
+  const float rcl = psi * P.rc_l + (1.0f - psi) * P.rc_g;
+  const float Es = rcs * P.T_sol;
+  const float El = rcl * P.T_liq + psi * P.rho_l_latent;
+  float fl;
+  if (E < Es) {
+    fl = 0.0f;
+    T = E / rcs;
+  } else if (E > El) {
+    fl = 1.0f;
+    T = P.T_liq + (E - El) / rcl;
+  } else {
+    const float d = El - Es;
+    fl = (d <= 1e-12f * fmaxf(1.0f, fabsf(E))) ? 1.0f : (E - Es) / d;
+    T = P.T_sol + fl * (P.T_liq - P.T_sol);
+  }
+  fs = psi * (1.0f - fl);
+}
+
+// Pointwise closure of one node from its raw moments (Sec. 3.1, 3.3, Eq. NS1):
+// phi from phi0 and div u, then one predictor and one corrector of the
+// implicit enthalpy moment.  Outputs phi, T, f_s and the enthalpy source Q.
+struct Closure {
+  float phi, T, fs, E, Q;
+};
+
+__device__ __forceinline__ Closure closure(const KParams& P, float phi0, float E0, float D) {
+  Closure c;
+  const float psi = clamp01(0.5f * (1.0f + phi0));
+  c.phi = phi0 / (1.0f - 0.5f * D);
+  float T0, fs0;
+  enthalpy_map(P, E0, psi, T0, fs0);
+  const float rc0 = interp(c.phi, fs0, P.rho_l, P.rho_g, P.rho_s) *
+                    interp(c.phi, fs0, P.cp_l, P.cp_g, P.cp_s);
+  c.Q = rc0 * T0 * D;
+  c.E = E0 + 0.5f * c.Q;
+  enthalpy_map(P, c.E, psi, c.T, c.fs);
+  return c;
+}
+
+// Wave64 + block reduction of doubles into lds scratch (blockDim.x threads).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sred) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sred[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += sred[w];
+  }
+  return s;  // valid on thread 0
+}
+
+// Map a hardware block index to a logical tile index so that each of the 8
+// XCDs (blocks are dealt round-robin to them) works on one contiguous band of
+// tiles and the halo rows it re-reads stay in its own L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblk) {
+  const int per = nblk >> 3;
+  if (per == 0 || (nblk & 7)) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
+}  // namespace lbfz

@@ -1,0 +1,241 @@
+"""Thin ctypes binding of the C ABI in ``include/lbfz.h`` (``liblbfz.so``).
+
+Argument marshalling only: every step of the scheme runs in the HIP kernels
+of the shared library.  PyTorch provides the device workspace and the stream.
+The functions keep the C names (``lbfz_create``, ``lbfz_step``,
+``lbfz_fields``, ``lbfz_totals``, ...); :class:`Solver` bundles them.
+
+The library must have been built (``python -m paper_2511_09422_amd.build``);
+there is no fallback of any kind: a missing or unloadable library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbfz.so")
+
+LBFZ_OK, LBFZ_EINVAL, LBFZ_ENOMEM, LBFZ_EHIP, LBFZ_ENONFINITE, LBFZ_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+FIELDS = ("phi", "fl", "T", "C", "ux", "uy", "uz", "p", "rho")
+
+_INTS = ("dim", "nx", "ny", "nz", "walls", "t_lo_dirichlet", "t_hi_dirichlet",
+         "surface_tension_mode", "storage", "contact_angle_deg")
+_DOUBLES = ("rho_l", "rho_g", "rho_s", "nu", "tau_phi", "tau_h", "tau_c", "eps", "sigma0",
+            "sigma_T", "sigma_c", "T_ref", "c_ref", "cp_l", "cp_s", "cp_g", "rhoc_ref", "latent",
+            "T_sol", "T_liq", "k_p", "Ds_over_Dl", "T_lo", "T_hi", "T_lo_amp")
+
+
+class lbfz_params(ctypes.Structure):
+    _fields_ = ([(k, ctypes.c_int32) for k in _INTS] + [(k, ctypes.c_double) for k in _DOUBLES]
+                + [("body_force", ctypes.c_double * 3)])
+
+
+class lbfz_totals_t(ctypes.Structure):
+    _fields_ = [("sum_f", ctypes.c_double), ("sum_l", ctypes.c_double),
+                ("sum_h", ctypes.c_double), ("mpc", ctypes.c_double),
+                ("vol_solid", ctypes.c_double), ("vol_sl", ctypes.c_double),
+                ("step", ctypes.c_int64), ("nonfinite", ctypes.c_int64)]
+
+
+class LbfzError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {lbfz_strerror(code)} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``liblbfz.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2511_09422_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        pp = ctypes.POINTER(lbfz_params)
+        L.lbfz_workspace_bytes.argtypes = [pp, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbfz_create.argtypes = [pp, dp, dp, dp, vp, vp, ctypes.c_size_t, vp,
+                                  ctypes.POINTER(vp)]
+        L.lbfz_step.argtypes = [vp, ctypes.c_int64]
+        L.lbfz_fields.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
+                                  ctypes.c_int]
+        L.lbfz_totals.argtypes = [vp, ctypes.POINTER(lbfz_totals_t)]
+        L.lbfz_sync.argtypes = [vp]
+        L.lbfz_state_floats.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbfz_get_state.argtypes = [vp, ctypes.c_void_p]
+        L.lbfz_set_state.argtypes = [vp, ctypes.c_void_p]
+        L.lbfz_destroy.argtypes = [vp]
+        L.lbfz_destroy.restype = None
+        L.lbfz_strerror.argtypes = [ctypes.c_int]
+        L.lbfz_strerror.restype = ctypes.c_char_p
+        for nm in ("lbfz_workspace_bytes", "lbfz_create", "lbfz_step", "lbfz_fields",
+                   "lbfz_totals", "lbfz_sync", "lbfz_state_floats", "lbfz_get_state",
+                   "lbfz_set_state"):
+            getattr(L, nm).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def lbfz_strerror(code: int) -> str:
+    return lib().lbfz_strerror(int(code)).decode()
+
+
+def make_params(cfg: dict, storage: str = "f32") -> lbfz_params:
+    P = lbfz_params()
+    for k in _INTS:
+        setattr(P, k, int(cfg.get(k, 0)))
+    if P.dim == 2:
+        P.nz = 1
+    P.storage = STORAGE[storage]
+    P.contact_angle_deg = int(cfg.get("contact_angle_deg", 90))
+    for k in _DOUBLES:
+        setattr(P, k, float(cfg[k]))
+    bf = cfg.get("body_force", (0.0, 0.0, 0.0))
+    for a in range(3):
+        P.body_force[a] = float(bf[a])
+    return P
+
+
+def _check(rc: int, where: str):
+    if rc != LBFZ_OK:
+        raise LbfzError(rc, where)
+
+
+def lbfz_workspace_bytes(cfg: dict, storage: str = "f32") -> int:
+    P = make_params(cfg, storage)
+    n = ctypes.c_size_t()
+    _check(lib().lbfz_workspace_bytes(ctypes.byref(P), ctypes.byref(n)), "lbfz_workspace_bytes")
+    return n.value
+
+
+def lbfz_create(cfg, phi, T, C, mask, ws_ptr: int, ws_bytes: int, stream_ptr: int,
+                storage: str = "f32") -> ctypes.c_void_p:
+    P = make_params(cfg, storage)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (phi, T, C)]
+    dp = ctypes.POINTER(ctypes.c_double)
+    mptr = None
+    if mask is not None:
+        m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+        mptr = m.ctypes.data_as(ctypes.c_void_p)
+    h = ctypes.c_void_p()
+    rc = lib().lbfz_create(ctypes.byref(P), *[a.ctypes.data_as(dp) for a in arrs], mptr,
+                           ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes),
+                           ctypes.c_void_p(stream_ptr), ctypes.byref(h))
+    _check(rc, "lbfz_create")
+    return h
+
+
+def lbfz_step(h, nsteps: int):
+    _check(lib().lbfz_step(h, int(nsteps)), "lbfz_step")
+
+
+def lbfz_fields(h, mask_bits: int, ptrs, dst_is_device: bool):
+    arr = (ctypes.c_void_p * len(FIELDS))(*[ctypes.c_void_p(p) for p in ptrs])
+    _check(lib().lbfz_fields(h, ctypes.c_uint32(mask_bits), arr, int(dst_is_device)),
+           "lbfz_fields")
+
+
+def lbfz_totals(h) -> dict:
+    t = lbfz_totals_t()
+    _check(lib().lbfz_totals(h, ctypes.byref(t)), "lbfz_totals")
+    return {k: getattr(t, k) for k, _ in lbfz_totals_t._fields_}
+
+
+def lbfz_state_floats(h) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().lbfz_state_floats(h, ctypes.byref(n)), "lbfz_state_floats")
+    return n.value
+
+
+def lbfz_get_state(h) -> np.ndarray:
+    out = np.empty(lbfz_state_floats(h), dtype=np.float32)
+    _check(lib().lbfz_get_state(h, out.ctypes.data_as(ctypes.c_void_p)), "lbfz_get_state")
+    return out
+
+
+def lbfz_set_state(h, arr) -> None:
+    a = np.ascontiguousarray(arr, dtype=np.float32).reshape(-1)
+    if a.size != lbfz_state_floats(h):
+        raise ValueError("state size does not match the solver")
+    _check(lib().lbfz_set_state(h, a.ctypes.data_as(ctypes.c_void_p)), "lbfz_set_state")
+
+
+def lbfz_sync(h):
+    _check(lib().lbfz_sync(h), "lbfz_sync")
+
+
+def lbfz_destroy(h):
+    lib().lbfz_destroy(h)
+
+
+class Solver:
+    """A solver state on one GPU.  ``cfg`` is a parameter dictionary (see
+    ``workloads.base_params``), phi/T/C the initial fields (C-order)."""
+
+    def __init__(self, cfg: dict, phi, T, C, mask=None, device: int = 0, storage: str = "f32",
+                 stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the lbfz solver runs on the GPU only")
+        self.cfg = dict(cfg)
+        self.device = torch.device("cuda", device)
+        self.storage = storage
+        nbytes = lbfz_workspace_bytes(cfg, storage)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.shape = ((cfg["nz"], cfg["ny"], cfg["nx"]) if cfg["dim"] == 3
+                      else (cfg["ny"], cfg["nx"]))
+        self.N = int(np.prod(self.shape))
+        self._h = lbfz_create(cfg, phi, T, C, mask, self.workspace.data_ptr(), nbytes,
+                              self.stream.cuda_stream, storage)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lbfz_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self, n: int = 1):
+        lbfz_step(self._h, n)
+
+    def sync(self):
+        lbfz_sync(self._h)
+
+    def fields(self, names=FIELDS, device: bool = False) -> dict:
+        """Macroscopic fields at the current time level (FP32).  device=True
+        returns torch tensors on the GPU (no host copy)."""
+        import torch
+        bits = 0
+        out = {}
+        ptrs = [0] * len(FIELDS)
+        for k, nm in enumerate(FIELDS):
+            if nm in names:
+                bits |= 1 << k
+                if device:
+                    t = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+                else:
+                    t = np.empty(self.shape, dtype=np.float32)
+                out[nm] = t
+                ptrs[k] = t.data_ptr() if device else t.ctypes.data
+        lbfz_fields(self._h, bits, ptrs, device)
+        return out
+
+    def totals(self) -> dict:
+        return lbfz_totals(self._h)
+
+    def get_state(self) -> np.ndarray:
+        """Raw state as (planes, *shape) FP32, in the order of lbfz.h."""
+        return lbfz_get_state(self._h).reshape((-1,) + self.shape)
+
+    def set_state(self, arr) -> None:
+        lbfz_set_state(self._h, arr)

@@ -1,0 +1,73 @@
+"""The C-ABI library loads, exports every symbol include/lbfz.h declares, and
+rejects bad arguments before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2511_09422_amd import lbfz
+from paper_2511_09422_amd.workloads import base_params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "lbfz.h")).read()
+    return sorted(set(re.findall(r"\b(lbfz_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    L = lbfz.lib()
+    names = _declared()
+    assert {"lbfz_create", "lbfz_step", "lbfz_fields", "lbfz_totals"} <= set(names)
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_params_struct_matches_header():
+    # the ctypes mirror lists the header's fields in order
+    txt = open(os.path.join(ROOT, "include", "lbfz.h")).read()
+    body = txt[txt.index("typedef struct lbfz_params"):txt.index("} lbfz_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S).split("{", 1)[1]
+    fields = re.findall(r"\b([a-zA-Z_][a-zA-Z0-9_]*)\s*(?:\[3\])?\s*[,;]", body)
+    assert fields == [f for f, _ in lbfz.lbfz_params._fields_]
+
+
+def test_strerror_and_workspace_errors():
+    assert lbfz.lbfz_strerror(0) == "ok"
+    assert "workspace" in lbfz.lbfz_strerror(lbfz.LBFZ_ENOMEM)
+    cfg = base_params(nx=64, ny=64)
+    assert lbfz.lbfz_workspace_bytes(cfg) > 64 * 64 * 24 * 4 * 2
+    for bad in (dict(tau_phi=0.5), dict(nu=0.0), dict(eps=0.0), dict(nx=1),
+                dict(contact_angle_deg=60)):
+        with pytest.raises(lbfz.LbfzError) as e:
+            lbfz.lbfz_workspace_bytes(base_params(**bad))
+        assert e.value.code == lbfz.LBFZ_EINVAL
+
+
+def test_create_rejects_bad_inputs_before_device_work():
+    cfg = base_params(nx=16, ny=8)
+    phi = np.zeros((8, 16))
+    T = np.zeros((8, 16))
+    C = np.zeros((8, 16))
+    need = lbfz.lbfz_workspace_bytes(cfg)
+    fake = 1 << 20          # never dereferenced: every check below fails first
+    with pytest.raises(lbfz.LbfzError) as e:
+        lbfz.lbfz_create(cfg, phi, T, C, None, fake, need - 256, 0)
+    assert e.value.code == lbfz.LBFZ_ENOMEM
+    with pytest.raises(lbfz.LbfzError) as e:
+        lbfz.lbfz_create(cfg, phi, T, C, None, fake + 4, need, 0)
+    assert e.value.code == lbfz.LBFZ_ENOMEM
+    bad = T.copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(lbfz.LbfzError) as e:
+        lbfz.lbfz_create(cfg, phi, bad, C, None, fake, need, 0)
+    assert e.value.code == lbfz.LBFZ_ENONFINITE
+    with pytest.raises(lbfz.LbfzError) as e:
+        lbfz.lbfz_create(cfg, phi, T, C, np.zeros((8, 16), np.uint8), fake, need, 0)
+    assert e.value.code == lbfz.LBFZ_EINVAL
+    with pytest.raises(lbfz.LbfzError) as e:
+        lbfz.lbfz_create(base_params(nx=16, ny=8, tau_h=0.4), phi, T, C, None, fake, need, 0)
+    assert e.value.code == lbfz.LBFZ_EINVAL

@@ -1,0 +1,214 @@
+"""GPU FP32 path (through the C ABI) against the FP64 oracle, field by field.
+
+Parity measure (per field): max |gpu - oracle| / max |oracle| over the grid,
+for phi, f_l, T, C, u, p.
+
+Three bars:
+* one step from the same state: the GPU state after K steps is loaded into
+  the oracle and both take one step; every population, every previous-level
+  field and every macroscopic field must agree to 2e-5 (FP32 rounding of one
+  step).  This checks the step at any point of a long trajectory.
+* trajectories of 1 to 1000 steps from the initial state: within 1e-4 or
+  three times the spread of the FP64 oracle itself when its populations carry
+  FP32-sized (6e-8 relative) noise each step, whichever is larger.  Freezing
+  with volume change makes these configurations amplify rounding-level
+  perturbations by ~1e4 over 1000 steps (the noisy FP64 oracle drifts by 1e-3
+  to 5e-3 from the clean one), so no FP32 implementation meets 1e-4 there;
+  the one-step bar above is what checks the arithmetic.
+
+Cases cover a single partial tile, several tiles with a ragged tail in both
+axes, a fully periodic box, both Dirichlet walls with a modulated wall
+temperature and the plain surface-tension mode with a body force, and the
+2048x2048 droplet in the launch configuration the benchmark times."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.lbref import Oracle
+from paper_2511_09422_amd.workloads import droplet_2d
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi", "fl", "T", "C", "ux", "uy", "p")
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def rel_linf(got, ref):
+    return float(np.abs(np.asarray(got, np.float64) - ref).max() / max(np.abs(ref).max(), 1e-30))
+
+
+def _periodic_case():
+    cfg, _, _, _ = droplet_2d(96, 68, R=18.0, seed=3, walls=0, t_lo_dirichlet=0)
+    y, x = np.meshgrid(np.arange(68.), np.arange(96.), indexing="ij")
+    d = np.hypot(x - 48, y - 30)
+    phi = np.tanh((18 - d) / 2.0)
+    T = 0.1 - 0.4 * np.exp(-((x - 40) ** 2 + (y - 25) ** 2) / 60.0)
+    C = 0.05 * np.clip((1 + phi) / 2, 0, 1)
+    return cfg, phi, T, C
+
+
+CASES = {
+    "8x8": lambda: droplet_2d(8, 8, R=3.0, seed=1, sigma_T=-1e-3),
+    "64x64": lambda: droplet_2d(64, 64, R=16.0, seed=0),
+    "150x37": lambda: droplet_2d(150, 37, R=20.0, seed=2),
+    "periodic": _periodic_case,
+    "walls": lambda: droplet_2d(80, 40, R=15.0, seed=4, t_hi_dirichlet=1, T_hi=0.3,
+                                T_lo_amp=0.2, surface_tension_mode=1,
+                                body_force=(2e-6, -1e-6, 0.0), sigma_c=-2e-3,
+                                Ds_over_Dl=0.5, T_sol=-0.02, T_liq=0.03, rho_s=0.85),
+}
+
+
+def _solver(cfg, phi, T, C):
+    from paper_2511_09422_amd.lbfz import Solver
+    return Solver(cfg, phi, T, C)
+
+
+def _load_into_oracle(cfg, state, shape):
+    """Oracle whose populations and previous-level fields are the GPU's."""
+    o = Oracle(cfg, np.zeros(shape), np.zeros(shape), np.zeros(shape), threads=THREADS)
+    st = state.astype(np.float64)
+    o.set_pops(0, st[0:5])
+    o.set_pops(1, st[5:14])
+    o.set_pops(3, st[19:24])
+    o.set_pops(2, st[14:19])
+    for k, w in ((24, 0), (25, 1), (26, 2), (27, 3), (28, 5), (29, 6)):
+        o.set_state(w, st[k])
+    o.set_state(4, np.zeros(shape))
+    return o
+
+
+@pytest.mark.parametrize("case,K", [("8x8", 50), ("64x64", 0), ("64x64", 300), ("64x64", 1000),
+                                    ("150x37", 300), ("periodic", 300), ("walls", 400)])
+def test_one_step_from_gpu_state(case, K):
+    cfg, phi, T, C = CASES[case]()
+    print(f"[one-step] {case} after {K} steps", flush=True)
+    s = _solver(cfg, phi, T, C)
+    s.step(K)
+    o = _load_into_oracle(cfg, s.get_state(), s.shape)
+    s.step(1)
+    o.step(1)
+    got_state = s.get_state().astype(np.float64)
+    for name, sl, w in (("f", slice(0, 5), 0), ("g", slice(5, 14), 1), ("h", slice(14, 19), 2),
+                        ("l", slice(19, 24), 3)):
+        err = rel_linf(got_state[sl], o.get_pops(w))
+        assert err <= 2e-5, (case, K, name, err)
+    for k, w in ((24, 0), (25, 1), (26, 2), (27, 3), (28, 5), (29, 6)):
+        err = rel_linf(got_state[k], o.get_state(w))
+        assert err <= 2e-5, (case, K, "state", k, err)
+    got, ref = s.fields(), o.fields()
+    errs = {k: rel_linf(got[k], ref[k]) for k in FIELDS}
+    print(f"[one-step] {case} K={K} " + " ".join(f"{k}={v:.1e}" for k, v in errs.items()),
+          flush=True)
+    for k, e in errs.items():
+        assert e <= 2e-5, (case, K, k, e)
+
+
+@pytest.mark.parametrize("case,steps", [("8x8", 1), ("8x8", 10), ("8x8", 100), ("64x64", 30),
+                                        ("64x64", 100), ("150x37", 100), ("periodic", 100),
+                                        ("walls", 100)])
+def test_multi_step_parity(case, steps):
+    cfg, phi, T, C = CASES[case]()
+    s = _solver(cfg, phi, T, C)
+    s.step(steps)
+    got = s.fields()
+    o = Oracle(cfg, phi, T, C, threads=THREADS)
+    o.step(steps)
+    ref = o.fields()
+    spread = _noisy_oracle_spread(cfg, phi, T, C, steps, ref)
+    errs = {k: rel_linf(got[k], ref[k]) for k in FIELDS}
+    print(f"[multi] {case} {steps} gpu " + " ".join(f"{k}={v:.1e}" for k, v in errs.items())
+          + " | spread " + " ".join(f"{k}={v:.1e}" for k, v in spread.items()), flush=True)
+    for k, e in errs.items():
+        assert e <= max(1e-4, 3.0 * spread[k]), (case, steps, k, e, spread[k])
+    assert s.totals()["nonfinite"] == 0
+
+
+def _noisy_oracle_spread(cfg, phi, T, C, steps, ref, seeds=(1, 2, 3)):
+    spread = {k: 0.0 for k in FIELDS}
+    for sd in seeds:
+        rng = np.random.default_rng(sd)
+        o = Oracle(cfg, phi, T, C, threads=THREADS)
+        for _ in range(steps):
+            for w in range(4):
+                p = o.get_pops(w)
+                o.set_pops(w, p * (1 + 6e-8 * rng.uniform(-1, 1, size=p.shape)))
+            o.step(1)
+        f = o.fields()
+        for k in FIELDS:
+            spread[k] = max(spread[k], rel_linf(f[k], ref[k]))
+    return spread
+
+
+def test_droplet_64x64_1000_steps():
+    cfg, phi, T, C = CASES["64x64"]()
+    s = _solver(cfg, phi, T, C)
+    t0 = s.totals()
+    s.step(1000)
+    got = s.fields()
+    tg = s.totals()
+    o = Oracle(cfg, phi, T, C, threads=THREADS)
+    o.step(1000)
+    ref = o.fields()
+    tr = o.totals()
+    spread = _noisy_oracle_spread(cfg, phi, T, C, 1000, ref)
+    errs = {k: rel_linf(got[k], ref[k]) for k in FIELDS}
+    print("[1000] gpu " + " ".join(f"{k}={v:.1e}" for k, v in errs.items()), flush=True)
+    print("[1000] fp64 oracle spread under fp32 noise " +
+          " ".join(f"{k}={v:.1e}" for k, v in spread.items()), flush=True)
+    for k in FIELDS:
+        assert errs[k] <= max(1e-4, 3.0 * spread[k]), (k, errs[k], spread[k])
+    # integral quantities are well conditioned
+    norm = np.abs(phi).sum()
+    assert abs(tg["sum_f"] - t0["sum_f"] - tg["mpc"]) <= 1e-5 * norm
+    assert abs(tg["sum_l"] - t0["sum_l"]) <= 1e-5 * t0["sum_l"]
+    assert abs(tg["vol_solid"] - tr["vol_solid"]) <= 1e-3 * tr["vol_solid"]
+    assert abs(tg["sum_h"] - tr["sum_h"]) <= 1e-4 * abs(tr["sum_h"])
+    assert tg["step"] == 1000 and tg["nonfinite"] == 0
+
+
+def test_totals_are_deterministic_and_restart_is_exact():
+    cfg, phi, T, C = droplet_2d(200, 100, R=30.0, seed=5)
+    s = _solver(cfg, phi, T, C)
+    s.step(50)
+    a, b = s.totals(), s.totals()
+    assert a == b
+    s2 = _solver(cfg, phi, T, C)
+    s2.step(50)
+    assert s2.totals() == a
+    # checkpoint / restart: continuing from an exported state is bit-identical
+    chk = s.get_state()
+    s.step(60)
+    s3 = _solver(cfg, phi, T, C)
+    s3.set_state(chk)
+    s3.step(60)
+    assert np.array_equal(s.get_state(), s3.get_state())
+
+
+def test_full_size_2048_parity_and_conservation():
+    """The 2048^2 droplet (radius 512) in the benchmark's launch
+    configuration: every field against the oracle after 3 steps, one step
+    from the GPU state after 200 steps, and the conservation properties."""
+    cfg, phi, T, C = droplet_2d(2048, 2048, R=512.0, seed=0)
+    s = _solver(cfg, phi, T, C)
+    t0 = s.totals()
+    s.step(3)
+    got = s.fields()
+    o = Oracle(cfg, phi, T, C, threads=THREADS)
+    o.step(3)
+    ref = o.fields()
+    for k in FIELDS:
+        assert rel_linf(got[k], ref[k]) <= 1e-4, k
+    del o
+    s.step(197)
+    o = _load_into_oracle(cfg, s.get_state(), s.shape)
+    s.step(1)
+    o.step(1)
+    got, ref = s.fields(), o.fields()
+    for k in FIELDS:
+        assert rel_linf(got[k], ref[k]) <= 2e-5, k
+    t1 = s.totals()
+    assert t1["nonfinite"] == 0
+    assert abs(t1["sum_f"] - t0["sum_f"] - t1["mpc"]) <= 1e-5 * np.abs(phi).sum()
+    assert abs(t1["sum_l"] - t0["sum_l"]) <= 1e-5 * t0["sum_l"]
