@@ -573,8 +573,11 @@ static double forces_node(const lbref_state* s, int n, double* u, double* F, dou
   for (int a = 0; a < 3; ++a)
     grho[a] = 0.5 * (P->rho_l - P->rho_g) * gphi[a] + (P->rho_s - P->rho_l) * gfs[a];
   double ng = sqrt(dot3(gphi, gphi));
-  /* Reading: n = grad phi / |grad phi| is taken as 0 where |grad phi| < 1e-10. */
-  for (int a = 0; a < 3; ++a) nvec[a] = ng >= 1e-10 ? gphi[a] / ng : 0.0;
+  /* Reading: n = grad phi / |grad phi| (Sec. 3.1, 3.4) is undefined in the
+   * bulk, where grad phi is rounding noise; it is taken as
+   * grad phi / max(|grad phi|, 1e-6), exact wherever an interface is resolved
+   * and continuous, so that noise cannot pick its direction. */
+  for (int a = 0; a < 3; ++a) nvec[a] = gphi[a] / fmax(ng, 1e-6);
   /* Chemical potential with phi1 = 1, phi2 = -1, k = 1, beta = 1/(4 eps^2). */
   double mu = phi * (phi * phi - 1.0) / (P->eps * P->eps) - s->lapphi[n];
   double sigma = P->sigma0 + P->sigma_T * (s->T[n] - P->T_ref) + P->sigma_c * (s->C[n] - P->c_ref);

@@ -28,6 +28,7 @@ constexpr int TX = 64, TY = LBFZ_TY, NT = TX * TY;
 constexpr int HX = TX + 2, HY = TY + 2;  // closure ring
 constexpr int UX = TX + 4, UY = TY + 4;  // velocity ring
 constexpr int RING = 2 * HX + 2 * TY;
+static_assert(RING <= NT, "every ring slot needs a thread");
 
 constexpr int PF = 0, PG = 5, PH = 14, PL = 19;
 
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
   const float gry = 0.5f * (P.rho_l - P.rho_g) * gpy + (P.rho_s - P.rho_l) * gfy;
   const float g2 = gpx * gpx + gpy * gpy;
   const float ng = sqrtf(g2);
-  const float inv_ng = ng >= 1e-10f ? 1.0f / ng : 0.0f;
+  const float inv_ng = 1.0f / fmaxf(ng, 1e-6f);  // n regularised in the bulk
   const float nvx = gpx * inv_ng, nvy = gpy * inv_ng;
   const float mu = phi * (phi * phi - 1.0f) * P.ieps2 - lap;
   const float sig = P.sigma0 + P.sigma_T * (T - P.T_ref) + P.sigma_c * (C - P.c_ref);

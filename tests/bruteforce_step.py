@@ -115,7 +115,8 @@ def step(P, pops, state):
         grx = (P["rho_l"] - P["rho_g"]) / 2 * gpx + (P["rho_s"] - P["rho_l"]) * gfx
         gry = (P["rho_l"] - P["rho_g"]) / 2 * gpy + (P["rho_s"] - P["rho_l"]) * gfy
         ng = sqrt(gpx ** 2 + gpy ** 2)
-        nx_, ny_ = (gpx / ng, gpy / ng) if ng >= mpf("1e-10") else (mpf(0), mpf(0))
+        den = max(ng, mpf("1e-6"))
+        nx_, ny_ = gpx / den, gpy / den
         ph = phi[y][x]
         mu = ph * (ph ** 2 - 1) / eps ** 2 - lp
         sig = P["sigma0"] + P["sigma_T"] * (T[y][x] - P["T_ref"]) + P["sigma_c"] * (C[y][x] - P["c_ref"])
