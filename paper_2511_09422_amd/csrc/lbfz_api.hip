@@ -34,6 +34,7 @@ struct lbfz_handle {
   int64_t step;
   int ntiles;
   int npop;
+  int seg;  // 3D: z planes per block
 };
 
 namespace {
@@ -46,9 +47,11 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 bool valid_params(const lbfz_params* p) {
   if (!p) return false;
-  if (p->dim != 2) return false;  // 3D is declared but reported unsupported below
-  if (p->nx < 2 || p->ny < 2 || p->nz != 1) return false;
-  if ((long long)p->nx * p->ny > (1ll << 26)) return false;
+  if (p->dim != 2 && p->dim != 3) return false;
+  if (p->nx < 2 || p->ny < 2) return false;
+  if (p->dim == 2 && p->nz != 1) return false;
+  if (p->dim == 3 && p->nz < 2) return false;
+  if ((long long)p->nx * p->ny * p->nz > (1ll << 26)) return false;
   if (!(p->tau_phi > 0.5 && p->tau_h > 0.5 && p->tau_c > 0.5 && p->nu > 0.0)) return false;
   if (!(p->eps > 0.0 && p->rhoc_ref > 0.0)) return false;
   if (!(p->rho_l > 0 && p->rho_g > 0 && p->rho_s > 0)) return false;
@@ -61,9 +64,17 @@ bool valid_params(const lbfz_params* p) {
 }
 
 int check_support(const lbfz_params* p) {
-  if (p && p->dim == 3) return LBFZ_EUNSUPPORTED;
   if (p && p->storage != LBFZ_STORE_F32) return LBFZ_EUNSUPPORTED;
   return LBFZ_OK;
+}
+
+int npop_of(const lbfz_params* p) { return p->dim == 3 ? 40 : 24; }
+int seg_of(const lbfz_params* p) { return p->dim == 3 ? std::min(32, p->nz) : 1; }
+
+int tiles_of(const lbfz_params* p, int* nbx, int* nby, int* nbz) {
+  if (p->dim == 3) return tiles3d(p->nx, p->ny, p->nz, seg_of(p), nbx, nby, nbz);
+  *nbz = 1;
+  return tiles2d(p->nx, p->ny, nbx, nby);
 }
 
 Layout layout(const lbfz_params* p, int ntiles, int npop) {
@@ -82,7 +93,7 @@ Layout layout(const lbfz_params* p, int ntiles, int npop) {
   return L;
 }
 
-KParams make_kparams(const lbfz_params* p, int nbx, int nby) {
+KParams make_kparams(const lbfz_params* p, int nbx, int nby, int nbz) {
   KParams k;
   std::memset(&k, 0, sizeof(k));
   k.nx = p->nx;
@@ -95,8 +106,8 @@ KParams make_kparams(const lbfz_params* p, int nbx, int nby) {
   k.st_mode = p->surface_tension_mode;
   k.nblk_x = nbx;
   k.nblk_y = nby;
-  k.nblk_z = 1;
-  k.nblk = nbx * nby;
+  k.nblk_z = nbz;
+  k.nblk = nbx * nby * nbz;
   k.rho_l = (float)p->rho_l;
   k.rho_g = (float)p->rho_g;
   k.rho_s = (float)p->rho_s;
@@ -174,6 +185,11 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ tot,
     if ((x) != hipSuccess) return LBFZ_EHIP; \
   } while (0)
 
+hipError_t launch_step(lbfz_handle* h, const StepArgs& a, bool dry) {
+  if (h->prm.dim == 3) return launch_step3d(h->kp, a, h->seg, dry, h->stream);
+  return launch_step2d(h->kp, a, dry, h->stream);
+}
+
 StepArgs base_args(lbfz_handle* h) {
   StepArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -197,10 +213,12 @@ StepArgs base_args(lbfz_handle* h) {
 extern "C" {
 
 int lbfz_workspace_bytes(const lbfz_params* p, size_t* bytes) {
-  if (!bytes || !valid_params(p)) return p && p->dim == 3 ? LBFZ_EUNSUPPORTED : LBFZ_EINVAL;
-  int nbx, nby;
-  const int nt = tiles2d(p->nx, p->ny, &nbx, &nby);
-  *bytes = layout(p, nt, 24).total;
+  if (!bytes || !valid_params(p)) return LBFZ_EINVAL;
+  const int sup = check_support(p);
+  if (sup != LBFZ_OK) return sup;
+  int nbx, nby, nbz;
+  const int nt = tiles_of(p, &nbx, &nby, &nbz);
+  *bytes = layout(p, nt, npop_of(p)).total;
   return LBFZ_OK;
 }
 
@@ -218,9 +236,9 @@ int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const 
   for (size_t n = 0; n < N; ++n)
     if (!std::isfinite(phi[n]) || !std::isfinite(T[n]) || !std::isfinite(C[n]))
       return LBFZ_ENONFINITE;
-  int nbx, nby;
-  const int ntiles = tiles2d(p->nx, p->ny, &nbx, &nby);
-  const int npop = 24;
+  int nbx, nby, nbz;
+  const int ntiles = tiles_of(p, &nbx, &nby, &nbz);
+  const int npop = npop_of(p);
   const Layout L = layout(p, ntiles, npop);
   if (ws_bytes < L.total) return LBFZ_ENOMEM;
 
@@ -228,7 +246,8 @@ int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const 
   if (!h) return LBFZ_ENOMEM;
   std::memset(h, 0, sizeof(*h));
   h->prm = *p;
-  h->kp = make_kparams(p, nbx, nby);
+  h->kp = make_kparams(p, nbx, nby, nbz);
+  h->seg = seg_of(p);
   h->stream = (hipStream_t)stream;
   h->ws = (char*)d_workspace;
   h->ws_bytes = ws_bytes;
@@ -248,7 +267,8 @@ int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const 
   h->tot_part = (double*)q; q += L.tot;
   h->red = (double*)q; q += L.red;
   h->stage = (float*)q; q += L.stage;
-  h->mask = nullptr;
+  h->mask = p->dim == 3 && mask ? (uint8_t*)q : nullptr;
+  q += L.mask;
   h->cur = 0;
   h->step = 0;
 
@@ -265,7 +285,16 @@ int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const 
       break;
     }
     StateArgs S{h->p[0], h->p[1], h->u[0], h->u[1], h->fs, h->phiP, h->CP};
-    if (launch_init2d(h->kp, st, st + N, st + 2 * N, h->pop[0], S, h->stream) != hipSuccess) {
+    if (h->mask &&
+        hipMemcpyAsync(h->mask, mask, N, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+      rc = LBFZ_EHIP;
+      break;
+    }
+    const hipError_t e = p->dim == 3 ? launch_init3d(h->kp, st, st + N, st + 2 * N, h->mask,
+                                                     h->pop[0], h->pop[1], S, h->stream)
+                                     : launch_init2d(h->kp, st, st + N, st + 2 * N, h->pop[0], S,
+                                                     h->stream);
+    if (e != hipSuccess) {
       rc = LBFZ_EHIP;
       break;
     }
@@ -285,7 +314,7 @@ int lbfz_step(lbfz_handle* h, int64_t nsteps) {
   if (!h || nsteps < 0) return LBFZ_EINVAL;
   for (int64_t k = 0; k < nsteps; ++k) {
     StepArgs a = base_args(h);
-    HIPCHK(launch_step2d(h->kp, a, false, h->stream));
+    HIPCHK(launch_step(h, a, false));
     h->cur ^= 1;
     h->step += 1;
   }
@@ -303,7 +332,7 @@ int lbfz_fields(lbfz_handle* h, uint32_t field_mask, float* const* dst, int dst_
       a.out[k] = dst_is_device ? dst[k] : h->stage + (size_t)k * N;
     }
   }
-  HIPCHK(launch_step2d(h->kp, a, true, h->stream));
+  HIPCHK(launch_step(h, a, true));
   if (!dst_is_device) {
     for (int k = 0; k < LBFZ_NFIELDS; ++k)
       if (field_mask & (1u << k))
@@ -319,7 +348,7 @@ int lbfz_totals(lbfz_handle* h, lbfz_totals_t* out) {
   StepArgs a = base_args(h);
   for (int k = 0; k < LBFZ_NFIELDS; ++k) a.out[k] = nullptr;
   a.tot_part = h->tot_part;
-  HIPCHK(launch_step2d(h->kp, a, true, h->stream));
+  HIPCHK(launch_step(h, a, true));
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, h->stream, h->tot_part, h->mpc_part,
                      h->ntiles, h->red);
   HIPCHK(hipGetLastError());

@@ -40,4 +40,11 @@ hipError_t launch_init2d(const KParams& P, const double* phi, const double* T, c
                          float* pop, const StateArgs& S, hipStream_t st);
 hipError_t launch_step2d(const KParams& P, const StepArgs& A, bool dry, hipStream_t st);
 
+int tiles3d(int nx, int ny, int nz, int seg, int* nbx, int* nby, int* nbz);
+size_t lds3d_bytes();
+hipError_t launch_init3d(const KParams& P, const double* phi, const double* T, const double* C,
+                         const uint8_t* mask, float* popA, float* popB, const StateArgs& S,
+                         hipStream_t st);
+hipError_t launch_step3d(const KParams& P, const StepArgs& A, int seg, bool dry, hipStream_t st);
+
 }  // namespace lbfz
