@@ -332,109 +332,111 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
     return;
   }
 
-  // 5. collisions
+  // 5. collisions, each post-collision population pushed along its link as
+  // soon as it is computed (no arrays of post-collision values stay live).
+  // A link across a wall is closed by half-way bounce-back into the opposite
+  // slot of the same node; h at a Dirichlet wall by anti-bounce-back.
+  float* __restrict__ dst = A.dst;
+  auto target = [&](int i, int& m) -> bool {  // true: the link leaves through a wall
+    const int ty2 = gy + CY[i];
+    if (P.walls && (ty2 < 0 || ty2 >= ny)) return true;
+    m = wrapc(ty2, ny) * nx + wrapc(gx + CX[i], nx);
+    return false;
+  };
+  auto push = [&](int base, int i, float v) {
+    int m = n;
+    if (target(i, m))
+      dst[(base + OPP[i]) * N + n] = v;
+    else
+      dst[(base + i) * N + m] = v;
+  };
   // flow BGK (Sec. 3.2)
-  float gp[9];
-  float geq0 = 0.0f;
+  if (valid) {
+    float geq_sum = 0.0f;
 #pragma unroll
-  for (int i = 1; i < 9; ++i) {
-    const float cu = CX[i] * ux + CY[i] * uy;
-    const float si = W9[i] * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
-    const float geq = pn * kInvCs2 * W9[i] + rho * si;
-    geq0 -= geq;
-    gp[i] = g[i] - (g[i] - geq) * P.itau_g + P.wg * G[i];
+    for (int i = 1; i < 9; ++i) {
+      const float cu = CX[i] * ux + CY[i] * uy;
+      const float si = W9[i] * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+      const float geq = pn * kInvCs2 * W9[i] + rho * si;
+      geq_sum += geq;
+      push(PG, i, g[i] - (g[i] - geq) * P.itau_g + P.wg * G[i]);
+    }
+    dst[(PG + 0) * N + n] = g[0] - (g[0] + geq_sum) * P.itau_g + P.wg * G[0];
   }
-  gp[0] = g[0] - (g[0] - geq0) * P.itau_g + P.wg * G[0];
   // phase field BGK (Sec. 3.1)
   const float upx = s_ux[ty + 2][tx + 2], upy = s_uy[ty + 2][tx + 2];
-  const float cf = kCs2 * (1.0f - phi * phi) * P.isq;
-  const float Bx = (phi * ux - phiP * upx) + cf * nvx;
-  const float By = (phi * uy - phiP * upy) + cf * nvy;
-  float fp[5];
-  float feq0 = phi, F0 = phi * D;
+  if (valid) {
+    const float cf = kCs2 * (1.0f - phi * phi) * P.isq;
+    const float Bx = (phi * ux - phiP * upx) + cf * nvx;
+    const float By = (phi * uy - phiP * upy) + cf * nvy;
+    float feq_sum = 0.0f, F_sum = 0.0f;
 #pragma unroll
-  for (int i = 1; i < 5; ++i) {
-    const float cu = CX[i] * ux + CY[i] * uy;
-    const float Fi = W5[i] * (kInvCs2 * (CX[i] * Bx + CY[i] * By) + phi * D);
-    const float feq = W5[i] * phi * (1.0f + kInvCs2 * cu);
-    feq0 -= feq;
-    F0 -= Fi;
-    fp[i] = f[i] - (f[i] - feq) * P.itau_f + P.wf * Fi;
+    for (int i = 1; i < 5; ++i) {
+      const float cu = CX[i] * ux + CY[i] * uy;
+      const float Fi = W5[i] * (kInvCs2 * (CX[i] * Bx + CY[i] * By) + phi * D);
+      const float feq = W5[i] * phi * (1.0f + kInvCs2 * cu);
+      feq_sum += feq;
+      F_sum += Fi;
+      push(PF, i, f[i] - (f[i] - feq) * P.itau_f + P.wf * Fi);
+    }
+    dst[(PF + 0) * N + n] =
+        f[0] - (f[0] - (phi - feq_sum)) * P.itau_f + P.wf * (phi * D - F_sum);
   }
-  fp[0] = f[0] - (f[0] - feq0) * P.itau_f + P.wf * F0;
   // enthalpy TRT (Sec. 3.3); E and Q from the closure of the own node
-  float heq[5], hq[5];
-  {
+  if (valid) {
+    float heq[5];
     const float rT = P.rhoc_ref * T, cT = rcp * T;
     heq[0] = cl.E;
-    hq[0] = cl.Q;
 #pragma unroll
     for (int i = 1; i < 5; ++i) {
       const float cu = CX[i] * ux + CY[i] * uy;
       heq[i] = W5[i] * (rT + cT * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
       heq[0] -= heq[i];
-      hq[i] = W5[i] * cl.Q;
-      hq[0] -= hq[i];
     }
-  }
-  float hp[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    const int o = OPP[i];
-    const float hs = 0.5f * (h[i] + h[o]), ha = 0.5f * (h[i] - h[o]);
-    const float es = 0.5f * (heq[i] + heq[o]), ea = 0.5f * (heq[i] - heq[o]);
-    hp[i] = h[i] - (hs - es) * P.itau_s - (ha - ea) * P.itau_a + P.ws * hq[i];
-  }
-  // solute BGK (Sec. 3.4)
-  const float keff = 1.0f - fs * (1.0f - P.k_p);
-  const float De = fs * P.k_p * P.Ds + (1.0f - fs) * P.Dl;
-  const float tau_l = De / (kCs2 * keff) + 0.5f;
-  const float itau_l = 1.0f / tau_l, wl = 1.0f - 0.5f * itau_l;
-  const float cr = (1.0f - phi) * C * P.isq, ck = (P.k_p - 1.0f) * C / keff;
-  const float Lx = (C * ux - CP * upx) + kCs2 * (cr * nvx + ck * gfx);
-  const float Ly = (C * uy - CP * upy) + kCs2 * (cr * nvy + ck * gfy);
-  float lp[5];
-  float leq0 = C;
-#pragma unroll
-  for (int i = 1; i < 5; ++i) {
-    const float cu = CX[i] * ux + CY[i] * uy;
-    const float Li = W5[i] * kInvCs2 * (CX[i] * Lx + CY[i] * Ly);
-    const float leq = W5[i] * C * (1.0f + kInvCs2 * cu);
-    leq0 -= leq;
-    lp[i] = l[i] - (l[i] - leq) * itau_l + wl * Li;
-  }
-  lp[0] = l[0] - (l[0] - leq0) * itau_l;
-
-  // 6. streaming (push) with walls, and the time-level state
-  if (valid) {
-    float* __restrict__ dst = A.dst;
+    const float hq = W5[1] * cl.Q, hq0 = cl.Q - 4.0f * hq;
     const float Tw_lo = P.T_lo + P.T_lo_amp * cosf(P.kwall * (float)gx);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const int ty2 = gy + CY[i];
-      const int tx2 = wrapc(gx + CX[i], nx);
-      if (i < 5) {
-        if (P.walls && (ty2 < 0 || ty2 >= ny)) {
-          const int o = OPP[i];
-          dst[(PF + o) * N + n] = fp[i];
-          dst[(PL + o) * N + n] = lp[i];
-          float hv = hp[i];
-          if (ty2 < 0 && P.tlo_dir) hv = -hv + 2.0f * W5[o] * P.rhoc_ref * Tw_lo;
-          if (ty2 >= ny && P.thi_dir) hv = -hv + 2.0f * W5[o] * P.rhoc_ref * P.T_hi;
-          dst[(PH + o) * N + n] = hv;
-        } else {
-          const int m = wrapc(ty2, ny) * nx + tx2;
-          dst[(PF + i) * N + m] = fp[i];
-          dst[(PH + i) * N + m] = hp[i];
-          dst[(PL + i) * N + m] = lp[i];
-        }
-      }
-      if (P.walls && (ty2 < 0 || ty2 >= ny)) {
-        dst[(PG + OPP[i]) * N + n] = gp[i];
+    for (int i = 0; i < 5; ++i) {
+      const int o = OPP[i];
+      const float hs = 0.5f * (h[i] + h[o]), ha = 0.5f * (h[i] - h[o]);
+      const float es = 0.5f * (heq[i] + heq[o]), ea = 0.5f * (heq[i] - heq[o]);
+      const float v = h[i] - (hs - es) * P.itau_s - (ha - ea) * P.itau_a +
+                      P.ws * (i == 0 ? hq0 : hq);
+      int m = n;
+      if (target(i, m)) {
+        const int ty2 = gy + CY[i];
+        float hv = v;
+        if (ty2 < 0 && P.tlo_dir) hv = -hv + 2.0f * W5[o] * P.rhoc_ref * Tw_lo;
+        if (ty2 >= ny && P.thi_dir) hv = -hv + 2.0f * W5[o] * P.rhoc_ref * P.T_hi;
+        dst[(PH + o) * N + n] = hv;
       } else {
-        dst[(PG + i) * N + wrapc(ty2, ny) * nx + tx2] = gp[i];
+        dst[(PH + i) * N + m] = v;
       }
     }
+  }
+  // solute BGK (Sec. 3.4)
+  if (valid) {
+    const float keff = 1.0f - fs * (1.0f - P.k_p);
+    const float De = fs * P.k_p * P.Ds + (1.0f - fs) * P.Dl;
+    const float tau_l = De / (kCs2 * keff) + 0.5f;
+    const float itau_l = 1.0f / tau_l, wl = 1.0f - 0.5f * itau_l;
+    const float cr = (1.0f - phi) * C * P.isq, ck = (P.k_p - 1.0f) * C / keff;
+    const float Lx = (C * ux - CP * upx) + kCs2 * (cr * nvx + ck * gfx);
+    const float Ly = (C * uy - CP * upy) + kCs2 * (cr * nvy + ck * gfy);
+    float leq_sum = 0.0f;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      const float cu = CX[i] * ux + CY[i] * uy;
+      const float Li = W5[i] * kInvCs2 * (CX[i] * Lx + CY[i] * Ly);
+      const float leq = W5[i] * C * (1.0f + kInvCs2 * cu);
+      leq_sum += leq;
+      push(PL, i, l[i] - (l[i] - leq) * itau_l + wl * Li);
+    }
+    dst[(PL + 0) * N + n] = l[0] - (l[0] - (C - leq_sum)) * itau_l;
+  }
+
+  // 6. the time-level state
+  if (valid) {
     A.p_new[n] = pn;
     A.u_new[n] = ux;
     A.u_new[N + n] = uy;

@@ -26,7 +26,7 @@ constexpr int TX = 32, TY = 8, NT = TX * TY;
 constexpr int HX = TX + 2, HY = TY + 2;  // closure ring
 constexpr int UX = TX + 4, UY = TY + 4;  // velocity ring
 constexpr int HS = HX * HY, US = UX * UY;
-constexpr int NF = 6;                    // phi, T, C, f_s, p, div u
+constexpr int NF = 8;                    // phi, T, C, f_s, p, div u, E, Q
 
 constexpr int PF = 0, PG = 7, PH = 26, PL = 33;
 
@@ -134,6 +134,8 @@ __device__ __forceinline__ void close_plane(const KParams& P, const StepArgs& A,
       S.c[slot][3][s] = 0.0f;
       S.c[slot][4][s] = 0.0f;
       S.c[slot][5][s] = 0.0f;
+      S.c[slot][6][s] = E0;
+      S.c[slot][7][s] = 0.0f;
       continue;
     }
     // div u^{n-1}: D3Q19 isotropic gradient, obstacle neighbours give -u(centre)
@@ -157,6 +159,8 @@ __device__ __forceinline__ void close_plane(const KParams& P, const StepArgs& A,
     S.c[slot][3][s] = cl.fs;
     S.c[slot][4][s] = A.p_old[n];
     S.c[slot][5][s] = D;
+    S.c[slot][6][s] = cl.E;
+    S.c[slot][7][s] = cl.Q;
   }
 }
 
@@ -215,20 +219,30 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
     const bool ob = S.cm[s0][cs] != 0;
     if (valid) {
       // stencil neighbour value with the obstacle rule (kind 0 -> centre)
+      // obstacle neighbours as a bit set (bit i for link i), so the stencils
+      // below read the mask once; without a mask it stays zero
+      uint32_t obm = 0;
+      if (A.mask) {
+#pragma unroll
+        for (int i = 1; i < 19; ++i) {
+          const int pl = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
+          obm |= S.cm[pl][cs + CY[i] * HX + CX[i]] ? (1u << i) : 0u;
+        }
+      }
       auto nb = [&](int f, int i, bool kind0) -> float {
         const int pl = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
         const int t = cs + CY[i] * HX + CX[i];
-        if (kind0 && S.cm[pl][t]) return S.c[s0][f][cs];
+        if (kind0 && (obm >> i & 1u)) return S.c[s0][f][cs];
         return S.c[pl][f][t];
       };
-      float h[7];
-#pragma unroll
-      for (int i = 0; i < 7; ++i) h[i] = A.src[(PH + i) * N + n];
       const float phi = S.c[s0][0][cs], T = S.c[s0][1][cs], C = S.c[s0][2][cs];
       const float fs = S.c[s0][3][cs];
       if (ob) {
         // obstacle: enthalpy at rest without source (pure conduction)
-        const float E = h[0] + h[1] + h[2] + h[3] + h[4] + h[5] + h[6];
+        float h[7];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) h[i] = A.src[(PH + i) * N + n];
+        const float E = S.c[s0][6][cs];
         float heq[7];
         heq[0] = E;
 #pragma unroll
@@ -279,36 +293,37 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
           A.CP[n] = 0.f;
         }
       } else {
-        float f[7], l[7], g[19];
-        f[0] = 0.f;
-        l[0] = 0.f;
+        // stencils (isotropic D3Q19 gradient / Laplacian), one field per pass so
+        // that few LDS values are in flight at once
+        float gp[3], gT[3], gC[3], gf[3], gP[3], lap = 0.f;
+        auto grad = [&](int fld, bool kind0, float* gr) {
+          float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
-        for (int i = 1; i < 7; ++i) {
-          f[i] = A.src[(PF + i) * N + n];
-          l[i] = A.src[(PL + i) * N + n];
-        }
+          for (int i = 1; i < 19; ++i) {
+            const float v = nb(fld, i, kind0) * (W19[i] * kInvCs2);
+            if (CX[i]) a0 += CX[i] * v;
+            if (CY[i]) a1 += CY[i] * v;
+            if (CZ[i]) a2 += CZ[i] * v;
+          }
+          gr[0] = a0;
+          gr[1] = a1;
+          gr[2] = a2;
+        };
+        grad(0, true, gp);
+#pragma unroll
+        for (int i = 1; i < 19; ++i) lap += 2.0f * W19[i] * kInvCs2 * (nb(0, i, true) - phi);
+        __builtin_amdgcn_sched_barrier(0);
+        grad(1, false, gT);
+        __builtin_amdgcn_sched_barrier(0);
+        grad(2, true, gC);
+        __builtin_amdgcn_sched_barrier(0);
+        grad(3, true, gf);
+        __builtin_amdgcn_sched_barrier(0);
+        grad(4, true, gP);
+        __builtin_amdgcn_sched_barrier(0);
+        float g[19];
 #pragma unroll
         for (int i = 0; i < 19; ++i) g[i] = A.src[(PG + i) * N + n];
-        // stencils (isotropic D3Q19 gradient / Laplacian)
-        float gp[3] = {0, 0, 0}, gT[3] = {0, 0, 0}, gC[3] = {0, 0, 0}, gf[3] = {0, 0, 0},
-              gP[3] = {0, 0, 0};
-        float lap = 0.f;
-#pragma unroll
-        for (int i = 1; i < 19; ++i) {
-          const float vphi = nb(0, i, true), vT = nb(1, i, false), vC = nb(2, i, true);
-          const float vfs = nb(3, i, true), vp = nb(4, i, true);
-          const float w = W19[i] * kInvCs2;
-          const float cxyz[3] = {(float)CX[i], (float)CY[i], (float)CZ[i]};
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            gp[a] += w * cxyz[a] * vphi;
-            gT[a] += w * cxyz[a] * vT;
-            gC[a] += w * cxyz[a] * vC;
-            gf[a] += w * cxyz[a] * vfs;
-            gP[a] += w * cxyz[a] * vp;
-          }
-          lap += 2.0f * w * (vphi - phi);
-        }
         // forces, velocity, pressure (Sec. 3.2, Eq. Fs)
         float grho[3], F[3], nv[3], gsig[3];
         const float g2 = gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2];
@@ -389,9 +404,9 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
           bool bad = !isfinite(phi) || !isfinite(T) || !isfinite(pn) || !isfinite(uu);
 #pragma unroll
           for (int i = 0; i < 7; ++i) {
-            df += (double)f[i];
-            dh += (double)h[i];
-            dl += (double)l[i];
+            if (i) df += (double)A.src[(PF + i) * N + n];
+            dh += (double)A.src[(PH + i) * N + n];
+            if (i) dl += (double)A.src[(PL + i) * N + n];
           }
           bad = bad || !isfinite(df) || !isfinite(dh) || !isfinite(dl);
           tot[0] += df;
@@ -401,15 +416,9 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
           tot[4] += (double)clamp01(0.5f * (1.0f + phi));
           tot[5] += bad ? 1.0 : 0.0;
         } else {
-          // E and Q of the own node: the closure rebuilt from the same inputs
-          // (phi0, E0, div u) that the ring closure used
-          float phi0 = 0.f, E0 = 0.f;
-#pragma unroll
-          for (int i = 1; i < 7; ++i) phi0 += f[i];
-#pragma unroll
-          for (int i = 0; i < 7; ++i) E0 += h[i];
+          // div u, E and Q of the own node from its closure
           const float Dr = S.c[s0][5][cs];
-          const Closure cl = closure(P, phi0, E0, Dr);
+          const float clE = S.c[s0][6][cs], clQ = S.c[s0][7][cs];
           mpc_acc += (double)phi * (double)Dr;
           // Each post-collision population is computed and pushed along its
           // link at once.  Link kinds: 0 stream to m, 1 wall (bounce-back, or
@@ -435,7 +444,12 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
             else A.dst[(PG + i) * N + m] = post;
           }
           A.dst[(PG + 0) * N + n] = g[0] - (g[0] + geq_sum) * P.itau_g + P.wg * G0;
+          __builtin_amdgcn_sched_barrier(0);
           // phase field BGK (Sec. 3.1); the D3Q7 rest component is zero
+          float f[7];
+          f[0] = 0.f;
+#pragma unroll
+          for (int i = 1; i < 7; ++i) f[i] = A.src[(PF + i) * N + n];
           const float up0 = A.u_old[n], up1 = A.u_old[N + n], up2 = A.u_old[2 * N + n];
           const float phiP = A.phiP[n], CP = A.CP[n];
           {
@@ -455,18 +469,22 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
               else A.dst[(PF + i) * N + m] = post;
             }
           }
+          __builtin_amdgcn_sched_barrier(0);
           // enthalpy TRT (Sec. 3.3)
           {
+            float h[7];
+#pragma unroll
+            for (int i = 0; i < 7; ++i) h[i] = A.src[(PH + i) * N + n];
             float heq[7];
             const float rT = P.rhoc_ref * T, cT = rcp * T;
-            heq[0] = cl.E;
+            heq[0] = clE;
 #pragma unroll
             for (int i = 1; i < 7; ++i) {
               const float cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
               heq[i] = W7 * (rT + cT * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
               heq[0] -= heq[i];
             }
-            const float hq = W7 * cl.Q, hq0 = cl.Q - 6.0f * hq;
+            const float hq = W7 * clQ, hq0 = clQ - 6.0f * hq;
             const float Tw_lo = P.T_lo + P.T_lo_amp * cosf(P.kwall * (float)gx);
 #pragma unroll
             for (int i = 0; i < 7; ++i) {
@@ -487,8 +505,13 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
               }
             }
           }
+          __builtin_amdgcn_sched_barrier(0);
           // solute BGK (Sec. 3.4)
           {
+            float l[7];
+            l[0] = 0.f;
+#pragma unroll
+            for (int i = 1; i < 7; ++i) l[i] = A.src[(PL + i) * N + n];
             const float keff = 1.0f - fs * (1.0f - P.k_p);
             const float De = fs * P.k_p * P.Ds + (1.0f - fs) * P.Dl;
             const float itau_l = 1.0f / (De / (kCs2 * keff) + 0.5f), wl = 1.0f - 0.5f * itau_l;
