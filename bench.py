@@ -29,6 +29,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 POP_BYTES = {"f32": 4, "f16": 2, "bf16": 2}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2d_2048.json")
+# sources of the timed kernel: the stored counter figures hold only while
+# these are unchanged
+KERNEL_SOURCES = ("paper_2511_09422_amd/csrc/lbfz_2d.hip",
+                  "paper_2511_09422_amd/csrc/lbfz_common.hpp",
+                  "paper_2511_09422_amd/csrc/lbfz_kernels.hpp")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def bytes_per_node(storage: str) -> int:
@@ -64,7 +78,7 @@ def load_traffic(kernel_tag: str):
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_tag") != kernel_tag:
+    if d.get("kernel_tag") != kernel_tag or d.get("source_sha256") != kernel_source_hash():
         return None
     return d.get("bytes_per_launch")
 
