@@ -3,17 +3,24 @@
 // enthalpy h (TRT) and solute l.
 //
 // One kernel launch = one time step.  Populations live in two SoA buffers
-// (plane q of N floats each: f 0..4, g 5..13, h 14..18, l 19..23); a step
-// reads buffer A at each node's own location and pushes post-collision values
-// along their links into buffer B (half-way bounce-back / anti-bounce-back at
-// walls).  Each 64x4 tile stages in LDS
+// (plane q starts at q * ps floats: f 0..4, g 5..13, h 14..18, l 19..23); a
+// step reads buffer A at each node's own location and pushes post-collision
+// values along their links into buffer B (half-way bounce-back /
+// anti-bounce-back at walls).  Each 64 x TY tile (one row per wave) stages in
+// LDS
 //   - the previous velocity on the tile + 2 ring   (div u for the closure),
 //   - phi, T, C, f_s of the tile + 1 ring, computed from that ring's own
-//     populations (the pointwise closure, evaluated redundantly on the ring),
+//     populations (the pointwise closure, evaluated redundantly on the ring
+//     by the first ceil(ring / 64) waves only),
 //   - the previous pressure on the tile + 1 ring,
 // and then every thread owns one node: stencils, forces, velocity, pressure,
 // four collisions and the streaming writes.  Reads and writes each touch every
 // population once, so HBM traffic is the algorithmic 240 B per node update.
+//
+// The step is bound by vector-ALU issue as much as by HBM, so addressing is
+// kept off the vector units: plane bases and the tile row are wave-uniform
+// (scalar registers), a lane carries only a 32-bit byte offset into a plane,
+// and every load or store is one instruction.
 #include "lbfz_common.hpp"
 #include "lbfz_kernels.hpp"
 
@@ -25,6 +32,7 @@ namespace {
 #define LBFZ_TY 4
 #endif
 constexpr int TX = 64, TY = LBFZ_TY, NT = TX * TY;
+static_assert(TX == 64, "one tile row per wave64");
 constexpr int HX = TX + 2, HY = TY + 2;  // closure ring
 constexpr int UX = TX + 4, UY = TY + 4;  // velocity ring
 constexpr int RING = 2 * HX + 2 * TY;
@@ -40,54 +48,96 @@ constexpr float W9[9] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
                          1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
 constexpr float W5[5] = {1.f / 3, 1.f / 6, 1.f / 6, 1.f / 6, 1.f / 6};
 
-__device__ __forceinline__ int wrapc(int v, int n) {
-  return v < 0 ? v + n : (v >= n ? v - n : v);
+// Word 3 of a CDNA buffer descriptor: 32-bit data format, no swizzle.
+constexpr int kBufWord3 = 0x00020000;
+
+// Buffer descriptor of `bytes` bytes at `base`; accesses through it are one
+// buffer instruction each: descriptor and plane offset wave-uniform (scalar
+// registers), the lane supplies only a 32-bit byte offset.  Offsets outside
+// the range read 0 and write nothing.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t rsrc(const float* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)bytes,
+                                           kBufWord3);
+}
+__device__ __forceinline__ float ld(rsrc_t r, uint32_t off, uint32_t soff = 0) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
+}
+__device__ __forceinline__ void st(rsrc_t r, uint32_t off, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, (int)soff, 0);
 }
 
-// Map a wall-axis coordinate to the node whose value its slot holds.
-// side: 0 inside, -1 ghost below the low wall, +1 ghost above the high wall.
-__device__ __forceinline__ int map_axis(int g, int n, int walls, int& side) {
+// Descriptors of one step: population sets of the source and destination
+// buffers (plane i of a set at byte offset i * pb) and the time-level fields.
+struct Bufs {
+  rsrc_t f, g, h, l;          // source sets
+  rsrc_t df, dg, dh, dl;      // destination sets
+  rsrc_t p_old, u_old;        // u_old: x plane, then y plane
+  uint32_t pb;                // plane bytes
+};
+
+__device__ __forceinline__ Bufs make_bufs(const KParams& P, const StepArgs& A) {
+  Bufs B;
+  const long PS = P.ps;
+  B.pb = (uint32_t)PS * 4u;
+  B.f = rsrc(A.src + PF * PS, 5 * B.pb);
+  B.g = rsrc(A.src + PG * PS, 9 * B.pb);
+  B.h = rsrc(A.src + PH * PS, 5 * B.pb);
+  B.l = rsrc(A.src + PL * PS, 5 * B.pb);
+  B.df = rsrc(A.dst + PF * PS, 5 * B.pb);
+  B.dg = rsrc(A.dst + PG * PS, 9 * B.pb);
+  B.dh = rsrc(A.dst + PH * PS, 5 * B.pb);
+  B.dl = rsrc(A.dst + PL * PS, 5 * B.pb);
+  B.p_old = rsrc(A.p_old, B.pb);
+  B.u_old = rsrc(A.u_old, 2 * B.pb);
+  return B;
+}
+
+// Periodic image of v in [-n, 2n); positions beyond that (staged only by
+// partial tiles, never read for a node of the grid) are clamped into it.
+__device__ __forceinline__ int wrap_near(int v, int n) {
+  return v < 0 ? v + n : (v >= n ? min(v - n, n - 1) : v);
+}
+
+// Wall-normal (y) coordinate -> stored row.  side: 0 inside, -1 ghost below
+// the low wall, +1 ghost above the high wall; a ghost takes its mirror row.
+__device__ __forceinline__ int map_y(int g, int n, int walls, int& side) {
   side = 0;
-  if (walls) {
-    if (g < 0) {
-      side = -1;
-      g = -1 - g;
-    } else if (g >= n) {
-      side = 1;
-      g = 2 * n - 1 - g;
-    }
-    g = min(max(g, 0), n - 1);
-  } else {
-    g = ((g % n) + n) % n;
+  if (!walls) return wrap_near(g, n);
+  if (g < 0) {
+    side = -1;
+    g = -1 - g;
+  } else if (g >= n) {
+    side = 1;
+    g = 2 * n - 1 - g;
   }
-  return g;
+  return min(max(g, 0), n - 1);
 }
 
-__device__ __forceinline__ int map_periodic(int g, int n) { return ((g % n) + n) % n; }
+__device__ __forceinline__ uint32_t node_off(int mx, int my, int nx) {
+  return ((uint32_t)my * (uint32_t)nx + (uint32_t)mx) * 4u;
+}
 
 struct Slot {
   float phi, T, C, fs, p;
 };
 
-// Closure of the node staged in ring slot (lx, ly) (closure-ring coordinates).
-// Returns the slot values; pops of the source node are returned in f/h/l.
-__device__ __forceinline__ Slot eval_slot(const KParams& P, const float* __restrict__ src,
-                                          const float* __restrict__ p_old, int x0, int y0,
-                                          int lx, int ly, float (*s_ux)[UX],
+// Closure of the node (mx, my) staged in closure-ring slot (lx, ly): its 15
+// f/h/l populations (returned), div u^{n-1} from the velocity ring and
+// p^{n-1}.  A ghost slot (side != 0) holds the mirror node with the wall's
+// temperature transform.
+__device__ __forceinline__ Slot eval_slot(const KParams& P, const Bufs& B, int y0, int mx,
+                                          int my, int side, int lx, int ly, float (*s_ux)[UX],
                                           float (*s_uy)[UX], float* f, float* h, float* l,
                                           float& Dout, Closure& cout) {
-  const int nx = P.nx, ny = P.ny;
-  const long N = P.N;
-  const int mx = map_periodic(x0 + lx - 1, nx);
-  int side;
-  const int my = map_axis(y0 + ly - 1, ny, P.walls, side);
-  const int n = my * nx + mx;
+  const uint32_t o = node_off(mx, my, P.nx);
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    f[i] = src[(PF + i) * N + n];
-    h[i] = src[(PH + i) * N + n];
-    l[i] = src[(PL + i) * N + n];
+    f[i] = ld(B.f, o, i * B.pb);
+    h[i] = ld(B.h, o, i * B.pb);
+    l[i] = ld(B.l, o, i * B.pb);
   }
+  const float p = ld(B.p_old, o);
   float phi0 = 0.f, E0 = 0.f, C = 0.f;
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
@@ -114,7 +164,7 @@ __device__ __forceinline__ Slot eval_slot(const KParams& P, const float* __restr
   s.phi = c.phi;
   s.C = C;
   s.fs = c.fs;
-  s.p = p_old[n];
+  s.p = p;
   float T = c.T;
   if (side < 0 && P.tlo_dir) T = 2.0f * (P.T_lo + P.T_lo_amp * cosf(P.kwall * (float)mx)) - T;
   if (side > 0 && P.thi_dir) T = 2.0f * P.T_hi - T;
@@ -137,30 +187,37 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
   const int tile = xcd_tile(blockIdx.x, P.nblk);
   const int bx = tile % P.nblk_x, by = tile / P.nblk_x;
   const int x0 = bx * TX, y0 = by * TY;
-  const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+  const int tid = threadIdx.x, tx = tid & (TX - 1);
+  const int ty = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform row
   const int nx = P.nx, ny = P.ny;
-  const long N = P.N;
-  const float* __restrict__ src = A.src;
+  const long PS = P.ps;
+  const Bufs B = make_bufs(P, A);
+  const uint32_t PB = B.pb, NB = (uint32_t)P.N * 4u;  // plane / output bytes
   const int gx = x0 + tx, gy = y0 + ty;
   const bool valid = gx < nx && gy < ny;
-  const int n = valid ? gy * nx + gx : 0;
+  // own slot; lanes of a partial tile outside the grid stage the periodic
+  // image or wall mirror that the ring of the last nodes of the grid needs
+  int oside;
+  const int omx = wrap_near(gx, nx);
+  const int omy = map_y(gy, ny, P.walls, oside);
+  const uint32_t on = node_off(omx, omy, nx);
   // own-node loads that do not depend on the LDS phases are issued first
   float g[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = src[(PG + i) * N + n];
-  const float fs_prev = A.fs[n];
-  const float phiP = A.phiP[n], CP = A.CP[n];
+  for (int i = 0; i < 9; ++i) g[i] = ld(B.g, on, i * PB);
+  const rsrc_t r_fs = rsrc(A.fs, PB), r_phiP = rsrc(A.phiP, PB), r_CP = rsrc(A.CP, PB);
+  const float fs_prev = ld(r_fs, on);
+  const float phiP = ld(r_phiP, on), CP = ld(r_CP, on);
 
   // 1. previous velocity on tile + 2 ring; no-slip ghosts are negated mirrors
   for (int s = tid; s < UX * UY; s += NT) {
     const int lx = s % UX, ly = s / UX;
-    const int gx = map_periodic(x0 + lx - 2, nx);
     int side;
-    const int gy = map_axis(y0 + ly - 2, ny, P.walls, side);
-    const int n = gy * nx + gx;
+    const int my = map_y(y0 + ly - 2, ny, P.walls, side);
+    const uint32_t o = node_off(wrap_near(x0 + lx - 2, nx), my, nx);
     const float sg = side ? -1.0f : 1.0f;
-    s_ux[ly][lx] = sg * A.u_old[n];
-    s_uy[ly][lx] = sg * A.u_old[N + n];
+    s_ux[ly][lx] = sg * ld(B.u_old, o);
+    s_uy[ly][lx] = sg * ld(B.u_old, o, PB);
   }
   __syncthreads();
 
@@ -168,7 +225,7 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
   float f[5], h[5], l[5], D;
   Closure cl;
   {
-    const Slot s = eval_slot(P, src, A.p_old, x0, y0, tx + 1, ty + 1, s_ux, s_uy, f, h, l, D,
+    const Slot s = eval_slot(P, B, y0, omx, omy, oside, tx + 1, ty + 1, s_ux, s_uy, f, h, l, D,
                              cl);
     s_phi[ty + 1][tx + 1] = s.phi;
     s_T[ty + 1][tx + 1] = s.T;
@@ -176,28 +233,29 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
     s_fs[ty + 1][tx + 1] = s.fs;
     s_p[ty + 1][tx + 1] = s.p;
   }
-  // ring slots are dealt to the waves in turn (slot r -> lane r / NW of wave
-  // r % NW) so that every wave carries an equal share of the extra closures
-  constexpr int NW = NT / 64;
-  const int rslot = (tid & 63) * NW + (tid >> 6);
-  if (rslot < RING) {
+  // ring slots go to the first threads, so only ceil(RING / 64) waves run the
+  // extra closure
+  if (tid < RING) {
     int lx, ly;
-    if (rslot < HX) {
-      lx = rslot;
+    if (tid < HX) {
+      lx = tid;
       ly = 0;
-    } else if (rslot < 2 * HX) {
-      lx = rslot - HX;
+    } else if (tid < 2 * HX) {
+      lx = tid - HX;
       ly = HY - 1;
-    } else if (rslot < 2 * HX + TY) {
+    } else if (tid < 2 * HX + TY) {
       lx = 0;
-      ly = rslot - 2 * HX + 1;
+      ly = tid - 2 * HX + 1;
     } else {
       lx = HX - 1;
-      ly = rslot - 2 * HX - TY + 1;
+      ly = tid - 2 * HX - TY + 1;
     }
+    int side;
+    const int my = map_y(y0 + ly - 1, ny, P.walls, side);
+    const int mx = wrap_near(x0 + lx - 1, nx);
     float f2[5], h2[5], l2[5], D2;
     Closure c2;
-    const Slot s = eval_slot(P, src, A.p_old, x0, y0, lx, ly, s_ux, s_uy, f2, h2, l2, D2, c2);
+    const Slot s = eval_slot(P, B, y0, mx, my, side, lx, ly, s_ux, s_uy, f2, h2, l2, D2, c2);
     s_phi[ly][lx] = s.phi;
     s_T[ly][lx] = s.T;
     s_C[ly][lx] = s.C;
@@ -235,8 +293,8 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
   const float grx = 0.5f * (P.rho_l - P.rho_g) * gpx + (P.rho_s - P.rho_l) * gfx;
   const float gry = 0.5f * (P.rho_l - P.rho_g) * gpy + (P.rho_s - P.rho_l) * gfy;
   const float g2 = gpx * gpx + gpy * gpy;
-  const float ng = sqrtf(g2);
-  const float inv_ng = 1.0f / fmaxf(ng, 1e-6f);  // n regularised in the bulk
+  // 1 / max(|grad phi|, 1e-6): n regularised in the bulk
+  const float inv_ng = __builtin_amdgcn_rsqf(fmaxf(g2, 1e-12f));
   const float nvx = gpx * inv_ng, nvy = gpy * inv_ng;
   const float mu = phi * (phi * phi - 1.0f) * P.ieps2 - lap;
   const float sig = P.sigma0 + P.sigma_T * (T - P.T_ref) + P.sigma_c * (C - P.c_ref);
@@ -251,7 +309,7 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
   const float rcp = rho * interp(phi, fs, P.cp_l, P.cp_g, P.cp_s);
   const float momx = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
   const float momy = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
-  const float irho = 1.0f / rho;
+  const float irho = frcp(rho);
   const float usx = (momx + 0.5f * Fx) * irho, usy = (momy + 0.5f * Fy) * irho;
   const float fdx = -fs * usx, fdy = -fs * usy;
   const float ux = usx + 0.5f * fdx, uy = usy + 0.5f * fdy;
@@ -284,15 +342,15 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
   if (DRY) {
     if (valid) {
       float* const* o = A.out;
-      if (o[0]) o[0][n] = phi;
-      if (o[1]) o[1][n] = 1.0f - fs;
-      if (o[2]) o[2][n] = T;
-      if (o[3]) o[3][n] = C;
-      if (o[4]) o[4][n] = ux;
-      if (o[5]) o[5][n] = uy;
-      if (o[6]) o[6][n] = 0.0f;
-      if (o[7]) o[7][n] = pn;
-      if (o[8]) o[8][n] = rho;
+      if (o[0]) st(rsrc(o[0], NB), on, 0, phi);
+      if (o[1]) st(rsrc(o[1], NB), on, 0, 1.0f - fs);
+      if (o[2]) st(rsrc(o[2], NB), on, 0, T);
+      if (o[3]) st(rsrc(o[3], NB), on, 0, C);
+      if (o[4]) st(rsrc(o[4], NB), on, 0, ux);
+      if (o[5]) st(rsrc(o[5], NB), on, 0, uy);
+      if (o[6]) st(rsrc(o[6], NB), on, 0, 0.0f);
+      if (o[7]) st(rsrc(o[7], NB), on, 0, pn);
+      if (o[8]) st(rsrc(o[8], NB), on, 0, rho);
     }
     if (A.tot_part) {
       double vals[6] = {0, 0, 0, 0, 0, 0};
@@ -336,19 +394,20 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
   // soon as it is computed (no arrays of post-collision values stay live).
   // A link across a wall is closed by half-way bounce-back into the opposite
   // slot of the same node; h at a Dirichlet wall by anti-bounce-back.
-  float* __restrict__ dst = A.dst;
-  auto target = [&](int i, int& m) -> bool {  // true: the link leaves through a wall
-    const int ty2 = gy + CY[i];
-    if (P.walls && (ty2 < 0 || ty2 >= ny)) return true;
-    m = wrapc(ty2, ny) * nx + wrapc(gx + CX[i], nx);
-    return false;
-  };
-  auto push = [&](int base, int i, float v) {
-    int m = n;
-    if (target(i, m))
-      dst[(base + OPP[i]) * N + n] = v;
+  // Link targets: x periodic; y periodic, or closed by the walls.  Row
+  // offsets are wave-uniform, column offsets per lane.
+  const bool wlo = P.walls && gy == 0, whi = P.walls && gy == ny - 1;
+  const int rm = gy == 0 ? ny - 1 : gy - 1, rp = gy == ny - 1 ? 0 : gy + 1;
+  const uint32_t rowb[3] = {(uint32_t)rm * (uint32_t)nx * 4u, (uint32_t)gy * (uint32_t)nx * 4u,
+                            (uint32_t)rp * (uint32_t)nx * 4u};
+  const uint32_t colb[3] = {(uint32_t)(omx == 0 ? nx - 1 : omx - 1) * 4u, (uint32_t)omx * 4u,
+                            (uint32_t)(omx == nx - 1 ? 0 : omx + 1) * 4u};
+  auto walled = [&](int i) { return (CY[i] < 0 && wlo) || (CY[i] > 0 && whi); };
+  auto push = [&](rsrc_t set, int i, float v) {
+    if (walled(i))
+      st(set, on, OPP[i] * PB, v);  // half-way bounce-back
     else
-      dst[(base + i) * N + m] = v;
+      st(set, rowb[CY[i] + 1] + colb[CX[i] + 1], i * PB, v);
   };
   // flow BGK (Sec. 3.2)
   if (valid) {
@@ -359,9 +418,9 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
       const float si = W9[i] * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
       const float geq = pn * kInvCs2 * W9[i] + rho * si;
       geq_sum += geq;
-      push(PG, i, g[i] - (g[i] - geq) * P.itau_g + P.wg * G[i]);
+      push(B.dg, i, g[i] - (g[i] - geq) * P.itau_g + P.wg * G[i]);
     }
-    dst[(PG + 0) * N + n] = g[0] - (g[0] + geq_sum) * P.itau_g + P.wg * G[0];
+    st(B.dg, on, 0, g[0] - (g[0] + geq_sum) * P.itau_g + P.wg * G[0]);
   }
   // phase field BGK (Sec. 3.1)
   const float upx = s_ux[ty + 2][tx + 2], upy = s_uy[ty + 2][tx + 2];
@@ -377,10 +436,10 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
       const float feq = W5[i] * phi * (1.0f + kInvCs2 * cu);
       feq_sum += feq;
       F_sum += Fi;
-      push(PF, i, f[i] - (f[i] - feq) * P.itau_f + P.wf * Fi);
+      push(B.df, i, f[i] - (f[i] - feq) * P.itau_f + P.wf * Fi);
     }
-    dst[(PF + 0) * N + n] =
-        f[0] - (f[0] - (phi - feq_sum)) * P.itau_f + P.wf * (phi * D - F_sum);
+    st(B.df, on, 0,
+       f[0] - (f[0] - (phi - feq_sum)) * P.itau_f + P.wf * (phi * D - F_sum));
   }
   // enthalpy TRT (Sec. 3.3); E and Q from the closure of the own node
   if (valid) {
@@ -394,7 +453,6 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
       heq[0] -= heq[i];
     }
     const float hq = W5[1] * cl.Q, hq0 = cl.Q - 4.0f * hq;
-    const float Tw_lo = P.T_lo + P.T_lo_amp * cosf(P.kwall * (float)gx);
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       const int o = OPP[i];
@@ -402,15 +460,17 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
       const float es = 0.5f * (heq[i] + heq[o]), ea = 0.5f * (heq[i] - heq[o]);
       const float v = h[i] - (hs - es) * P.itau_s - (ha - ea) * P.itau_a +
                       P.ws * (i == 0 ? hq0 : hq);
-      int m = n;
-      if (target(i, m)) {
-        const int ty2 = gy + CY[i];
+      if (i == 0) {
+        st(B.dh, on, 0, v);
+      } else if (walled(i)) {
         float hv = v;
-        if (ty2 < 0 && P.tlo_dir) hv = -hv + 2.0f * W5[o] * P.rhoc_ref * Tw_lo;
-        if (ty2 >= ny && P.thi_dir) hv = -hv + 2.0f * W5[o] * P.rhoc_ref * P.T_hi;
-        dst[(PH + o) * N + n] = hv;
+        if (CY[i] < 0 && P.tlo_dir)
+          hv = -hv + 2.0f * W5[o] * P.rhoc_ref *
+                         (P.T_lo + P.T_lo_amp * cosf(P.kwall * (float)gx));
+        if (CY[i] > 0 && P.thi_dir) hv = -hv + 2.0f * W5[o] * P.rhoc_ref * P.T_hi;
+        st(B.dh, on, o * PB, hv);
       } else {
-        dst[(PH + i) * N + m] = v;
+        st(B.dh, rowb[CY[i] + 1] + colb[CX[i] + 1], i * PB, v);
       }
     }
   }
@@ -418,9 +478,10 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
   if (valid) {
     const float keff = 1.0f - fs * (1.0f - P.k_p);
     const float De = fs * P.k_p * P.Ds + (1.0f - fs) * P.Dl;
-    const float tau_l = De / (kCs2 * keff) + 0.5f;
-    const float itau_l = 1.0f / tau_l, wl = 1.0f - 0.5f * itau_l;
-    const float cr = (1.0f - phi) * C * P.isq, ck = (P.k_p - 1.0f) * C / keff;
+    const float ikeff = frcp(keff);
+    const float tau_l = 3.0f * De * ikeff + 0.5f;  // D_e / (cs2 k_eff) + 1/2
+    const float itau_l = frcp(tau_l), wl = 1.0f - 0.5f * itau_l;
+    const float cr = (1.0f - phi) * C * P.isq, ck = (P.k_p - 1.0f) * C * ikeff;
     const float Lx = (C * ux - CP * upx) + kCs2 * (cr * nvx + ck * gfx);
     const float Ly = (C * uy - CP * upy) + kCs2 * (cr * nvy + ck * gfy);
     float leq_sum = 0.0f;
@@ -430,19 +491,20 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
       const float Li = W5[i] * kInvCs2 * (CX[i] * Lx + CY[i] * Ly);
       const float leq = W5[i] * C * (1.0f + kInvCs2 * cu);
       leq_sum += leq;
-      push(PL, i, l[i] - (l[i] - leq) * itau_l + wl * Li);
+      push(B.dl, i, l[i] - (l[i] - leq) * itau_l + wl * Li);
     }
-    dst[(PL + 0) * N + n] = l[0] - (l[0] - (C - leq_sum)) * itau_l;
+    st(B.dl, on, 0, l[0] - (l[0] - (C - leq_sum)) * itau_l);
   }
 
   // 6. the time-level state
   if (valid) {
-    A.p_new[n] = pn;
-    A.u_new[n] = ux;
-    A.u_new[N + n] = uy;
-    A.fs[n] = fs;
-    A.phiP[n] = phi;
-    A.CP[n] = C;
+    st(rsrc(A.p_new, PB), on, 0, pn);
+    const rsrc_t r_un = rsrc(A.u_new, 2 * PB);
+    st(r_un, on, 0, ux);
+    st(r_un, on, PB, uy);
+    st(r_fs, on, 0, fs);
+    st(r_phiP, on, 0, phi);
+    st(r_CP, on, 0, C);
   }
   // phase-field source budget: sum of phi div u over the tile, FP64
   const double s = block_sum<NT>(valid ? (double)phi * (double)D : 0.0, s_red);
@@ -453,7 +515,7 @@ __global__ __launch_bounds__(256) void k_init2d(KParams P, const double* __restr
                                                 const double* __restrict__ T_in,
                                                 const double* __restrict__ C_in,
                                                 float* __restrict__ pop, StateArgs S) {
-  const long N = P.N;
+  const long N = P.N, PS = P.ps;
   for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < N;
        n += (long)gridDim.x * blockDim.x) {
     const float phi = (float)phi_in[n], T = (float)T_in[n], C = (float)C_in[n];
@@ -463,22 +525,22 @@ __global__ __launch_bounds__(256) void k_init2d(KParams P, const double* __restr
     float h0 = E, f0 = phi, l0 = C;
 #pragma unroll
     for (int i = 1; i < 5; ++i) {
-      pop[(PH + i) * N + n] = W5[i] * P.rhoc_ref * T;
-      pop[(PF + i) * N + n] = W5[i] * phi;
-      pop[(PL + i) * N + n] = W5[i] * C;
+      pop[(PH + i) * PS + n] = W5[i] * P.rhoc_ref * T;
+      pop[(PF + i) * PS + n] = W5[i] * phi;
+      pop[(PL + i) * PS + n] = W5[i] * C;
       h0 -= W5[i] * P.rhoc_ref * T;
       f0 -= W5[i] * phi;
       l0 -= W5[i] * C;
     }
-    pop[(PH + 0) * N + n] = h0;
-    pop[(PF + 0) * N + n] = f0;
-    pop[(PL + 0) * N + n] = l0;
+    pop[(PH + 0) * PS + n] = h0;
+    pop[(PF + 0) * PS + n] = f0;
+    pop[(PL + 0) * PS + n] = l0;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) pop[(PG + i) * N + n] = 0.0f;
+    for (int i = 0; i < 9; ++i) pop[(PG + i) * PS + n] = 0.0f;
     S.pA[n] = 0.f;
     S.pB[n] = 0.f;
-    S.uA[n] = S.uA[N + n] = 0.f;
-    S.uB[n] = S.uB[N + n] = 0.f;
+    S.uA[n] = S.uA[PS + n] = 0.f;
+    S.uB[n] = S.uB[PS + n] = 0.f;
     S.fs[n] = 0.f;
     S.phiP[n] = 0.f;
     S.CP[n] = 0.f;

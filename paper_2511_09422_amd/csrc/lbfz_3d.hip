@@ -70,7 +70,7 @@ __device__ __forceinline__ int map_plane(const KParams& P, int k, int& ghost) {
 // Stage velocity plane k (tile + 2 ring) and its mask into slot k % 3.
 __device__ __forceinline__ void load_u_plane(const KParams& P, const StepArgs& A, LDS3& S, int x0,
                                              int y0, int k) {
-  const long N = P.N;
+  const long N = P.N, PS = P.ps;
   int ghost;
   const int kz = map_plane(P, k, ghost);
   const int slot = wrapm(k, 3);
@@ -82,8 +82,8 @@ __device__ __forceinline__ void load_u_plane(const KParams& P, const StepArgs& A
     const uint8_t m = A.mask ? A.mask[n] : (uint8_t)0;
     S.mk[slot][s] = ghost ? (uint8_t)0 : m;
     S.u[slot][0][s] = sg * A.u_old[n];
-    S.u[slot][1][s] = sg * A.u_old[N + n];
-    S.u[slot][2][s] = sg * A.u_old[2 * N + n];
+    S.u[slot][1][s] = sg * A.u_old[PS + n];
+    S.u[slot][2][s] = sg * A.u_old[2 * PS + n];
   }
 }
 
@@ -91,7 +91,7 @@ __device__ __forceinline__ void load_u_plane(const KParams& P, const StepArgs& A
 // wall copy the adjacent plane (already closed) with the wall rule for T.
 __device__ __forceinline__ void close_plane(const KParams& P, const StepArgs& A, LDS3& S, int x0,
                                             int y0, int k) {
-  const long N = P.N;
+  const long N = P.N, PS = P.ps;
   const int slot = wrapm(k, 3);
   int ghost;
   const int kz = map_plane(P, k, ghost);
@@ -119,11 +119,11 @@ __device__ __forceinline__ void close_plane(const KParams& P, const StepArgs& A,
     float phi0 = 0.f, E0 = 0.f, C = 0.f;
 #pragma unroll
     for (int i = 1; i < 7; ++i) {
-      phi0 += A.src[(PF + i) * N + n];
-      C += A.src[(PL + i) * N + n];
+      phi0 += A.src[(PF + i) * PS + n];
+      C += A.src[(PL + i) * PS + n];
     }
 #pragma unroll
-    for (int i = 0; i < 7; ++i) E0 += A.src[(PH + i) * N + n];
+    for (int i = 0; i < 7; ++i) E0 += A.src[(PH + i) * PS + n];
     S.cm[slot][s] = S.mk[u0][us];
     if (S.mk[u0][us]) {
       float T, fs;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
   const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
   const int gx = x0 + tx, gy = y0 + ty;
   const bool inxy = gx < P.nx && gy < P.ny;
-  const long N = P.N;
+  const long N = P.N, PS = P.ps;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
 
   // prologue: closure planes z0-1 and z0 (velocity planes z0-2 .. z0+1)
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
         // obstacle: enthalpy at rest without source (pure conduction)
         float h[7];
 #pragma unroll
-        for (int i = 0; i < 7; ++i) h[i] = A.src[(PH + i) * N + n];
+        for (int i = 0; i < 7; ++i) h[i] = A.src[(PH + i) * PS + n];
         const float E = S.c[s0][6][cs];
         float heq[7];
         heq[0] = E;
@@ -279,15 +279,15 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
               if (tz < 0 && P.tlo_dir)
                 hv = -hv + 2.0f * W7 * P.rhoc_ref * (P.T_lo + P.T_lo_amp * cosf(P.kwall * (float)gx));
               if (tz >= nz && P.thi_dir) hv = -hv + 2.0f * W7 * P.rhoc_ref * P.T_hi;
-              A.dst[(PH + o) * N + n] = hv;
+              A.dst[(PH + o) * PS + n] = hv;
             } else {
               const long m = ((long)wrapc(tz, nz) * ny + wrapc(gy + CY[i], ny)) * nx +
                              wrapc(gx + CX[i], nx);
-              A.dst[(PH + i) * N + m] = hp;
+              A.dst[(PH + i) * PS + m] = hp;
             }
           }
           A.p_new[n] = 0.f;
-          A.u_new[n] = A.u_new[N + n] = A.u_new[2 * N + n] = 0.f;
+          A.u_new[n] = A.u_new[PS + n] = A.u_new[2 * PS + n] = 0.f;
           A.fs[n] = 0.f;
           A.phiP[n] = -1.f;
           A.CP[n] = 0.f;
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
         __builtin_amdgcn_sched_barrier(0);
         float g[19];
 #pragma unroll
-        for (int i = 0; i < 19; ++i) g[i] = A.src[(PG + i) * N + n];
+        for (int i = 0; i < 19; ++i) g[i] = A.src[(PG + i) * PS + n];
         // forces, velocity, pressure (Sec. 3.2, Eq. Fs)
         float grho[3], F[3], nv[3], gsig[3];
         const float g2 = gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2];
@@ -404,9 +404,9 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
           bool bad = !isfinite(phi) || !isfinite(T) || !isfinite(pn) || !isfinite(uu);
 #pragma unroll
           for (int i = 0; i < 7; ++i) {
-            if (i) df += (double)A.src[(PF + i) * N + n];
-            dh += (double)A.src[(PH + i) * N + n];
-            if (i) dl += (double)A.src[(PL + i) * N + n];
+            if (i) df += (double)A.src[(PF + i) * PS + n];
+            dh += (double)A.src[(PH + i) * PS + n];
+            if (i) dl += (double)A.src[(PL + i) * PS + n];
           }
           bad = bad || !isfinite(df) || !isfinite(dh) || !isfinite(dl);
           tot[0] += df;
@@ -440,17 +440,17 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
             geq_sum += geq;
             const float post = g[i] - (g[i] - geq) * P.itau_g + P.wg * Gi(i);
             long m = n;
-            if (link(i, m)) A.dst[(PG + OPP[i]) * N + n] = post;
-            else A.dst[(PG + i) * N + m] = post;
+            if (link(i, m)) A.dst[(PG + OPP[i]) * PS + n] = post;
+            else A.dst[(PG + i) * PS + m] = post;
           }
-          A.dst[(PG + 0) * N + n] = g[0] - (g[0] + geq_sum) * P.itau_g + P.wg * G0;
+          A.dst[(PG + 0) * PS + n] = g[0] - (g[0] + geq_sum) * P.itau_g + P.wg * G0;
           __builtin_amdgcn_sched_barrier(0);
           // phase field BGK (Sec. 3.1); the D3Q7 rest component is zero
           float f[7];
           f[0] = 0.f;
 #pragma unroll
-          for (int i = 1; i < 7; ++i) f[i] = A.src[(PF + i) * N + n];
-          const float up0 = A.u_old[n], up1 = A.u_old[N + n], up2 = A.u_old[2 * N + n];
+          for (int i = 1; i < 7; ++i) f[i] = A.src[(PF + i) * PS + n];
+          const float up0 = A.u_old[n], up1 = A.u_old[PS + n], up2 = A.u_old[2 * PS + n];
           const float phiP = A.phiP[n], CP = A.CP[n];
           {
             const float cf = kCs2 * (1.0f - phi * phi) * P.isq;
@@ -465,8 +465,8 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
               const float feq = W7 * phi * (1.0f + kInvCs2 * cu);
               const float post = f[i] - (f[i] - feq) * P.itau_f + P.wf * Fi;
               long m = n;
-              if (link(i, m)) A.dst[(PF + OPP[i]) * N + n] = post;
-              else A.dst[(PF + i) * N + m] = post;
+              if (link(i, m)) A.dst[(PF + OPP[i]) * PS + n] = post;
+              else A.dst[(PF + i) * PS + m] = post;
             }
           }
           __builtin_amdgcn_sched_barrier(0);
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
           {
             float h[7];
 #pragma unroll
-            for (int i = 0; i < 7; ++i) h[i] = A.src[(PH + i) * N + n];
+            for (int i = 0; i < 7; ++i) h[i] = A.src[(PH + i) * PS + n];
             float heq[7];
             const float rT = P.rhoc_ref * T, cT = rcp * T;
             heq[0] = clE;
@@ -499,9 +499,9 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
                 const int tz = k + CZ[i];
                 if (tz < 0 && P.tlo_dir) hv = -hv + 2.0f * W7 * P.rhoc_ref * Tw_lo;
                 if (tz >= nz && P.thi_dir) hv = -hv + 2.0f * W7 * P.rhoc_ref * P.T_hi;
-                A.dst[(PH + o) * N + n] = hv;
+                A.dst[(PH + o) * PS + n] = hv;
               } else {
-                A.dst[(PH + i) * N + m] = post;
+                A.dst[(PH + i) * PS + m] = post;
               }
             }
           }
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
             float l[7];
             l[0] = 0.f;
 #pragma unroll
-            for (int i = 1; i < 7; ++i) l[i] = A.src[(PL + i) * N + n];
+            for (int i = 1; i < 7; ++i) l[i] = A.src[(PL + i) * PS + n];
             const float keff = 1.0f - fs * (1.0f - P.k_p);
             const float De = fs * P.k_p * P.Ds + (1.0f - fs) * P.Dl;
             const float itau_l = 1.0f / (De / (kCs2 * keff) + 0.5f), wl = 1.0f - 0.5f * itau_l;
@@ -526,14 +526,14 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
               const float leq = W7 * C * (1.0f + kInvCs2 * cu);
               const float post = l[i] - (l[i] - leq) * itau_l + wl * W7 * kInvCs2 * cL;
               long m = n;
-              if (link(i, m)) A.dst[(PL + OPP[i]) * N + n] = post;
-              else A.dst[(PL + i) * N + m] = post;
+              if (link(i, m)) A.dst[(PL + OPP[i]) * PS + n] = post;
+              else A.dst[(PL + i) * PS + m] = post;
             }
           }
           A.p_new[n] = pn;
           A.u_new[n] = u[0];
-          A.u_new[N + n] = u[1];
-          A.u_new[2 * N + n] = u[2];
+          A.u_new[PS + n] = u[1];
+          A.u_new[2 * PS + n] = u[2];
           A.fs[n] = fs;
           A.phiP[n] = phi;
           A.CP[n] = C;
@@ -562,7 +562,7 @@ __global__ __launch_bounds__(256) void k_init3d(KParams P, const double* __restr
                                                 const uint8_t* __restrict__ mask,
                                                 float* __restrict__ popA,
                                                 float* __restrict__ popB, StateArgs S) {
-  const long N = P.N;
+  const long N = P.N, PS = P.ps;
   for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < N;
        n += (long)gridDim.x * blockDim.x) {
     const bool ob = mask && mask[n];
@@ -574,22 +574,22 @@ __global__ __launch_bounds__(256) void k_init3d(KParams P, const double* __restr
     float h0 = E;
 #pragma unroll
     for (int i = 1; i < 7; ++i) {
-      popA[(PH + i) * N + n] = W7 * P.rhoc_ref * T;
-      popA[(PF + i) * N + n] = ob ? 0.0f : W7 * phi;
-      popA[(PL + i) * N + n] = ob ? 0.0f : W7 * C;
+      popA[(PH + i) * PS + n] = W7 * P.rhoc_ref * T;
+      popA[(PF + i) * PS + n] = ob ? 0.0f : W7 * phi;
+      popA[(PL + i) * PS + n] = ob ? 0.0f : W7 * C;
       h0 -= W7 * P.rhoc_ref * T;
     }
-    popA[(PH + 0) * N + n] = h0;
-    popA[(PF + 0) * N + n] = 0.0f;
-    popA[(PL + 0) * N + n] = 0.0f;
+    popA[(PH + 0) * PS + n] = h0;
+    popA[(PF + 0) * PS + n] = 0.0f;
+    popA[(PL + 0) * PS + n] = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) popA[(PG + i) * N + n] = 0.0f;
+    for (int i = 0; i < 19; ++i) popA[(PG + i) * PS + n] = 0.0f;
     // the other buffer: obstacle and rest slots are never written by a step
 #pragma unroll
-    for (int q = 0; q < 40; ++q) popB[q * N + n] = 0.0f;
+    for (int q = 0; q < 40; ++q) popB[q * PS + n] = 0.0f;
     S.pA[n] = S.pB[n] = 0.f;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) S.uA[a * N + n] = S.uB[a * N + n] = 0.f;
+    for (int a = 0; a < 3; ++a) S.uA[a * PS + n] = S.uB[a * PS + n] = 0.f;
     S.fs[n] = 0.f;
     S.phiP[n] = 0.f;
     S.CP[n] = 0.f;

@@ -45,6 +45,12 @@ struct Layout {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+#ifndef LBFZ_PLANE_PAD
+#define LBFZ_PLANE_PAD 1088
+#endif
+// Elements between consecutive planes of a population or velocity array.
+size_t plane_stride(size_t N) { return ((N + 63) / 64) * 64 + LBFZ_PLANE_PAD; }
+
 bool valid_params(const lbfz_params* p) {
   if (!p) return false;
   if (p->dim != 2 && p->dim != 3) return false;
@@ -79,11 +85,12 @@ int tiles_of(const lbfz_params* p, int* nbx, int* nby, int* nbz) {
 
 Layout layout(const lbfz_params* p, int ntiles, int npop) {
   const size_t N = (size_t)p->nx * p->ny * p->nz;
+  const size_t ps = plane_stride(N);
   Layout L;
-  L.pop = align256(N * npop * sizeof(float));
-  L.p = align256(N * sizeof(float));
-  L.u = align256(N * p->dim * sizeof(float));
-  L.scal = align256(N * sizeof(float));
+  L.pop = align256(ps * npop * sizeof(float));
+  L.p = align256(ps * sizeof(float));
+  L.u = align256(ps * p->dim * sizeof(float));
+  L.scal = align256(ps * sizeof(float));
   L.mpc = align256((size_t)ntiles * sizeof(double));
   L.tot = align256((size_t)ntiles * 8 * sizeof(double));
   L.red = 256;
@@ -100,6 +107,7 @@ KParams make_kparams(const lbfz_params* p, int nbx, int nby, int nbz) {
   k.ny = p->ny;
   k.nz = p->nz;
   k.N = p->nx * p->ny * p->nz;
+  k.ps = (int)plane_stride((size_t)k.N);
   k.walls = p->walls;
   k.tlo_dir = p->t_lo_dirichlet;
   k.thi_dir = p->t_hi_dirichlet;
@@ -369,13 +377,13 @@ int lbfz_totals(lbfz_handle* h, lbfz_totals_t* out) {
 namespace {
 // Device planes of the exported state, in the documented order.
 int state_planes(lbfz_handle* h, std::vector<float*>& planes) {
-  const size_t N = (size_t)h->kp.N;
+  const size_t ps = (size_t)h->kp.ps;
   planes.clear();
   float* pop = h->pop[h->cur];
-  for (int q = 0; q < h->npop; ++q) planes.push_back(pop + q * N);
+  for (int q = 0; q < h->npop; ++q) planes.push_back(pop + q * ps);
   planes.push_back(h->fs);
   planes.push_back(h->p[h->cur]);
-  for (int a = 0; a < h->prm.dim; ++a) planes.push_back(h->u[h->cur] + a * N);
+  for (int a = 0; a < h->prm.dim; ++a) planes.push_back(h->u[h->cur] + a * ps);
   planes.push_back(h->phiP);
   planes.push_back(h->CP);
   return (int)planes.size();

@@ -15,6 +15,7 @@ constexpr float kInvCs2 = 3.0f;
 // host from lbfz_params and passed by value.
 struct KParams {
   int nx, ny, nz, N;
+  int ps;  // stride between the planes of one array (elements), >= N
   int walls, tlo_dir, thi_dir, st_mode;
   int nblk_x, nblk_y, nblk_z, nblk;  // tile grid (logical)
   // property end members (end of Sec. 2)
@@ -42,27 +43,27 @@ __device__ __forceinline__ float interp(float phi, float fs, float zl, float zg,
   return 0.5f * phi * (zl - zg) + fs * (zs - zl) + 0.5f * (zl + zg);
 }
 
+// Reciprocal by the hardware instruction (about 1 ulp); the scheme's
+// denominators are all O(0.1 .. 10), far from the denormal and overflow range.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Enthalpy -> (T, f_s) map of Eq. (Hfl) with the heat capacities and the
 // latent heat weighted by the phase-change-material fraction psi; f_s =
-// psi (1 - f_l).  At psi = 1 this is Eq. (Hfl).
+// psi (1 - f_l).  At psi = 1 this is Eq. (Hfl).  The three branches share one
+// reciprocal (solid: E / rcs, liquid: (E - El) / rcl, mushy: (E - Es) / d).
 __device__ __forceinline__ void enthalpy_map(const KParams& P, float E, float psi, float& T,
                                              float& fs) {
   const float rcs = psi * P.rc_s + (1.0f - psi) * P.rc_g;
   const float rcl = psi * P.rc_l + (1.0f - psi) * P.rc_g;
   const float Es = rcs * P.T_sol;
   const float El = rcl * P.T_liq + psi * P.rho_l_latent;
-  float fl;
-  if (E < Es) {
-    fl = 0.0f;
-    T = E / rcs;
-  } else if (E > El) {
-    fl = 1.0f;
-    T = P.T_liq + (E - El) / rcl;
-  } else {
-    const float d = El - Es;
-    fl = (d <= 1e-12f * fmaxf(1.0f, fabsf(E))) ? 1.0f : (E - Es) / d;
-    T = P.T_sol + fl * (P.T_liq - P.T_sol);
-  }
+  const bool below = E < Es, above = E > El;
+  const float d = El - Es;
+  const bool flat = d <= 1e-12f * fmaxf(1.0f, fabsf(E));  // pure substance, no latent heat
+  const float den = below ? rcs : (above ? rcl : (flat ? 1.0f : d));
+  const float q = (below ? E : (above ? E - El : E - Es)) * frcp(den);
+  const float fl = below ? 0.0f : (above ? 1.0f : (flat ? 1.0f : q));
+  T = below ? q : (above ? P.T_liq + q : P.T_sol + fl * (P.T_liq - P.T_sol));
   fs = psi * (1.0f - fl);
 }
 
@@ -76,7 +77,7 @@ struct Closure {
 __device__ __forceinline__ Closure closure(const KParams& P, float phi0, float E0, float D) {
   Closure c;
   const float psi = clamp01(0.5f * (1.0f + phi0));
-  c.phi = phi0 / (1.0f - 0.5f * D);
+  c.phi = phi0 * frcp(1.0f - 0.5f * D);
   float T0, fs0;
   enthalpy_map(P, E0, psi, T0, fs0);
   const float rc0 = interp(c.phi, fs0, P.rho_l, P.rho_g, P.rho_s) *
