@@ -10,8 +10,10 @@ one pass of the whole method over the grid.  Prints one JSON line.
 
 The roofline entry uses the algorithmic bytes of one node update (every
 population read once and written once, plus the previous-time-level fields
-the scheme carries: 24 populations and 6 scalars, 240 B in FP32) divided by
-the average launch time measured with HIP events on the solver's stream.
+the scheme carries: 24 populations and 6 scalars, 240 B in FP32; with 16-bit
+storage 4 FP32 rest + 20 16-bit moving populations and 8 scalars read, 7
+written, 172 B) divided by the average launch time measured with HIP events
+on the solver's stream.
 The CPU baseline is the FP64 oracle on the host cores, timed on whole steps of
 the same 2048 x 2048 workload.
 """
@@ -46,9 +48,13 @@ def kernel_source_hash() -> str:
 
 
 def bytes_per_node(storage: str) -> int:
-    # 24 populations read + written, 6 FP32 scalars (f_s, p, u_x, u_y, phi, C)
-    # read + written
-    return 2 * 24 * POP_BYTES[storage] + 2 * 6 * 4
+    if storage == "f32":
+        # 24 populations read + written, 6 FP32 scalars (f_s, p, u_x, u_y, phi,
+        # C) read + written
+        return 2 * 24 * 4 + 2 * 6 * 4
+    # 4 FP32 rest + 20 16-bit moving populations read + written; FP32 scalars:
+    # 8 read (f_s, p, p two levels back, u_x, u_y, phi, C, T) and 7 written
+    return 2 * (4 * 4 + 20 * POP_BYTES[storage]) + (8 + 7) * 4
 
 
 def cpu_baseline(cfg, phi, T, C, budget_s: float = 12.0) -> dict:
@@ -73,14 +79,50 @@ def cpu_baseline(cfg, phi, T, C, budget_s: float = 12.0) -> dict:
 
 
 def load_traffic(kernel_tag: str):
+    """Calibrated HBM bytes per launch of the tagged kernel from the stored
+    counter summary, or None when it is missing or the kernel sources changed
+    since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_tag") != kernel_tag or d.get("source_sha256") != kernel_source_hash():
+    if d.get("source_sha256") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    e = d.get("entries", {}).get(kernel_tag)
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def time_form(cfg, phi, T, C, storage: str, warmup: int, steps: int) -> dict:
+    """Time `steps` steps of one storage form with HIP events on the solver's
+    stream, after `warmup` untimed steps."""
+    import torch
+    from paper_2511_09422_amd.lbfz import Solver
+    solver = Solver(cfg, phi, T, C, device=0, storage=storage)
+    stream = solver.stream
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    solver.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = ev0.elapsed_time(ev1) / steps
+    tot = solver.totals()
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+    if tot["nonfinite"]:
+        print(f"bench: non-finite state ({storage})", file=sys.stderr)
+        sys.exit(1)
+    N = cfg["nx"] * cfg["ny"]
+    bpn = bytes_per_node(storage)
+    achieved = bpn * N / (ms_per_step * 1e-3) / 1e9
+    return {"ms_per_step": ms_per_step, "mlups": N / (ms_per_step * 1e-3) / 1e6,
+            "bytes_per_node": bpn, "achieved": achieved, "wall": wall}
 
 
 def main():
@@ -88,7 +130,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--storage", default="f32", choices=sorted(POP_BYTES))
+    ap.add_argument("--storage", default="f32", choices=sorted(POP_BYTES),
+                    help="population storage of the headline figure")
+    ap.add_argument("--forms", default="f16,bf16",
+                    help="other storage forms timed on the same workload ('' for none)")
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -98,39 +143,33 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2511_09422_amd.lbfz import Solver
     from paper_2511_09422_amd.workloads import droplet_2d
 
     n = args.n
     cfg, phi, T, C = droplet_2d(n, n, R=n / 4.0, seed=0)
-    print(f"bench: 2D droplet {n}x{n}, storage {args.storage}, warmup {args.warmup}, "
-          f"steps {args.steps}", file=sys.stderr, flush=True)
-    solver = Solver(cfg, phi, T, C, device=0, storage=args.storage)
-    stream = solver.stream
-    solver.step(args.warmup)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    solver.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = ev0.elapsed_time(ev1)
-    tot = solver.totals()
-    if tot["nonfinite"]:
-        print("bench: non-finite state", file=sys.stderr)
-        sys.exit(1)
-    N = n * n
-    ms_per_step = ms_total / args.steps
-    mlups = N / (ms_per_step * 1e-3) / 1e6
-    bpn = bytes_per_node(args.storage)
-    achieved = bpn * N / (ms_per_step * 1e-3) / 1e9
-    tag = f"k_step2d_{args.storage}_{n}"
-    traffic = load_traffic(tag)
+    forms = [f for f in args.forms.split(",") if f and f != args.storage]
+    for f in forms:
+        if f not in POP_BYTES:
+            print(f"bench.py: unknown storage form {f}", file=sys.stderr)
+            sys.exit(2)
+    print(f"bench: 2D droplet {n}x{n}, storage {args.storage} (+ {forms}), warmup "
+          f"{args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    main_r = time_form(cfg, phi, T, C, args.storage, args.warmup, args.steps)
+    print(f"bench: {args.storage} {main_r['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr,
+          flush=True)
+    other = {}
+    for f in forms:
+        r = time_form(cfg, phi, T, C, f, args.warmup, args.steps)
+        print(f"bench: {f} {r['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr, flush=True)
+        other[f] = {"value": round(r["mlups"], 2), "unit": "MLUPS",
+                    "ms_per_step": round(r["ms_per_step"], 6),
+                    "speedup_vs_" + args.storage: round(main_r["ms_per_step"] / r["ms_per_step"], 3),
+                    "roofline": {"bound": "hbm", "achieved": round(r["achieved"], 1),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(r["achieved"] / HBM_PEAK_GBS, 4),
+                                 "bytes_per_node": r["bytes_per_node"],
+                                 "traffic": load_traffic(f"k_step2d_{f}_{n}")}}
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -139,12 +178,12 @@ def main():
         torch.cuda.synchronize()
     out = {
         "metric": "coupled-field MLUPS (FP32 vs FP16-store); sweep cases/s; surrogate speedup",
-        "value": round(mlups, 2),
+        "value": round(main_r["mlups"], 2),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 6),
+        "ms_per_step": round(main_r["ms_per_step"], 6),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -152,12 +191,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D droplet freezing {n}x{n}, R={n // 4}, interface width 4, "
                                "D2Q9+3xD2Q5, FP32 arithmetic",
-                   "grid": [n, n], "storage": args.storage, "bytes_per_node": bpn,
-                   "wall_s": round(wall, 3)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                   "grid": [n, n], "storage": args.storage,
+                   "bytes_per_node": main_r["bytes_per_node"],
+                   "wall_s": round(main_r["wall"], 3)},
+        "roofline": {"bound": "hbm", "achieved": round(main_r["achieved"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(main_r["achieved"] / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic(f"k_step2d_{args.storage}_{n}")},
     }
+    if other:
+        out["storage_forms"] = other
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, phi, T, C)
     print(json.dumps(out), flush=True)

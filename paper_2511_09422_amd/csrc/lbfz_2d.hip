@@ -2,12 +2,10 @@
 // (arXiv 2511.09422, Sec. 3) for gfx950: D2Q9 flow g, D2Q5 phase field f,
 // enthalpy h (TRT) and solute l.
 //
-// One kernel launch = one time step.  Populations live in two SoA buffers
-// (plane q starts at q * ps floats: f 0..4, g 5..13, h 14..18, l 19..23); a
-// step reads buffer A at each node's own location and pushes post-collision
-// values along their links into buffer B (half-way bounce-back /
-// anti-bounce-back at walls).  Each 64 x TY tile (one row per wave) stages in
-// LDS
+// One kernel launch = one time step.  A step reads population buffer A at
+// each node's own location and pushes post-collision values along their
+// links into buffer B (half-way bounce-back / anti-bounce-back at walls).
+// Each 64 x TY tile (one row per wave) stages in LDS
 //   - the previous velocity on the tile + 2 ring   (div u for the closure),
 //   - phi, T, C, f_s of the tile + 1 ring, computed from that ring's own
 //     populations (the pointwise closure, evaluated redundantly on the ring
@@ -15,12 +13,29 @@
 //   - the previous pressure on the tile + 1 ring,
 // and then every thread owns one node: stencils, forces, velocity, pressure,
 // four collisions and the streaming writes.  Reads and writes each touch every
-// population once, so HBM traffic is the algorithmic 240 B per node update.
+// population once.
+//
+// Population storage (template parameter ST):
+//   F32   24 FP32 planes, plane q at q * ps floats: f 0..4, g 5..13, h 14..18,
+//         l 19..23.  240 B per node update.
+//   F16 / BF16  the four rest populations stay FP32 (planes 0..3: f0, g0, h0,
+//         l0; they carry most of each conserved sum), the 20 moving ones are
+//         16-bit planes after them (f1..4, g1..8, h1..4, l1..4).  A moving
+//         population is stored as (v - w_i r) * S of the node it sits at,
+//         with r the node's reference moment from the step that wrote it --
+//         phi for f, 3 p (= p / cs^2) for g, (rho c)_ref T for h, C for l --
+//         and a power-of-two scale S per set that keeps the offsets in the
+//         FP16 normal range.  The writer takes the target's references from
+//         the LDS ring (phi, T, C of this step, p of the previous one); the
+//         reader decodes with the same values from the time-level fields,
+//         which are double-buffered (p: triple) so that a ring read never
+//         races the owner's update.  172 B per node update.
 //
 // The step is bound by vector-ALU issue as much as by HBM, so addressing is
-// kept off the vector units: plane bases and the tile row are wave-uniform
-// (scalar registers), a lane carries only a 32-bit byte offset into a plane,
+// kept off the vector units: buffer descriptors and the tile row are
+// wave-uniform (scalar registers), a lane carries only a 32-bit byte offset,
 // and every load or store is one instruction.
+#include "../../include/lbfz.h"
 #include "lbfz_common.hpp"
 #include "lbfz_kernels.hpp"
 
@@ -38,7 +53,8 @@ constexpr int UX = TX + 4, UY = TY + 4;  // velocity ring
 constexpr int RING = 2 * HX + 2 * TY;
 static_assert(RING <= NT, "every ring slot needs a thread");
 
-constexpr int PF = 0, PG = 5, PH = 14, PL = 19;
+constexpr int PF = 0, PG = 5, PH = 14, PL = 19;  // FP32 layout: first plane of each set
+enum { SF = 0, SG = 1, SH = 2, SL = 3 };         // set index (16-bit layout: rest plane)
 
 // D2Q9 (first five = D2Q5)
 constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -48,6 +64,9 @@ constexpr float W9[9] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
                          1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
 constexpr float W5[5] = {1.f / 3, 1.f / 6, 1.f / 6, 1.f / 6, 1.f / 6};
 
+// 16-bit offset scales (powers of two: exact).
+constexpr float SC_F = 256.0f, SC_G = 16384.0f, SC_H = 1024.0f, SC_L = 4096.0f;
+
 // Word 3 of a CDNA buffer descriptor: 32-bit data format, no swizzle.
 constexpr int kBufWord3 = 0x00020000;
 
@@ -56,8 +75,8 @@ constexpr int kBufWord3 = 0x00020000;
 // registers), the lane supplies only a 32-bit byte offset.  Offsets outside
 // the range read 0 and write nothing.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
-__device__ __forceinline__ rsrc_t rsrc(const float* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)bytes,
+__device__ __forceinline__ rsrc_t rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
                                            kBufWord3);
 }
 __device__ __forceinline__ float ld(rsrc_t r, uint32_t off, uint32_t soff = 0) {
@@ -66,28 +85,73 @@ __device__ __forceinline__ float ld(rsrc_t r, uint32_t off, uint32_t soff = 0) {
 __device__ __forceinline__ void st(rsrc_t r, uint32_t off, uint32_t soff, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, (int)soff, 0);
 }
+__device__ __forceinline__ uint16_t ld16(rsrc_t r, uint32_t off, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0);
+}
+__device__ __forceinline__ void st16(rsrc_t r, uint32_t off, uint32_t soff, uint16_t v) {
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, (int)soff, 0);
+}
 
-// Descriptors of one step: population sets of the source and destination
-// buffers (plane i of a set at byte offset i * pb) and the time-level fields.
+// 16-bit storage formats: round to nearest even either way.
+template <int ST>
+__device__ __forceinline__ float dec16(uint16_t b) {
+  if constexpr (ST == LBFZ_STORE_F16)
+    return (float)__builtin_bit_cast(_Float16, b);
+  else
+    return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+template <int ST>
+__device__ __forceinline__ uint16_t enc16(float v) {
+  if constexpr (ST == LBFZ_STORE_F16)
+    return __builtin_bit_cast(uint16_t, (_Float16)v);
+  else
+    return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
+// Descriptors of one step.  F32: population sets incl. rest (plane i of a set
+// at byte offset i * pb).  16-bit: rest = the four FP32 rest planes, f/g/h/l =
+// the moving 16-bit planes of each set (plane i - 1 at (i - 1) * hb).
 struct Bufs {
-  rsrc_t f, g, h, l;          // source sets
-  rsrc_t df, dg, dh, dl;      // destination sets
-  rsrc_t p_old, u_old;        // u_old: x plane, then y plane
-  uint32_t pb;                // plane bytes
+  rsrc_t f, g, h, l, rest;       // source
+  rsrc_t df, dg, dh, dl, drest;  // destination
+  rsrc_t p_old, u_old;           // u_old: x plane, then y plane
+  rsrc_t phiO, CO, TO, pR;       // 16-bit: decode references of the source
+  uint32_t pb, hb;               // FP32 / 16-bit plane bytes
 };
 
+template <int ST>
 __device__ __forceinline__ Bufs make_bufs(const KParams& P, const StepArgs& A) {
   Bufs B;
   const long PS = P.ps;
   B.pb = (uint32_t)PS * 4u;
-  B.f = rsrc(A.src + PF * PS, 5 * B.pb);
-  B.g = rsrc(A.src + PG * PS, 9 * B.pb);
-  B.h = rsrc(A.src + PH * PS, 5 * B.pb);
-  B.l = rsrc(A.src + PL * PS, 5 * B.pb);
-  B.df = rsrc(A.dst + PF * PS, 5 * B.pb);
-  B.dg = rsrc(A.dst + PG * PS, 9 * B.pb);
-  B.dh = rsrc(A.dst + PH * PS, 5 * B.pb);
-  B.dl = rsrc(A.dst + PL * PS, 5 * B.pb);
+  B.hb = (uint32_t)PS * 2u;
+  if constexpr (ST == LBFZ_STORE_F32) {
+    B.f = rsrc(A.src + PF * PS, 5 * B.pb);
+    B.g = rsrc(A.src + PG * PS, 9 * B.pb);
+    B.h = rsrc(A.src + PH * PS, 5 * B.pb);
+    B.l = rsrc(A.src + PL * PS, 5 * B.pb);
+    B.df = rsrc(A.dst + PF * PS, 5 * B.pb);
+    B.dg = rsrc(A.dst + PG * PS, 9 * B.pb);
+    B.dh = rsrc(A.dst + PH * PS, 5 * B.pb);
+    B.dl = rsrc(A.dst + PL * PS, 5 * B.pb);
+  } else {
+    const uint16_t* s16 = reinterpret_cast<const uint16_t*>(A.src + 4 * PS);
+    const uint16_t* d16 = reinterpret_cast<const uint16_t*>(A.dst + 4 * PS);
+    B.rest = rsrc(A.src, 4 * B.pb);
+    B.f = rsrc(s16, 4 * B.hb);
+    B.g = rsrc(s16 + 4 * PS, 8 * B.hb);
+    B.h = rsrc(s16 + 12 * PS, 4 * B.hb);
+    B.l = rsrc(s16 + 16 * PS, 4 * B.hb);
+    B.drest = rsrc(A.dst, 4 * B.pb);
+    B.df = rsrc(d16, 4 * B.hb);
+    B.dg = rsrc(d16 + 4 * PS, 8 * B.hb);
+    B.dh = rsrc(d16 + 12 * PS, 4 * B.hb);
+    B.dl = rsrc(d16 + 16 * PS, 4 * B.hb);
+    B.phiO = rsrc(A.phiP_old, B.pb);
+    B.CO = rsrc(A.CP_old, B.pb);
+    B.TO = rsrc(A.T_old, B.pb);
+    B.pR = rsrc(A.p_ref, B.pb);
+  }
   B.p_old = rsrc(A.p_old, B.pb);
   B.u_old = rsrc(A.u_old, 2 * B.pb);
   return B;
@@ -118,32 +182,75 @@ __device__ __forceinline__ uint32_t node_off(int mx, int my, int nx) {
   return ((uint32_t)my * (uint32_t)nx + (uint32_t)mx) * 4u;
 }
 
+// f, h, l populations of the node at byte offset o (FP32 units).
+template <int ST>
+__device__ __forceinline__ void load_fhl(const KParams& P, const Bufs& B, uint32_t o, float* f,
+                                         float* h, float* l) {
+  if constexpr (ST == LBFZ_STORE_F32) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      f[i] = ld(B.f, o, i * B.pb);
+      h[i] = ld(B.h, o, i * B.pb);
+      l[i] = ld(B.l, o, i * B.pb);
+    }
+  } else {
+    const uint32_t o2 = o >> 1;
+    const float rf = W5[1] * ld(B.phiO, o), rh = W5[1] * P.rhoc_ref * ld(B.TO, o),
+                rl = W5[1] * ld(B.CO, o);
+    f[0] = ld(B.rest, o, SF * B.pb);
+    h[0] = ld(B.rest, o, SH * B.pb);
+    l[0] = ld(B.rest, o, SL * B.pb);
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      f[i] = fmaf(dec16<ST>(ld16(B.f, o2, (i - 1) * B.hb)), 1.0f / SC_F, rf);
+      h[i] = fmaf(dec16<ST>(ld16(B.h, o2, (i - 1) * B.hb)), 1.0f / SC_H, rh);
+      l[i] = fmaf(dec16<ST>(ld16(B.l, o2, (i - 1) * B.hb)), 1.0f / SC_L, rl);
+    }
+  }
+}
+
+template <int ST>
+__device__ __forceinline__ void load_g(const Bufs& B, uint32_t o, float* g) {
+  if constexpr (ST == LBFZ_STORE_F32) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = ld(B.g, o, i * B.pb);
+  } else {
+    const uint32_t o2 = o >> 1;
+    const float p3 = 3.0f * ld(B.pR, o);
+    g[0] = ld(B.rest, o, SG * B.pb);
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+      g[i] = fmaf(dec16<ST>(ld16(B.g, o2, (i - 1) * B.hb)), 1.0f / SC_G, W9[i] * p3);
+  }
+}
+
 struct Slot {
   float phi, T, C, fs, p;
 };
 
-// Closure of the node (mx, my) staged in closure-ring slot (lx, ly): its 15
-// f/h/l populations (returned), div u^{n-1} from the velocity ring and
-// p^{n-1}.  A ghost slot (side != 0) holds the mirror node with the wall's
-// temperature transform.
-__device__ __forceinline__ Slot eval_slot(const KParams& P, const Bufs& B, int y0, int mx,
-                                          int my, int side, int lx, int ly, float (*s_ux)[UX],
-                                          float (*s_uy)[UX], float* f, float* h, float* l,
-                                          float& Dout, Closure& cout) {
-  const uint32_t o = node_off(mx, my, P.nx);
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    f[i] = ld(B.f, o, i * B.pb);
-    h[i] = ld(B.h, o, i * B.pb);
-    l[i] = ld(B.l, o, i * B.pb);
-  }
-  const float p = ld(B.p_old, o);
+// Raw inputs of one closure slot: its f, h, l populations and p^{n-1}.
+struct Raw {
+  float f[5], h[5], l[5], p;
+};
+
+template <int ST>
+__device__ __forceinline__ void load_raw(const KParams& P, const Bufs& B, uint32_t o, Raw& r) {
+  load_fhl<ST>(P, B, o, r.f, r.h, r.l);
+  r.p = ld(B.p_old, o);
+}
+
+// Closure of the node (mx, my) staged in closure-ring slot (lx, ly), from its
+// raw inputs and div u^{n-1} on the velocity ring.  A ghost slot (side != 0)
+// holds the mirror node with the wall's temperature transform.
+__device__ __forceinline__ Slot close_slot(const KParams& P, const Raw& r, int y0, int mx,
+                                           int my, int side, int lx, int ly, float (*s_ux)[UX],
+                                           float (*s_uy)[UX], float& Dout, Closure& cout) {
   float phi0 = 0.f, E0 = 0.f, C = 0.f;
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    phi0 += f[i];
-    E0 += h[i];
-    C += l[i];
+    phi0 += r.f[i];
+    E0 += r.h[i];
+    C += r.l[i];
   }
   // velocity-ring position of the source node
   const int ux = lx + 1;
@@ -164,7 +271,7 @@ __device__ __forceinline__ Slot eval_slot(const KParams& P, const Bufs& B, int y
   s.phi = c.phi;
   s.C = C;
   s.fs = c.fs;
-  s.p = p;
+  s.p = r.p;
   float T = c.T;
   if (side < 0 && P.tlo_dir) T = 2.0f * (P.T_lo + P.T_lo_amp * cosf(P.kwall * (float)mx)) - T;
   if (side > 0 && P.thi_dir) T = 2.0f * P.T_hi - T;
@@ -178,8 +285,8 @@ __device__ __forceinline__ Slot eval_slot(const KParams& P, const Bufs& B, int y
 #define LBFZ_OCC
 #endif
 
-template <bool DRY>
-__global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A) {
+template <bool DRY, int ST>
+__global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, StepArgs A) {
   __shared__ float s_ux[UY][UX], s_uy[UY][UX];
   __shared__ float s_phi[HY][HX], s_T[HY][HX], s_C[HY][HX], s_fs[HY][HX], s_p[HY][HX];
   __shared__ double s_red[NT / 64];
@@ -190,9 +297,8 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
   const int tid = threadIdx.x, tx = tid & (TX - 1);
   const int ty = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform row
   const int nx = P.nx, ny = P.ny;
-  const long PS = P.ps;
-  const Bufs B = make_bufs(P, A);
-  const uint32_t PB = B.pb, NB = (uint32_t)P.N * 4u;  // plane / output bytes
+  const Bufs B = make_bufs<ST>(P, A);
+  const uint32_t PB = B.pb, HB = B.hb, NB = (uint32_t)P.N * 4u;  // plane / output bytes
   const int gx = x0 + tx, gy = y0 + ty;
   const bool valid = gx < nx && gy < ny;
   // own slot; lanes of a partial tile outside the grid stage the periodic
@@ -201,68 +307,90 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
   const int omx = wrap_near(gx, nx);
   const int omy = map_y(gy, ny, P.walls, oside);
   const uint32_t on = node_off(omx, omy, nx);
-  // own-node loads that do not depend on the LDS phases are issued first
+  // Every global load of the block -- own node and its ring slot -- is issued
+  // before the first barrier, so a block waits for memory once.
   float g[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = ld(B.g, on, i * PB);
-  const rsrc_t r_fs = rsrc(A.fs, PB), r_phiP = rsrc(A.phiP, PB), r_CP = rsrc(A.CP, PB);
+  load_g<ST>(B, on, g);
+  const rsrc_t r_fs = rsrc(A.fs, PB);
   const float fs_prev = ld(r_fs, on);
-  const float phiP = ld(r_phiP, on), CP = ld(r_CP, on);
-
-  // 1. previous velocity on tile + 2 ring; no-slip ghosts are negated mirrors
-  for (int s = tid; s < UX * UY; s += NT) {
+  const float phiP = ld(rsrc(A.phiP_old, PB), on), CP = ld(rsrc(A.CP_old, PB), on);
+  Raw own;
+  load_raw<ST>(P, B, on, own);
+  // 1. previous velocity on tile + 2 ring; no-slip ghosts are negated mirrors.
+  // All of a thread's slots are loaded before the first is stored.
+  constexpr int UN = UX * UY, UIT = (UN + NT - 1) / NT;
+  float vx[UIT], vy[UIT], sg[UIT];
+#pragma unroll
+  for (int k = 0; k < UIT; ++k) {
+    const int s = min(tid + k * NT, UN - 1);
     const int lx = s % UX, ly = s / UX;
     int side;
     const int my = map_y(y0 + ly - 2, ny, P.walls, side);
     const uint32_t o = node_off(wrap_near(x0 + lx - 2, nx), my, nx);
-    const float sg = side ? -1.0f : 1.0f;
-    s_ux[ly][lx] = sg * ld(B.u_old, o);
-    s_uy[ly][lx] = sg * ld(B.u_old, o, PB);
+    sg[k] = side ? -1.0f : 1.0f;
+    vx[k] = ld(B.u_old, o);
+    vy[k] = ld(B.u_old, o, PB);
+  }
+  // ring slots go to the first threads, so only ceil(RING / 64) waves run the
+  // extra closure
+  const bool has_ring = tid < RING;
+  int rlx = 0, rly = 0, rmx = 0, rmy = 0, rside = 0;
+  Raw ring;
+  if (has_ring) {
+    if (tid < HX) {
+      rlx = tid;
+      rly = 0;
+    } else if (tid < 2 * HX) {
+      rlx = tid - HX;
+      rly = HY - 1;
+    } else if (tid < 2 * HX + TY) {
+      rlx = 0;
+      rly = tid - 2 * HX + 1;
+    } else {
+      rlx = HX - 1;
+      rly = tid - 2 * HX - TY + 1;
+    }
+    rmy = map_y(y0 + rly - 1, ny, P.walls, rside);
+    rmx = wrap_near(x0 + rlx - 1, nx);
+    load_raw<ST>(P, B, node_off(rmx, rmy, nx), ring);
+  }
+
+#pragma unroll
+  for (int k = 0; k < UIT; ++k) {
+    const int s = tid + k * NT;
+    if (s < UN) {
+      s_ux[s / UX][s % UX] = sg[k] * vx[k];
+      s_uy[s / UX][s % UX] = sg[k] * vy[k];
+    }
   }
   __syncthreads();
 
-  // 2. closure on tile + 1 ring: own slot first (pops kept in registers)
-  float f[5], h[5], l[5], D;
+  // 2. closure on tile + 1 ring
+  float D;
   Closure cl;
   {
-    const Slot s = eval_slot(P, B, y0, omx, omy, oside, tx + 1, ty + 1, s_ux, s_uy, f, h, l, D,
-                             cl);
+    const Slot s =
+        close_slot(P, own, y0, omx, omy, oside, tx + 1, ty + 1, s_ux, s_uy, D, cl);
     s_phi[ty + 1][tx + 1] = s.phi;
     s_T[ty + 1][tx + 1] = s.T;
     s_C[ty + 1][tx + 1] = s.C;
     s_fs[ty + 1][tx + 1] = s.fs;
     s_p[ty + 1][tx + 1] = s.p;
   }
-  // ring slots go to the first threads, so only ceil(RING / 64) waves run the
-  // extra closure
-  if (tid < RING) {
-    int lx, ly;
-    if (tid < HX) {
-      lx = tid;
-      ly = 0;
-    } else if (tid < 2 * HX) {
-      lx = tid - HX;
-      ly = HY - 1;
-    } else if (tid < 2 * HX + TY) {
-      lx = 0;
-      ly = tid - 2 * HX + 1;
-    } else {
-      lx = HX - 1;
-      ly = tid - 2 * HX - TY + 1;
-    }
-    int side;
-    const int my = map_y(y0 + ly - 1, ny, P.walls, side);
-    const int mx = wrap_near(x0 + lx - 1, nx);
-    float f2[5], h2[5], l2[5], D2;
+  if (has_ring) {
+    float D2;
     Closure c2;
-    const Slot s = eval_slot(P, B, y0, mx, my, side, lx, ly, s_ux, s_uy, f2, h2, l2, D2, c2);
-    s_phi[ly][lx] = s.phi;
-    s_T[ly][lx] = s.T;
-    s_C[ly][lx] = s.C;
-    s_fs[ly][lx] = s.fs;
-    s_p[ly][lx] = s.p;
+    const Slot s = close_slot(P, ring, y0, rmx, rmy, rside, rlx, rly, s_ux, s_uy, D2, c2);
+    s_phi[rly][rlx] = s.phi;
+    s_T[rly][rlx] = s.T;
+    s_C[rly][rlx] = s.C;
+    s_fs[rly][rlx] = s.fs;
+    s_p[rly][rlx] = s.p;
   }
   __syncthreads();
+  const float* f = own.f;
+  const float* h = own.h;
+  const float* l = own.l;
 
   const int cx = tx + 1, cy = ty + 1;
 
@@ -403,11 +531,30 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
   const uint32_t colb[3] = {(uint32_t)(omx == 0 ? nx - 1 : omx - 1) * 4u, (uint32_t)omx * 4u,
                             (uint32_t)(omx == nx - 1 ? 0 : omx + 1) * 4u};
   auto walled = [&](int i) { return (CY[i] < 0 && wlo) || (CY[i] > 0 && whi); };
-  auto push = [&](rsrc_t set, int i, float v) {
-    if (walled(i))
-      st(set, on, OPP[i] * PB, v);  // half-way bounce-back
+  // Store post-collision value v of link i (> 0) of a set at the node it
+  // streams to.  16-bit: encoded against w_i r of that node, where ref(dy, dx)
+  // reads w_i r from the LDS ring.
+  auto push = [&](rsrc_t set, int i, float v, float scale, auto ref) {
+    if constexpr (ST == LBFZ_STORE_F32) {
+      if (walled(i))
+        st(set, on, OPP[i] * PB, v);  // half-way bounce-back
+      else
+        st(set, rowb[CY[i] + 1] + colb[CX[i] + 1], i * PB, v);
+    } else {
+      if (walled(i)) {
+        st16(set, on >> 1, (OPP[i] - 1) * HB, enc16<ST>((v - ref(0, 0)) * scale));
+      } else {
+        st16(set, (rowb[CY[i] + 1] + colb[CX[i] + 1]) >> 1, (i - 1) * HB,
+             enc16<ST>((v - ref(CY[i], CX[i])) * scale));
+      }
+    }
+  };
+  // rest population of set k at the own node
+  auto put_rest = [&](rsrc_t set, int k, float v) {
+    if constexpr (ST == LBFZ_STORE_F32)
+      st(set, on, 0, v);
     else
-      st(set, rowb[CY[i] + 1] + colb[CX[i] + 1], i * PB, v);
+      st(B.drest, on, k * PB, v);
   };
   // flow BGK (Sec. 3.2)
   if (valid) {
@@ -418,9 +565,10 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
       const float si = W9[i] * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
       const float geq = pn * kInvCs2 * W9[i] + rho * si;
       geq_sum += geq;
-      push(B.dg, i, g[i] - (g[i] - geq) * P.itau_g + P.wg * G[i]);
+      push(B.dg, i, g[i] - (g[i] - geq) * P.itau_g + P.wg * G[i], SC_G,
+           [&](int dy, int dx) { return (3.0f * W9[i]) * s_p[cy + dy][cx + dx]; });
     }
-    st(B.dg, on, 0, g[0] - (g[0] + geq_sum) * P.itau_g + P.wg * G[0]);
+    put_rest(B.dg, SG, g[0] - (g[0] + geq_sum) * P.itau_g + P.wg * G[0]);
   }
   // phase field BGK (Sec. 3.1)
   const float upx = s_ux[ty + 2][tx + 2], upy = s_uy[ty + 2][tx + 2];
@@ -436,10 +584,10 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
       const float feq = W5[i] * phi * (1.0f + kInvCs2 * cu);
       feq_sum += feq;
       F_sum += Fi;
-      push(B.df, i, f[i] - (f[i] - feq) * P.itau_f + P.wf * Fi);
+      push(B.df, i, f[i] - (f[i] - feq) * P.itau_f + P.wf * Fi, SC_F,
+           [&](int dy, int dx) { return W5[1] * s_phi[cy + dy][cx + dx]; });
     }
-    st(B.df, on, 0,
-       f[0] - (f[0] - (phi - feq_sum)) * P.itau_f + P.wf * (phi * D - F_sum));
+    put_rest(B.df, SF, f[0] - (f[0] - (phi - feq_sum)) * P.itau_f + P.wf * (phi * D - F_sum));
   }
   // enthalpy TRT (Sec. 3.3); E and Q from the closure of the own node
   if (valid) {
@@ -453,6 +601,7 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
       heq[0] -= heq[i];
     }
     const float hq = W5[1] * cl.Q, hq0 = cl.Q - 4.0f * hq;
+    const float href_w = W5[1] * P.rhoc_ref;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       const int o = OPP[i];
@@ -461,16 +610,16 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
       const float v = h[i] - (hs - es) * P.itau_s - (ha - ea) * P.itau_a +
                       P.ws * (i == 0 ? hq0 : hq);
       if (i == 0) {
-        st(B.dh, on, 0, v);
-      } else if (walled(i)) {
-        float hv = v;
-        if (CY[i] < 0 && P.tlo_dir)
-          hv = -hv + 2.0f * W5[o] * P.rhoc_ref *
-                         (P.T_lo + P.T_lo_amp * cosf(P.kwall * (float)gx));
-        if (CY[i] > 0 && P.thi_dir) hv = -hv + 2.0f * W5[o] * P.rhoc_ref * P.T_hi;
-        st(B.dh, on, o * PB, hv);
+        put_rest(B.dh, SH, v);
+      } else if (walled(i) && ((CY[i] < 0 && P.tlo_dir) || (CY[i] > 0 && P.thi_dir))) {
+        const float Tw = CY[i] < 0 ? P.T_lo + P.T_lo_amp * cosf(P.kwall * (float)gx) : P.T_hi;
+        const float hv = -v + 2.0f * W5[o] * P.rhoc_ref * Tw;  // anti-bounce-back
+        if constexpr (ST == LBFZ_STORE_F32)
+          st(B.dh, on, o * PB, hv);
+        else
+          st16(B.dh, on >> 1, (o - 1) * HB, enc16<ST>((hv - href_w * T) * SC_H));
       } else {
-        st(B.dh, rowb[CY[i] + 1] + colb[CX[i] + 1], i * PB, v);
+        push(B.dh, i, v, SC_H, [&](int dy, int dx) { return href_w * s_T[cy + dy][cx + dx]; });
       }
     }
   }
@@ -491,26 +640,33 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, Step2DArgs A)
       const float Li = W5[i] * kInvCs2 * (CX[i] * Lx + CY[i] * Ly);
       const float leq = W5[i] * C * (1.0f + kInvCs2 * cu);
       leq_sum += leq;
-      push(B.dl, i, l[i] - (l[i] - leq) * itau_l + wl * Li);
+      push(B.dl, i, l[i] - (l[i] - leq) * itau_l + wl * Li, SC_L,
+           [&](int dy, int dx) { return W5[1] * s_C[cy + dy][cx + dx]; });
     }
-    st(B.dl, on, 0, l[0] - (l[0] - (C - leq_sum)) * itau_l);
+    put_rest(B.dl, SL, l[0] - (l[0] - (C - leq_sum)) * itau_l);
   }
 
-  // 6. the time-level state
+  // 6. the time-level state (16-bit: phi, C, T are also the decode references
+  // of the populations just written)
   if (valid) {
     st(rsrc(A.p_new, PB), on, 0, pn);
     const rsrc_t r_un = rsrc(A.u_new, 2 * PB);
     st(r_un, on, 0, ux);
     st(r_un, on, PB, uy);
     st(r_fs, on, 0, fs);
-    st(r_phiP, on, 0, phi);
-    st(r_CP, on, 0, C);
+    st(rsrc(A.phiP_new, PB), on, 0, phi);
+    st(rsrc(A.CP_new, PB), on, 0, C);
+    if constexpr (ST != LBFZ_STORE_F32) st(rsrc(A.T_new, PB), on, 0, T);
   }
   // phase-field source budget: sum of phi div u over the tile, FP64
   const double s = block_sum<NT>(valid ? (double)phi * (double)D : 0.0, s_red);
   if (tid == 0) A.mpc_part[tile] += s;
 }
 
+// Equilibrium populations of the initial fields (u = 0, p = 0) and the zero
+// previous-level state.  16-bit: every moving population sits exactly at its
+// reference (offset 0), and the references phi, C, T are stored.
+template <int ST>
 __global__ __launch_bounds__(256) void k_init2d(KParams P, const double* __restrict__ phi_in,
                                                 const double* __restrict__ T_in,
                                                 const double* __restrict__ C_in,
@@ -525,27 +681,113 @@ __global__ __launch_bounds__(256) void k_init2d(KParams P, const double* __restr
     float h0 = E, f0 = phi, l0 = C;
 #pragma unroll
     for (int i = 1; i < 5; ++i) {
-      pop[(PH + i) * PS + n] = W5[i] * P.rhoc_ref * T;
-      pop[(PF + i) * PS + n] = W5[i] * phi;
-      pop[(PL + i) * PS + n] = W5[i] * C;
       h0 -= W5[i] * P.rhoc_ref * T;
       f0 -= W5[i] * phi;
       l0 -= W5[i] * C;
     }
-    pop[(PH + 0) * PS + n] = h0;
-    pop[(PF + 0) * PS + n] = f0;
-    pop[(PL + 0) * PS + n] = l0;
+    if constexpr (ST == LBFZ_STORE_F32) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) pop[(PG + i) * PS + n] = 0.0f;
+      for (int i = 1; i < 5; ++i) {
+        pop[(PH + i) * PS + n] = W5[i] * P.rhoc_ref * T;
+        pop[(PF + i) * PS + n] = W5[i] * phi;
+        pop[(PL + i) * PS + n] = W5[i] * C;
+      }
+      pop[(PH + 0) * PS + n] = h0;
+      pop[(PF + 0) * PS + n] = f0;
+      pop[(PL + 0) * PS + n] = l0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) pop[(PG + i) * PS + n] = 0.0f;
+      S.phiA[n] = 0.f;
+      S.CA[n] = 0.f;
+    } else {
+      pop[SF * PS + n] = f0;
+      pop[SG * PS + n] = 0.0f;
+      pop[SH * PS + n] = h0;
+      pop[SL * PS + n] = l0;
+      uint16_t* m16 = reinterpret_cast<uint16_t*>(pop + 4 * PS);
+#pragma unroll
+      for (int j = 0; j < 20; ++j) m16[j * PS + n] = enc16<ST>(0.0f);
+      // decode references of the step that reads these populations
+      S.phiA[n] = phi;
+      S.CA[n] = C;
+      S.TA[n] = T;
+      S.pC[n] = 0.f;
+    }
     S.pA[n] = 0.f;
     S.pB[n] = 0.f;
     S.uA[n] = S.uA[PS + n] = 0.f;
     S.uB[n] = S.uB[PS + n] = 0.f;
     S.fs[n] = 0.f;
-    S.phiP[n] = 0.f;
-    S.CP[n] = 0.f;
   }
 }
+
+// 16-bit forms: populations of the current level decoded to FP32 planes
+// (state order) in dst[q * N + n], q < 24.
+template <int ST>
+__global__ __launch_bounds__(256) void k_export2d(KParams P, StepArgs A, float* __restrict__ dst) {
+  const long N = P.N;
+  const Bufs B = make_bufs<ST>(P, A);
+  for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < N;
+       n += (long)gridDim.x * blockDim.x) {
+    const uint32_t o = (uint32_t)n * 4u;
+    float f[5], h[5], l[5], g[9];
+    load_fhl<ST>(P, B, o, f, h, l);
+    load_g<ST>(B, o, g);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      dst[(PF + i) * N + n] = f[i];
+      dst[(PH + i) * N + n] = h[i];
+      dst[(PL + i) * N + n] = l[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dst[(PG + i) * N + n] = g[i];
+  }
+}
+
+// 16-bit forms: encode FP32 populations src[q * N + n] (state order) into the
+// buffer A.dst with the references phi = A.phiP_old, C = A.CP_old, p =
+// A.p_ref (all already imported) and T from the enthalpy map of the imported
+// populations, which is stored in A.T_new.
+template <int ST>
+__global__ __launch_bounds__(256) void k_import2d(KParams P, StepArgs A,
+                                                  const float* __restrict__ src) {
+  const long N = P.N, PS = P.ps;
+  for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < N;
+       n += (long)gridDim.x * blockDim.x) {
+    float f[5], h[5], l[5], g[9];
+    float phi0 = 0.f, E = 0.f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      f[i] = src[(PF + i) * N + n];
+      h[i] = src[(PH + i) * N + n];
+      l[i] = src[(PL + i) * N + n];
+      phi0 += f[i];
+      E += h[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = src[(PG + i) * N + n];
+    float T, fs;
+    enthalpy_map(P, E, clamp01(0.5f * (1.0f + phi0)), T, fs);
+    A.T_new[n] = T;
+    const float rf = W5[1] * A.phiP_old[n], rl = W5[1] * A.CP_old[n];
+    const float rh = W5[1] * P.rhoc_ref * T, p3 = 3.0f * A.p_ref[n];
+    A.dst[SF * PS + n] = f[0];
+    A.dst[SG * PS + n] = g[0];
+    A.dst[SH * PS + n] = h[0];
+    A.dst[SL * PS + n] = l[0];
+    uint16_t* m16 = reinterpret_cast<uint16_t*>(A.dst + 4 * PS);
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      m16[(i - 1) * PS + n] = enc16<ST>((f[i] - rf) * SC_F);
+      m16[(12 + i - 1) * PS + n] = enc16<ST>((h[i] - rh) * SC_H);
+      m16[(16 + i - 1) * PS + n] = enc16<ST>((l[i] - rl) * SC_L);
+    }
+#pragma unroll
+    for (int i = 1; i < 9; ++i) m16[(4 + i - 1) * PS + n] = enc16<ST>((g[i] - W9[i] * p3) * SC_G);
+  }
+}
+
+int grid_of(long N) { return (int)std::min<long>((N + 255) / 256, 65536); }
 
 }  // namespace
 
@@ -555,18 +797,65 @@ int tiles2d(int nx, int ny, int* nbx, int* nby) {
   return (*nbx) * (*nby);
 }
 
-hipError_t launch_init2d(const KParams& P, const double* phi, const double* T, const double* C,
-                         float* pop, const StateArgs& S, hipStream_t st) {
-  const int blocks = (int)std::min<long>((P.N + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_init2d, dim3(blocks), dim3(256), 0, st, P, phi, T, C, pop, S);
+size_t pop_bytes2d(int storage, size_t ps) {
+  return storage == LBFZ_STORE_F32 ? 24 * ps * sizeof(float)
+                                   : 4 * ps * sizeof(float) + 20 * ps * sizeof(uint16_t);
+}
+
+hipError_t launch_init2d(const KParams& P, int storage, const double* phi, const double* T,
+                         const double* C, float* pop, const StateArgs& S, hipStream_t st) {
+  const int blocks = grid_of(P.N);
+  switch (storage) {
+    case LBFZ_STORE_F32:
+      hipLaunchKernelGGL(k_init2d<LBFZ_STORE_F32>, dim3(blocks), dim3(256), 0, st, P, phi, T,
+                         C, pop, S);
+      break;
+    case LBFZ_STORE_F16:
+      hipLaunchKernelGGL(k_init2d<LBFZ_STORE_F16>, dim3(blocks), dim3(256), 0, st, P, phi, T,
+                         C, pop, S);
+      break;
+    default:
+      hipLaunchKernelGGL(k_init2d<LBFZ_STORE_BF16>, dim3(blocks), dim3(256), 0, st, P, phi, T,
+                         C, pop, S);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_step2d(const KParams& P, const Step2DArgs& A, bool dry, hipStream_t st) {
+template <int ST>
+static void launch_step2d_st(const KParams& P, const StepArgs& A, bool dry, hipStream_t st) {
   if (dry)
-    hipLaunchKernelGGL(k_step2d<true>, dim3(P.nblk), dim3(NT), 0, st, P, A);
+    hipLaunchKernelGGL((k_step2d<true, ST>), dim3(P.nblk), dim3(NT), 0, st, P, A);
   else
-    hipLaunchKernelGGL(k_step2d<false>, dim3(P.nblk), dim3(NT), 0, st, P, A);
+    hipLaunchKernelGGL((k_step2d<false, ST>), dim3(P.nblk), dim3(NT), 0, st, P, A);
+}
+
+hipError_t launch_step2d(const KParams& P, int storage, const StepArgs& A, bool dry,
+                         hipStream_t st) {
+  switch (storage) {
+    case LBFZ_STORE_F32: launch_step2d_st<LBFZ_STORE_F32>(P, A, dry, st); break;
+    case LBFZ_STORE_F16: launch_step2d_st<LBFZ_STORE_F16>(P, A, dry, st); break;
+    default: launch_step2d_st<LBFZ_STORE_BF16>(P, A, dry, st);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_export2d(const KParams& P, int storage, const StepArgs& A, float* dst,
+                           hipStream_t st) {
+  const int blocks = grid_of(P.N);
+  if (storage == LBFZ_STORE_F16)
+    hipLaunchKernelGGL(k_export2d<LBFZ_STORE_F16>, dim3(blocks), dim3(256), 0, st, P, A, dst);
+  else
+    hipLaunchKernelGGL(k_export2d<LBFZ_STORE_BF16>, dim3(blocks), dim3(256), 0, st, P, A, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_import2d(const KParams& P, int storage, const StepArgs& A, const float* src,
+                           hipStream_t st) {
+  const int blocks = grid_of(P.N);
+  if (storage == LBFZ_STORE_F16)
+    hipLaunchKernelGGL(k_import2d<LBFZ_STORE_F16>, dim3(blocks), dim3(256), 0, st, P, A, src);
+  else
+    hipLaunchKernelGGL(k_import2d<LBFZ_STORE_BF16>, dim3(blocks), dim3(256), 0, st, P, A, src);
   return hipGetLastError();
 }
 

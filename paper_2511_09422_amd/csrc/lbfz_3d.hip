@@ -289,8 +289,8 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
           A.p_new[n] = 0.f;
           A.u_new[n] = A.u_new[PS + n] = A.u_new[2 * PS + n] = 0.f;
           A.fs[n] = 0.f;
-          A.phiP[n] = -1.f;
-          A.CP[n] = 0.f;
+          A.phiP_new[n] = -1.f;
+          A.CP_new[n] = 0.f;
         }
       } else {
         // stencils (isotropic D3Q19 gradient / Laplacian), one field per pass so
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
 #pragma unroll
           for (int i = 1; i < 7; ++i) f[i] = A.src[(PF + i) * PS + n];
           const float up0 = A.u_old[n], up1 = A.u_old[PS + n], up2 = A.u_old[2 * PS + n];
-          const float phiP = A.phiP[n], CP = A.CP[n];
+          const float phiP = A.phiP_old[n], CP = A.CP_old[n];
           {
             const float cf = kCs2 * (1.0f - phi * phi) * P.isq;
             const float B0 = (phi * u[0] - phiP * up0) + cf * nv[0];
@@ -535,8 +535,8 @@ __global__ __launch_bounds__(NT) void k_step3d(KParams P, StepArgs A, int seg) {
           A.u_new[PS + n] = u[1];
           A.u_new[2 * PS + n] = u[2];
           A.fs[n] = fs;
-          A.phiP[n] = phi;
-          A.CP[n] = C;
+          A.phiP_new[n] = phi;
+          A.CP_new[n] = C;
         }
       }
     }
@@ -591,8 +591,8 @@ __global__ __launch_bounds__(256) void k_init3d(KParams P, const double* __restr
 #pragma unroll
     for (int a = 0; a < 3; ++a) S.uA[a * PS + n] = S.uB[a * PS + n] = 0.f;
     S.fs[n] = 0.f;
-    S.phiP[n] = 0.f;
-    S.CP[n] = 0.f;
+    S.phiA[n] = 0.f;
+    S.CA[n] = 0.f;
   }
 }
 

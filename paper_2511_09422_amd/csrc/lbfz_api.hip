@@ -21,10 +21,15 @@ struct lbfz_handle {
   hipStream_t stream;
   char* ws;
   size_t ws_bytes;
+  int storage;
   float* pop[2];
-  float* p[2];
+  float* p[3];     // FP32: two levels; 16-bit: three (p_ref)
   float* u[2];
-  float *fs, *phiP, *CP;
+  float* fs;
+  float* phiP[2];  // FP32: [1] == [0] (updated in place)
+  float* CP[2];
+  float* T[2];     // 16-bit only
+  bool narrow;     // 16-bit population storage
   double* mpc_part;
   double* tot_part;
   double* red;
@@ -41,6 +46,7 @@ namespace {
 
 struct Layout {
   size_t pop, p, u, scal, mpc, tot, red, stage, mask, total;
+  int np, nscal;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -70,7 +76,11 @@ bool valid_params(const lbfz_params* p) {
 }
 
 int check_support(const lbfz_params* p) {
-  if (p && p->storage != LBFZ_STORE_F32) return LBFZ_EUNSUPPORTED;
+  if (!p) return LBFZ_OK;
+  if (p->storage != LBFZ_STORE_F32 && p->storage != LBFZ_STORE_F16 &&
+      p->storage != LBFZ_STORE_BF16)
+    return LBFZ_EINVAL;
+  if (p->storage != LBFZ_STORE_F32 && p->dim != 2) return LBFZ_EUNSUPPORTED;
   return LBFZ_OK;
 }
 
@@ -87,16 +97,21 @@ Layout layout(const lbfz_params* p, int ntiles, int npop) {
   const size_t N = (size_t)p->nx * p->ny * p->nz;
   const size_t ps = plane_stride(N);
   Layout L;
-  L.pop = align256(ps * npop * sizeof(float));
+  const bool narrow = p->storage != LBFZ_STORE_F32;
+  L.pop = align256(p->dim == 2 ? pop_bytes2d(p->storage, ps) : ps * npop * sizeof(float));
   L.p = align256(ps * sizeof(float));
   L.u = align256(ps * p->dim * sizeof(float));
   L.scal = align256(ps * sizeof(float));
+  L.np = narrow ? 3 : 2;
+  L.nscal = narrow ? 7 : 3;  // fs, phi x2, C x2, T x2  |  fs, phi, C
   L.mpc = align256((size_t)ntiles * sizeof(double));
   L.tot = align256((size_t)ntiles * 8 * sizeof(double));
   L.red = 256;
   L.stage = align256(std::max(N * LBFZ_NFIELDS * sizeof(float), N * 3 * sizeof(double)));
+  if (narrow) L.stage = std::max(L.stage, align256(N * 24 * sizeof(float)));
   L.mask = p->dim == 3 ? align256(N) : 0;
-  L.total = 2 * L.pop + 2 * L.p + 2 * L.u + 3 * L.scal + L.mpc + L.tot + L.red + L.stage + L.mask;
+  L.total = 2 * L.pop + L.np * L.p + 2 * L.u + L.nscal * L.scal + L.mpc + L.tot + L.red +
+            L.stage + L.mask;
   return L;
 }
 
@@ -195,22 +210,36 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ tot,
 
 hipError_t launch_step(lbfz_handle* h, const StepArgs& a, bool dry) {
   if (h->prm.dim == 3) return launch_step3d(h->kp, a, h->seg, dry, h->stream);
-  return launch_step2d(h->kp, a, dry, h->stream);
+  return launch_step2d(h->kp, h->storage, a, dry, h->stream);
 }
 
+// Buffers of the next step from the current level.  16-bit storage: the
+// pressure of step s is written to p[s % 3], so the step reads p[(s + 2) % 3]
+// (previous level) and decodes g with p[(s + 1) % 3] (two levels back).
 StepArgs base_args(lbfz_handle* h) {
   StepArgs a;
   std::memset(&a, 0, sizeof(a));
   const int c = h->cur;
   a.src = h->pop[c];
   a.dst = h->pop[1 - c];
-  a.p_old = h->p[c];
-  a.p_new = h->p[1 - c];
+  if (h->narrow) {
+    const int s3 = (int)(h->step % 3);
+    a.p_new = h->p[s3];
+    a.p_old = h->p[(s3 + 2) % 3];
+    a.p_ref = h->p[(s3 + 1) % 3];
+    a.T_old = h->T[c];
+    a.T_new = h->T[1 - c];
+  } else {
+    a.p_old = h->p[c];
+    a.p_new = h->p[1 - c];
+  }
   a.u_old = h->u[c];
   a.u_new = h->u[1 - c];
   a.fs = h->fs;
-  a.phiP = h->phiP;
-  a.CP = h->CP;
+  a.phiP_old = h->phiP[c];
+  a.phiP_new = h->phiP[1 - c];
+  a.CP_old = h->CP[c];
+  a.CP_new = h->CP[1 - c];
   a.mask = h->mask;
   a.mpc_part = h->mpc_part;
   return a;
@@ -261,16 +290,29 @@ int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const 
   h->ws_bytes = ws_bytes;
   h->ntiles = ntiles;
   h->npop = npop;
+  h->storage = p->storage;
+  h->narrow = p->storage != LBFZ_STORE_F32;
   char* q = h->ws;
   h->pop[0] = (float*)q; q += L.pop;
   h->pop[1] = (float*)q; q += L.pop;
-  h->p[0] = (float*)q; q += L.p;
-  h->p[1] = (float*)q; q += L.p;
+  for (int k = 0; k < L.np; ++k) {
+    h->p[k] = (float*)q;
+    q += L.p;
+  }
   h->u[0] = (float*)q; q += L.u;
   h->u[1] = (float*)q; q += L.u;
   h->fs = (float*)q; q += L.scal;
-  h->phiP = (float*)q; q += L.scal;
-  h->CP = (float*)q; q += L.scal;
+  h->phiP[0] = (float*)q; q += L.scal;
+  h->CP[0] = (float*)q; q += L.scal;
+  if (h->narrow) {
+    h->phiP[1] = (float*)q; q += L.scal;
+    h->CP[1] = (float*)q; q += L.scal;
+    h->T[0] = (float*)q; q += L.scal;
+    h->T[1] = (float*)q; q += L.scal;
+  } else {
+    h->phiP[1] = h->phiP[0];
+    h->CP[1] = h->CP[0];
+  }
   h->mpc_part = (double*)q; q += L.mpc;
   h->tot_part = (double*)q; q += L.tot;
   h->red = (double*)q; q += L.red;
@@ -292,7 +334,8 @@ int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const 
       rc = LBFZ_EHIP;
       break;
     }
-    StateArgs S{h->p[0], h->p[1], h->u[0], h->u[1], h->fs, h->phiP, h->CP};
+    StateArgs S{h->p[0], h->p[1], h->narrow ? h->p[2] : nullptr, h->u[0], h->u[1], h->fs,
+                h->phiP[0], h->CP[0], h->narrow ? h->T[0] : nullptr};
     if (h->mask &&
         hipMemcpyAsync(h->mask, mask, N, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
       rc = LBFZ_EHIP;
@@ -300,8 +343,8 @@ int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const 
     }
     const hipError_t e = p->dim == 3 ? launch_init3d(h->kp, st, st + N, st + 2 * N, h->mask,
                                                      h->pop[0], h->pop[1], S, h->stream)
-                                     : launch_init2d(h->kp, st, st + N, st + 2 * N, h->pop[0], S,
-                                                     h->stream);
+                                     : launch_init2d(h->kp, h->storage, st, st + N, st + 2 * N,
+                                                     h->pop[0], S, h->stream);
     if (e != hipSuccess) {
       rc = LBFZ_EHIP;
       break;
@@ -375,17 +418,22 @@ int lbfz_totals(lbfz_handle* h, lbfz_totals_t* out) {
 }
 
 namespace {
-// Device planes of the exported state, in the documented order.
+// Device planes of the exported state, in the documented order.  16-bit
+// storage: the population planes are the FP32 decode in the stage buffer.
 int state_planes(lbfz_handle* h, std::vector<float*>& planes) {
-  const size_t ps = (size_t)h->kp.ps;
+  const size_t ps = (size_t)h->kp.ps, N = (size_t)h->kp.N;
   planes.clear();
-  float* pop = h->pop[h->cur];
-  for (int q = 0; q < h->npop; ++q) planes.push_back(pop + q * ps);
+  if (h->narrow) {
+    for (int q = 0; q < h->npop; ++q) planes.push_back(h->stage + q * N);
+  } else {
+    float* pop = h->pop[h->cur];
+    for (int q = 0; q < h->npop; ++q) planes.push_back(pop + q * ps);
+  }
   planes.push_back(h->fs);
-  planes.push_back(h->p[h->cur]);
+  planes.push_back(h->narrow ? h->p[(h->step + 2) % 3] : h->p[h->cur]);
   for (int a = 0; a < h->prm.dim; ++a) planes.push_back(h->u[h->cur] + a * ps);
-  planes.push_back(h->phiP);
-  planes.push_back(h->CP);
+  planes.push_back(h->phiP[h->cur]);
+  planes.push_back(h->CP[h->cur]);
   return (int)planes.size();
 }
 }  // namespace
@@ -402,6 +450,7 @@ int lbfz_get_state(lbfz_handle* h, float* host_dst) {
   const size_t N = (size_t)h->kp.N;
   std::vector<float*> planes;
   const int np = state_planes(h, planes);
+  if (h->narrow) HIPCHK(launch_export2d(h->kp, h->storage, base_args(h), h->stage, h->stream));
   for (int k = 0; k < np; ++k)
     HIPCHK(hipMemcpyAsync(host_dst + k * N, planes[k], N * sizeof(float), hipMemcpyDeviceToHost,
                           h->stream));
@@ -417,6 +466,15 @@ int lbfz_set_state(lbfz_handle* h, const float* host_src) {
   for (int k = 0; k < np; ++k)
     HIPCHK(hipMemcpyAsync(planes[k], host_src + k * N, N * sizeof(float), hipMemcpyHostToDevice,
                           h->stream));
+  if (h->narrow) {
+    // encode against the imported phi, C and p (p doubles as the g reference)
+    StepArgs a = base_args(h);
+    HIPCHK(hipMemcpyAsync((void*)a.p_ref, a.p_old, N * sizeof(float), hipMemcpyDeviceToDevice,
+                          h->stream));
+    a.dst = h->pop[h->cur];
+    a.T_new = h->T[h->cur];
+    HIPCHK(launch_import2d(h->kp, h->storage, a, h->stage, h->stream));
+  }
   HIPCHK(hipStreamSynchronize(h->stream));
   return LBFZ_OK;
 }

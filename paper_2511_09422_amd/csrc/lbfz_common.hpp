@@ -77,7 +77,10 @@ struct Closure {
 __device__ __forceinline__ Closure closure(const KParams& P, float phi0, float E0, float D) {
   Closure c;
   const float psi = clamp01(0.5f * (1.0f + phi0));
-  c.phi = phi0 * frcp(1.0f - 0.5f * D);
+  // correctly rounded: the phase-field budget sum f(n+1) - sum f(n) = phi D
+  // holds only through phi0 = phi (1 - D / 2), and a biased quotient would
+  // accumulate in it
+  c.phi = phi0 / (1.0f - 0.5f * D);
   float T0, fs0;
   enthalpy_map(P, E0, psi, T0, fs0);
   const float rc0 = interp(c.phi, fs0, P.rho_l, P.rho_g, P.rho_s) *

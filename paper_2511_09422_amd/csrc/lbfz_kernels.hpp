@@ -10,8 +10,11 @@
 namespace lbfz {
 
 // Buffers of one step.  src/dst: population buffers; p, u: double-buffered
-// previous-time-level fields read through stencils; fs, phiP, CP: pointwise
-// previous-time-level fields updated in place.  DRY launches evaluate the
+// previous-time-level fields read through stencils; fs: pointwise
+// previous-time-level f_s updated in place; phiP, CP: previous-level phi and C
+// (FP32 storage: one buffer, old == new, updated in place; 16-bit storage:
+// double-buffered, they are also the populations' decode references, as are
+// T and p_ref, the pressure two levels back).  DRY launches evaluate the
 // macroscopic fields of the current time level into out[] (any entry may be
 // null) and per-tile totals into tot_part[tile * 8 + k].
 struct StepArgs {
@@ -19,26 +22,38 @@ struct StepArgs {
   float* dst;
   const float* p_old;
   float* p_new;
-  const float* u_old;  // [dim][N]
+  const float* p_ref;  // 16-bit storage only
+  const float* u_old;  // [dim][ps]
   float* u_new;
   float* fs;
-  float* phiP;
-  float* CP;
+  const float* phiP_old;
+  float* phiP_new;
+  const float* CP_old;
+  float* CP_new;
+  const float* T_old;  // 16-bit storage only
+  float* T_new;
   const uint8_t* mask;  // 3D obstacle mask or null
   double* mpc_part;     // [ntiles]
   float* out[9];
   double* tot_part;     // [ntiles][8]
 };
-using Step2DArgs = StepArgs;
 
+// Buffers the initial state is written to (pop: the buffer the first step
+// reads; pC, TA: 16-bit storage only).
 struct StateArgs {
-  float *pA, *pB, *uA, *uB, *fs, *phiP, *CP;
+  float *pA, *pB, *pC, *uA, *uB, *fs, *phiA, *CA, *TA;
 };
 
 int tiles2d(int nx, int ny, int* nbx, int* nby);
-hipError_t launch_init2d(const KParams& P, const double* phi, const double* T, const double* C,
-                         float* pop, const StateArgs& S, hipStream_t st);
-hipError_t launch_step2d(const KParams& P, const StepArgs& A, bool dry, hipStream_t st);
+size_t pop_bytes2d(int storage, size_t ps);
+hipError_t launch_init2d(const KParams& P, int storage, const double* phi, const double* T,
+                         const double* C, float* pop, const StateArgs& S, hipStream_t st);
+hipError_t launch_step2d(const KParams& P, int storage, const StepArgs& A, bool dry,
+                         hipStream_t st);
+hipError_t launch_export2d(const KParams& P, int storage, const StepArgs& A, float* dst,
+                           hipStream_t st);
+hipError_t launch_import2d(const KParams& P, int storage, const StepArgs& A, const float* src,
+                           hipStream_t st);
 
 int tiles3d(int nx, int ny, int nz, int seg, int* nbx, int* nby, int* nbz);
 size_t lds3d_bytes();
