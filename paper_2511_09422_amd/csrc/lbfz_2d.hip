@@ -64,50 +64,6 @@ constexpr float W9[9] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
                          1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
 constexpr float W5[5] = {1.f / 3, 1.f / 6, 1.f / 6, 1.f / 6, 1.f / 6};
 
-// 16-bit offset scales (powers of two: exact).
-constexpr float SC_F = 256.0f, SC_G = 16384.0f, SC_H = 1024.0f, SC_L = 4096.0f;
-
-// Word 3 of a CDNA buffer descriptor: 32-bit data format, no swizzle.
-constexpr int kBufWord3 = 0x00020000;
-
-// Buffer descriptor of `bytes` bytes at `base`; accesses through it are one
-// buffer instruction each: descriptor and plane offset wave-uniform (scalar
-// registers), the lane supplies only a 32-bit byte offset.  Offsets outside
-// the range read 0 and write nothing.
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-__device__ __forceinline__ rsrc_t rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
-                                           kBufWord3);
-}
-__device__ __forceinline__ float ld(rsrc_t r, uint32_t off, uint32_t soff = 0) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
-}
-__device__ __forceinline__ void st(rsrc_t r, uint32_t off, uint32_t soff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, (int)soff, 0);
-}
-__device__ __forceinline__ uint16_t ld16(rsrc_t r, uint32_t off, uint32_t soff) {
-  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0);
-}
-__device__ __forceinline__ void st16(rsrc_t r, uint32_t off, uint32_t soff, uint16_t v) {
-  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, (int)soff, 0);
-}
-
-// 16-bit storage formats: round to nearest even either way.
-template <int ST>
-__device__ __forceinline__ float dec16(uint16_t b) {
-  if constexpr (ST == LBFZ_STORE_F16)
-    return (float)__builtin_bit_cast(_Float16, b);
-  else
-    return __builtin_bit_cast(float, (uint32_t)b << 16);
-}
-template <int ST>
-__device__ __forceinline__ uint16_t enc16(float v) {
-  if constexpr (ST == LBFZ_STORE_F16)
-    return __builtin_bit_cast(uint16_t, (_Float16)v);
-  else
-    return __builtin_bit_cast(uint16_t, (__bf16)v);
-}
-
 // Descriptors of one step.  F32: population sets incl. rest (plane i of a set
 // at byte offset i * pb).  16-bit: rest = the four FP32 rest planes, f/g/h/l =
 // the moving 16-bit planes of each set (plane i - 1 at (i - 1) * hb).
@@ -155,12 +111,6 @@ __device__ __forceinline__ Bufs make_bufs(const KParams& P, const StepArgs& A) {
   B.p_old = rsrc(A.p_old, B.pb);
   B.u_old = rsrc(A.u_old, 2 * B.pb);
   return B;
-}
-
-// Periodic image of v in [-n, 2n); positions beyond that (staged only by
-// partial tiles, never read for a node of the grid) are clamped into it.
-__device__ __forceinline__ int wrap_near(int v, int n) {
-  return v < 0 ? v + n : (v >= n ? min(v - n, n - 1) : v);
 }
 
 // Wall-normal (y) coordinate -> stored row.  side: 0 inside, -1 ghost below
@@ -566,7 +516,7 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, StepArgs A) {
       const float geq = pn * kInvCs2 * W9[i] + rho * si;
       geq_sum += geq;
       push(B.dg, i, g[i] - (g[i] - geq) * P.itau_g + P.wg * G[i], SC_G,
-           [&](int dy, int dx) { return (3.0f * W9[i]) * s_p[cy + dy][cx + dx]; });
+           [&](int dy, int dx) { return W9[i] * (3.0f * s_p[cy + dy][cx + dx]); });
     }
     put_rest(B.dg, SG, g[0] - (g[0] + geq_sum) * P.itau_g + P.wg * G[0]);
   }

@@ -25,10 +25,11 @@ struct lbfz_handle {
   float* pop[2];
   float* p[3];     // FP32: two levels; 16-bit: three (p_ref)
   float* u[2];
-  float* fs;
-  float* phiP[2];  // FP32: [1] == [0] (updated in place)
+  float* fs;       // 2D
+  float* phiP[2];  // 2D; FP32: [1] == [0] (updated in place)
   float* CP[2];
-  float* T[2];     // 16-bit only
+  float* T[2];     // 2D 16-bit only
+  float* cf[2];    // 3D closure fields (phi, T, C, f_s, div u planes) per level
   bool narrow;     // 16-bit population storage
   double* mpc_part;
   double* tot_part;
@@ -39,7 +40,6 @@ struct lbfz_handle {
   int64_t step;
   int ntiles;
   int npop;
-  int seg;  // 3D: z planes per block
 };
 
 namespace {
@@ -80,15 +80,13 @@ int check_support(const lbfz_params* p) {
   if (p->storage != LBFZ_STORE_F32 && p->storage != LBFZ_STORE_F16 &&
       p->storage != LBFZ_STORE_BF16)
     return LBFZ_EINVAL;
-  if (p->storage != LBFZ_STORE_F32 && p->dim != 2) return LBFZ_EUNSUPPORTED;
   return LBFZ_OK;
 }
 
 int npop_of(const lbfz_params* p) { return p->dim == 3 ? 40 : 24; }
-int seg_of(const lbfz_params* p) { return p->dim == 3 ? std::min(32, p->nz) : 1; }
 
 int tiles_of(const lbfz_params* p, int* nbx, int* nby, int* nbz) {
-  if (p->dim == 3) return tiles3d(p->nx, p->ny, p->nz, seg_of(p), nbx, nby, nbz);
+  if (p->dim == 3) return tiles3d(p->nx, p->ny, p->nz, nbx, nby, nbz);
   *nbz = 1;
   return tiles2d(p->nx, p->ny, nbx, nby);
 }
@@ -98,17 +96,19 @@ Layout layout(const lbfz_params* p, int ntiles, int npop) {
   const size_t ps = plane_stride(N);
   Layout L;
   const bool narrow = p->storage != LBFZ_STORE_F32;
-  L.pop = align256(p->dim == 2 ? pop_bytes2d(p->storage, ps) : ps * npop * sizeof(float));
+  L.pop = align256(p->dim == 2 ? pop_bytes2d(p->storage, ps) : pop_bytes3d(p->storage, ps));
   L.p = align256(ps * sizeof(float));
   L.u = align256(ps * p->dim * sizeof(float));
   L.scal = align256(ps * sizeof(float));
   L.np = narrow ? 3 : 2;
-  L.nscal = narrow ? 7 : 3;  // fs, phi x2, C x2, T x2  |  fs, phi, C
+  // 2D: fs, phi x2, C x2, T x2 (16-bit) | fs, phi, C (FP32); 3D: two levels of
+  // the five closure-field planes
+  L.nscal = p->dim == 3 ? 10 : (narrow ? 7 : 3);
   L.mpc = align256((size_t)ntiles * sizeof(double));
   L.tot = align256((size_t)ntiles * 8 * sizeof(double));
   L.red = 256;
   L.stage = align256(std::max(N * LBFZ_NFIELDS * sizeof(float), N * 3 * sizeof(double)));
-  if (narrow) L.stage = std::max(L.stage, align256(N * 24 * sizeof(float)));
+  if (narrow) L.stage = std::max(L.stage, align256(N * npop * sizeof(float)));
   L.mask = p->dim == 3 ? align256(N) : 0;
   L.total = 2 * L.pop + L.np * L.p + 2 * L.u + L.nscal * L.scal + L.mpc + L.tot + L.red +
             L.stage + L.mask;
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ tot,
   } while (0)
 
 hipError_t launch_step(lbfz_handle* h, const StepArgs& a, bool dry) {
-  if (h->prm.dim == 3) return launch_step3d(h->kp, a, h->seg, dry, h->stream);
+  if (h->prm.dim == 3) return launch_step3d(h->kp, h->storage, a, dry, h->stream);
   return launch_step2d(h->kp, h->storage, a, dry, h->stream);
 }
 
@@ -235,11 +235,16 @@ StepArgs base_args(lbfz_handle* h) {
   }
   a.u_old = h->u[c];
   a.u_new = h->u[1 - c];
-  a.fs = h->fs;
-  a.phiP_old = h->phiP[c];
-  a.phiP_new = h->phiP[1 - c];
-  a.CP_old = h->CP[c];
-  a.CP_new = h->CP[1 - c];
+  if (h->prm.dim == 3) {
+    a.cf_old = h->cf[c];
+    a.cf_new = h->cf[1 - c];
+  } else {
+    a.fs = h->fs;
+    a.phiP_old = h->phiP[c];
+    a.phiP_new = h->phiP[1 - c];
+    a.CP_old = h->CP[c];
+    a.CP_new = h->CP[1 - c];
+  }
   a.mask = h->mask;
   a.mpc_part = h->mpc_part;
   return a;
@@ -284,7 +289,6 @@ int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const 
   std::memset(h, 0, sizeof(*h));
   h->prm = *p;
   h->kp = make_kparams(p, nbx, nby, nbz);
-  h->seg = seg_of(p);
   h->stream = (hipStream_t)stream;
   h->ws = (char*)d_workspace;
   h->ws_bytes = ws_bytes;
@@ -301,17 +305,24 @@ int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const 
   }
   h->u[0] = (float*)q; q += L.u;
   h->u[1] = (float*)q; q += L.u;
-  h->fs = (float*)q; q += L.scal;
-  h->phiP[0] = (float*)q; q += L.scal;
-  h->CP[0] = (float*)q; q += L.scal;
-  if (h->narrow) {
-    h->phiP[1] = (float*)q; q += L.scal;
-    h->CP[1] = (float*)q; q += L.scal;
-    h->T[0] = (float*)q; q += L.scal;
-    h->T[1] = (float*)q; q += L.scal;
+  const size_t ps = (size_t)h->kp.ps;
+  if (p->dim == 3) {
+    h->cf[0] = (float*)q;
+    h->cf[1] = h->cf[0] + 5 * ps;
+    q += 10 * L.scal;
   } else {
-    h->phiP[1] = h->phiP[0];
-    h->CP[1] = h->CP[0];
+    h->fs = (float*)q; q += L.scal;
+    h->phiP[0] = (float*)q; q += L.scal;
+    h->CP[0] = (float*)q; q += L.scal;
+    if (h->narrow) {
+      h->phiP[1] = (float*)q; q += L.scal;
+      h->CP[1] = (float*)q; q += L.scal;
+      h->T[0] = (float*)q; q += L.scal;
+      h->T[1] = (float*)q; q += L.scal;
+    } else {
+      h->phiP[1] = h->phiP[0];
+      h->CP[1] = h->CP[0];
+    }
   }
   h->mpc_part = (double*)q; q += L.mpc;
   h->tot_part = (double*)q; q += L.tot;
@@ -335,14 +346,21 @@ int lbfz_create(const lbfz_params* p, const double* phi, const double* T, const 
       break;
     }
     StateArgs S{h->p[0], h->p[1], h->narrow ? h->p[2] : nullptr, h->u[0], h->u[1], h->fs,
-                h->phiP[0], h->CP[0], h->narrow ? h->T[0] : nullptr};
+                h->phiP[0], h->CP[0], h->narrow ? h->T[0] : nullptr, nullptr};
+    if (p->dim == 3) {  // previous-level closure fields: phi, T, C, f_s, div u
+      S.phiA = h->cf[0];
+      S.TA = h->cf[0] + ps;
+      S.CA = h->cf[0] + 2 * ps;
+      S.fs = h->cf[0] + 3 * ps;
+      S.DA = h->cf[0] + 4 * ps;
+    }
     if (h->mask &&
         hipMemcpyAsync(h->mask, mask, N, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
       rc = LBFZ_EHIP;
       break;
     }
-    const hipError_t e = p->dim == 3 ? launch_init3d(h->kp, st, st + N, st + 2 * N, h->mask,
-                                                     h->pop[0], h->pop[1], S, h->stream)
+    const hipError_t e = p->dim == 3 ? launch_init3d(h->kp, h->storage, st, st + N, st + 2 * N,
+                                                     h->mask, h->pop[0], h->pop[1], S, h->stream)
                                      : launch_init2d(h->kp, h->storage, st, st + N, st + 2 * N,
                                                      h->pop[0], S, h->stream);
     if (e != hipSuccess) {
@@ -429,11 +447,12 @@ int state_planes(lbfz_handle* h, std::vector<float*>& planes) {
     float* pop = h->pop[h->cur];
     for (int q = 0; q < h->npop; ++q) planes.push_back(pop + q * ps);
   }
-  planes.push_back(h->fs);
+  float* cf = h->cf[h->cur];
+  planes.push_back(h->prm.dim == 3 ? cf + 3 * ps : h->fs);
   planes.push_back(h->narrow ? h->p[(h->step + 2) % 3] : h->p[h->cur]);
   for (int a = 0; a < h->prm.dim; ++a) planes.push_back(h->u[h->cur] + a * ps);
-  planes.push_back(h->phiP[h->cur]);
-  planes.push_back(h->CP[h->cur]);
+  planes.push_back(h->prm.dim == 3 ? cf : h->phiP[h->cur]);
+  planes.push_back(h->prm.dim == 3 ? cf + 2 * ps : h->CP[h->cur]);
   return (int)planes.size();
 }
 }  // namespace
@@ -450,7 +469,10 @@ int lbfz_get_state(lbfz_handle* h, float* host_dst) {
   const size_t N = (size_t)h->kp.N;
   std::vector<float*> planes;
   const int np = state_planes(h, planes);
-  if (h->narrow) HIPCHK(launch_export2d(h->kp, h->storage, base_args(h), h->stage, h->stream));
+  if (h->narrow)
+    HIPCHK(h->prm.dim == 3
+               ? launch_export3d(h->kp, h->storage, base_args(h), h->stage, h->stream)
+               : launch_export2d(h->kp, h->storage, base_args(h), h->stage, h->stream));
   for (int k = 0; k < np; ++k)
     HIPCHK(hipMemcpyAsync(host_dst + k * N, planes[k], N * sizeof(float), hipMemcpyDeviceToHost,
                           h->stream));
@@ -472,8 +494,12 @@ int lbfz_set_state(lbfz_handle* h, const float* host_src) {
     HIPCHK(hipMemcpyAsync((void*)a.p_ref, a.p_old, N * sizeof(float), hipMemcpyDeviceToDevice,
                           h->stream));
     a.dst = h->pop[h->cur];
-    a.T_new = h->T[h->cur];
-    HIPCHK(launch_import2d(h->kp, h->storage, a, h->stage, h->stream));
+    if (h->prm.dim == 3) {
+      HIPCHK(launch_import3d(h->kp, h->storage, a, h->stage, h->stream));
+    } else {
+      a.T_new = h->T[h->cur];
+      HIPCHK(launch_import2d(h->kp, h->storage, a, h->stage, h->stream));
+    }
   }
   HIPCHK(hipStreamSynchronize(h->stream));
   return LBFZ_OK;

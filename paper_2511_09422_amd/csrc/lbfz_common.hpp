@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/lbfz.h"
+
 namespace lbfz {
 
 constexpr float kCs2 = 1.0f / 3.0f;
@@ -106,6 +108,60 @@ __device__ __forceinline__ double block_sum(double v, double* sred) {
     for (int w = 0; w < NT / 64; ++w) s += sred[w];
   }
   return s;  // valid on thread 0
+}
+
+// Word 3 of a CDNA buffer descriptor: 32-bit data format, no swizzle.
+constexpr int kBufWord3 = 0x00020000;
+
+// Buffer descriptor of `bytes` bytes at `base`; accesses through it are one
+// buffer instruction each: descriptor and plane offset wave-uniform (scalar
+// registers), the lane supplies only a 32-bit byte offset.  Offsets outside
+// the range read 0 and write nothing.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           kBufWord3);
+}
+__device__ __forceinline__ float ld(rsrc_t r, uint32_t off, uint32_t soff = 0) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
+}
+__device__ __forceinline__ void st(rsrc_t r, uint32_t off, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, (int)soff, 0);
+}
+__device__ __forceinline__ uint16_t ld16(rsrc_t r, uint32_t off, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0);
+}
+__device__ __forceinline__ uint8_t ld8(rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void st16(rsrc_t r, uint32_t off, uint32_t soff, uint16_t v) {
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, (int)soff, 0);
+}
+
+// 16-bit storage: offsets from the reference are scaled by these powers of two
+// (exact) so that typical offsets sit in the FP16 normal range.
+constexpr float SC_F = 256.0f, SC_G = 16384.0f, SC_H = 1024.0f, SC_L = 4096.0f;
+
+// 16-bit storage formats: round to nearest even either way.
+template <int ST>
+__device__ __forceinline__ float dec16(uint16_t b) {
+  if constexpr (ST == LBFZ_STORE_F16)
+    return (float)__builtin_bit_cast(_Float16, b);
+  else
+    return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+template <int ST>
+__device__ __forceinline__ uint16_t enc16(float v) {
+  if constexpr (ST == LBFZ_STORE_F16)
+    return __builtin_bit_cast(uint16_t, (_Float16)v);
+  else
+    return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
+// Periodic image of v in [-n, 2n); positions beyond that (staged only by
+// partial tiles, never read for a node of the grid) are clamped into it.
+__device__ __forceinline__ int wrap_near(int v, int n) {
+  return v < 0 ? v + n : (v >= n ? min(v - n, n - 1) : v);
 }
 
 // Map a hardware block index to a logical tile index so that each of the 8

@@ -32,6 +32,8 @@ struct StepArgs {
   float* CP_new;
   const float* T_old;  // 16-bit storage only
   float* T_new;
+  const float* cf_old;  // 3D closure fields phi, T, C, f_s, div u [5][ps]: previous level
+  float* cf_new;        //   and this level
   const uint8_t* mask;  // 3D obstacle mask or null
   double* mpc_part;     // [ntiles]
   float* out[9];
@@ -39,9 +41,9 @@ struct StepArgs {
 };
 
 // Buffers the initial state is written to (pop: the buffer the first step
-// reads; pC, TA: 16-bit storage only).
+// reads; pC: 16-bit storage only; TA: 16-bit 2D and 3D; DA: 3D only).
 struct StateArgs {
-  float *pA, *pB, *pC, *uA, *uB, *fs, *phiA, *CA, *TA;
+  float *pA, *pB, *pC, *uA, *uB, *fs, *phiA, *CA, *TA, *DA;
 };
 
 int tiles2d(int nx, int ny, int* nbx, int* nby);
@@ -55,11 +57,16 @@ hipError_t launch_export2d(const KParams& P, int storage, const StepArgs& A, flo
 hipError_t launch_import2d(const KParams& P, int storage, const StepArgs& A, const float* src,
                            hipStream_t st);
 
-int tiles3d(int nx, int ny, int nz, int seg, int* nbx, int* nby, int* nbz);
-size_t lds3d_bytes();
-hipError_t launch_init3d(const KParams& P, const double* phi, const double* T, const double* C,
-                         const uint8_t* mask, float* popA, float* popB, const StateArgs& S,
+int tiles3d(int nx, int ny, int nz, int* nbx, int* nby, int* nbz);
+size_t pop_bytes3d(int storage, size_t ps);
+hipError_t launch_init3d(const KParams& P, int storage, const double* phi, const double* T,
+                         const double* C, const uint8_t* mask, float* popA, float* popB,
+                         const StateArgs& S, hipStream_t st);
+hipError_t launch_step3d(const KParams& P, int storage, const StepArgs& A, bool dry,
                          hipStream_t st);
-hipError_t launch_step3d(const KParams& P, const StepArgs& A, int seg, bool dry, hipStream_t st);
+hipError_t launch_export3d(const KParams& P, int storage, const StepArgs& A, float* dst,
+                           hipStream_t st);
+hipError_t launch_import3d(const KParams& P, int storage, const StepArgs& A, const float* src,
+                           hipStream_t st);
 
 }  // namespace lbfz

@@ -5,8 +5,8 @@ population, previous-level field and macroscopic field), trajectories within
 1e-4 or three times the spread of the FP64 oracle under FP32-sized noise.
 
 Cases: the 16^3 droplet with its spherical obstacle, a 40x20x70 box (ragged
-xy tiles and three z segments of the z-march), a fully periodic box, and the
-64^3 copy of the 3D benchmark workload."""
+64 x 4 tiles in x and y, many z planes), a fully periodic box, and the 64^3
+copy of the 3D benchmark workload."""
 import os
 
 import numpy as np
