@@ -6,7 +6,10 @@ Workload: the 2D droplet freezing case scaled to a 2048 x 2048 grid (drop
 radius 512 on the cold wall, interface width 4, D2Q9 flow + D2Q5 phase
 field, enthalpy and solute), synthetic seeded initial fields, inputs resident
 in HBM when timing starts.  One step = one launch of the fused step kernel =
-one pass of the whole method over the grid.  Prints one JSON line.
+one pass of the whole method over the grid.  The headline is FP32 storage;
+the FP16 and BF16 storage forms and the 3D droplet (256^3 with its obstacle,
+two launches per step) are timed the same way and reported in the same JSON
+line.
 
 The roofline entry uses the algorithmic bytes of one node update (every
 population read once and written once, plus the previous-time-level fields
@@ -30,10 +33,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 POP_BYTES = {"f32": 4, "f16": 2, "bf16": 2}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2d_2048.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # sources of the timed kernel: the stored counter figures hold only while
 # these are unchanged
 KERNEL_SOURCES = ("paper_2511_09422_amd/csrc/lbfz_2d.hip",
+                  "paper_2511_09422_amd/csrc/lbfz_3d.hip",
                   "paper_2511_09422_amd/csrc/lbfz_common.hpp",
                   "paper_2511_09422_amd/csrc/lbfz_kernels.hpp")
 
@@ -55,6 +59,14 @@ def bytes_per_node(storage: str) -> int:
     # 4 FP32 rest + 20 16-bit moving populations read + written; FP32 scalars:
     # 8 read (f_s, p, p two levels back, u_x, u_y, phi, C, T) and 7 written
     return 2 * (4 * 4 + 20 * POP_BYTES[storage]) + (8 + 7) * 4
+
+
+def bytes_per_node3d(storage: str) -> int:
+    # the scheme's minimum: 40 populations (D3Q19 + 3 x D3Q7) read + written
+    # and 8 FP32 previous-level scalars (f_s, p, u, phi, C, div u) read +
+    # written; the two-launch design moves more (closure fields through HBM,
+    # f, h, l read twice), which the measured traffic shows
+    return 2 * 40 * POP_BYTES[storage] + 2 * 8 * 4
 
 
 def cpu_baseline(cfg, phi, T, C, budget_s: float = 12.0) -> dict:
@@ -93,12 +105,12 @@ def load_traffic(kernel_tag: str):
     return None if e is None else e.get("bytes_per_launch")
 
 
-def time_form(cfg, phi, T, C, storage: str, warmup: int, steps: int) -> dict:
+def time_form(cfg, phi, T, C, storage: str, warmup: int, steps: int, mask=None) -> dict:
     """Time `steps` steps of one storage form with HIP events on the solver's
     stream, after `warmup` untimed steps."""
     import torch
     from paper_2511_09422_amd.lbfz import Solver
-    solver = Solver(cfg, phi, T, C, device=0, storage=storage)
+    solver = Solver(cfg, phi, T, C, mask=mask, device=0, storage=storage)
     stream = solver.stream
     solver.step(warmup)
     torch.cuda.synchronize()
@@ -118,8 +130,8 @@ def time_form(cfg, phi, T, C, storage: str, warmup: int, steps: int) -> dict:
     if tot["nonfinite"]:
         print(f"bench: non-finite state ({storage})", file=sys.stderr)
         sys.exit(1)
-    N = cfg["nx"] * cfg["ny"]
-    bpn = bytes_per_node(storage)
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    bpn = bytes_per_node(storage) if cfg["dim"] == 2 else bytes_per_node3d(storage)
     achieved = bpn * N / (ms_per_step * 1e-3) / 1e9
     return {"ms_per_step": ms_per_step, "mlups": N / (ms_per_step * 1e-3) / 1e6,
             "bytes_per_node": bpn, "achieved": achieved, "wall": wall}
@@ -135,6 +147,9 @@ def main():
     ap.add_argument("--forms", default="f16,bf16",
                     help="other storage forms timed on the same workload ('' for none)")
     ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--n3d", type=int, default=256,
+                    help="side of the 3D droplet workload timed alongside (0: skip)")
+    ap.add_argument("--steps3d", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
@@ -170,6 +185,32 @@ def main():
                                  "frac": round(r["achieved"] / HBM_PEAK_GBS, 4),
                                  "bytes_per_node": r["bytes_per_node"],
                                  "traffic": load_traffic(f"k_step2d_{f}_{n}")}}
+    droplet3d = None
+    if args.n3d:
+        from paper_2511_09422_amd.workloads import droplet_3d
+        m = args.n3d
+        cfg3, phi3, T3, C3, mask3 = droplet_3d(m, R=m / 4.0, imp_R=12.0 * m / 256.0, seed=1)
+        forms3 = {}
+        base3 = None
+        for f in [args.storage] + forms:
+            r = time_form(cfg3, phi3, T3, C3, f, max(1, args.warmup // 10), args.steps3d,
+                          mask=mask3)
+            print(f"bench: 3D {f} {r['ms_per_step'] * 1e3:.1f} us/step", file=sys.stderr,
+                  flush=True)
+            if base3 is None:
+                base3 = r
+            forms3[f] = {"value": round(r["mlups"], 2), "unit": "MLUPS",
+                         "ms_per_step": round(r["ms_per_step"], 6),
+                         "speedup_vs_" + args.storage:
+                             round(base3["ms_per_step"] / r["ms_per_step"], 3),
+                         "roofline": {"bound": "hbm", "achieved": round(r["achieved"], 1),
+                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": round(r["achieved"] / HBM_PEAK_GBS, 4),
+                                      "bytes_per_node": r["bytes_per_node"],
+                                      "traffic": load_traffic(f"k_step3d_{f}_{m}")}}
+        droplet3d = {"workload": f"3D droplet freezing {m}^3, R={m // 4}, obstacle radius "
+                                 f"{12 * m // 256}, D3Q19+3xD3Q7, FP32 arithmetic",
+                     "steps": args.steps3d, "forms": forms3}
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -201,6 +242,8 @@ def main():
     }
     if other:
         out["storage_forms"] = other
+    if droplet3d:
+        out["droplet3d"] = droplet3d
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, phi, T, C)
     print(json.dumps(out), flush=True)

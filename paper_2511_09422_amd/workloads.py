@@ -88,7 +88,9 @@ def droplet_3d(n: int = 256, R: float = 64.0, imp_R: float = 12.0, seed: int = 1
     p = base_params(dim=3, nx=n, ny=n, nz=n, **over)
     eps = p["eps"]
     dx, dy, h = impurity_offset(seed, scale=n / 256.0)
-    z, y, x = np.meshgrid(*(np.arange(n, dtype=np.float64),) * 3, indexing="ij")
+    # broadcast axes ([z][y][x]) instead of full coordinate grids
+    a = np.arange(n, dtype=np.float64)
+    z, y, x = a[:, None, None], a[None, :, None], a[None, None, :]
     c = n / 2.0
     d = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z + 0.5) ** 2)
     phi = np.tanh((R - d) / (SQRT2 * eps))
