@@ -137,6 +137,54 @@ def time_form(cfg, phi, T, C, storage: str, warmup: int, steps: int, mask=None) 
             "bytes_per_node": bpn, "achieved": achieved, "wall": wall}
 
 
+def time_sweep(ncases: int, steps: int, case_steps: int, storage: str) -> dict:
+    """The batched parameter sweep: ncases grids drawn by sweep_case(k), tuned,
+    then `steps` batched steps timed with HIP events (graph replays), and a
+    few steps of the same grids with plain one-grid-at-a-time launches."""
+    import torch
+    from paper_2511_09422_amd.lbfz import Batch
+    from paper_2511_09422_amd.workloads import sweep_case
+    cases = [sweep_case(k) for k in range(ncases)]
+    nodes = sum(c[0]["nx"] * c[0]["ny"] for c in cases)
+    b = Batch(cases, device=0, storage=storage)
+    b.tune(4)
+    b.step(24)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(b.stream)
+    b.step(steps)
+    ev1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    seq_steps = max(2, steps // 20)
+    ev0.record(b.stream)
+    b.step_sequential(seq_steps)
+    ev1.record(b.stream)
+    torch.cuda.synchronize()
+    ms_seq = ev0.elapsed_time(ev1) / seq_steps
+    bad = sum(b.totals(i)["nonfinite"] for i in range(ncases))
+    groups = b.groups()
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    if bad:
+        print("bench: non-finite state in the sweep", file=sys.stderr)
+        sys.exit(1)
+    print(f"bench: sweep {ncases} grids {ms * 1e3:.1f} us/step batched, "
+          f"{ms_seq * 1e3:.1f} us/step sequential", file=sys.stderr, flush=True)
+    return {"value": round(ncases / (case_steps * ms * 1e-3), 3), "unit": "cases/s",
+            "cases": ncases, "steps_per_case": case_steps, "nodes": nodes,
+            "workload": "sweep_case(k), k < cases: side in {64,128,256,512}, sigma_T, "
+                        "Stefan number, rho_s/rho_l, C0 drawn per case; 2D droplet",
+            "storage": storage, "ms_per_step": round(ms, 6), "steps_timed": steps,
+            "mlups": round(nodes / (ms * 1e-3) / 1e6, 1),
+            "sequential": {"ms_per_step": round(ms_seq, 6), "steps_timed": seq_steps,
+                           "value": round(ncases / (case_steps * ms_seq * 1e-3), 3)},
+            "speedup_vs_sequential": round(ms_seq / ms, 3),
+            "groups": groups}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +198,11 @@ def main():
     ap.add_argument("--n3d", type=int, default=256,
                     help="side of the 3D droplet workload timed alongside (0: skip)")
     ap.add_argument("--steps3d", type=int, default=200)
+    ap.add_argument("--sweep-cases", type=int, default=512,
+                    help="grids of the batched parameter sweep timed alongside (0: skip)")
+    ap.add_argument("--sweep-steps", type=int, default=240)
+    ap.add_argument("--sweep-case-steps", type=int, default=10000,
+                    help="steps that make one sweep case (cases/s is quoted for this length)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
@@ -211,6 +264,10 @@ def main():
         droplet3d = {"workload": f"3D droplet freezing {m}^3, R={m // 4}, obstacle radius "
                                  f"{12 * m // 256}, D3Q19+3xD3Q7, FP32 arithmetic",
                      "steps": args.steps3d, "forms": forms3}
+    sweep = None
+    if args.sweep_cases:
+        sweep = time_sweep(args.sweep_cases, args.sweep_steps, args.sweep_case_steps,
+                           args.storage)
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -244,6 +301,8 @@ def main():
         out["storage_forms"] = other
     if droplet3d:
         out["droplet3d"] = droplet3d
+    if sweep:
+        out["sweep"] = sweep
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, phi, T, C)
     print(json.dumps(out), flush=True)

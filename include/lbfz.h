@@ -148,6 +148,55 @@ int lbfz_state_floats(lbfz_handle* h, size_t* nfloats);
 int lbfz_get_state(lbfz_handle* h, float* host_dst);
 int lbfz_set_state(lbfz_handle* h, const float* host_src);
 
+/* ------------------------------------------------------------------------
+ * Batched sweep: many independent 2D grids (the parameter sweep of Sec. 5's
+ * study, each grid a complete solver state with its own parameters, size,
+ * buffers and totals) advanced in lockstep.  Grids of equal size form a
+ * group; one batch step is one launch per group over a table of (grid, tile)
+ * work items, replayed from a captured HIP graph.  Results are those of the
+ * same grids stepped one by one (the per-node arithmetic is identical).
+ * ------------------------------------------------------------------------ */
+typedef struct lbfz_batch lbfz_batch;
+
+/* Device workspace for ncases grids (params[i]: dim 2, one storage form for
+ * all).  Errors: LBFZ_EINVAL. */
+int lbfz_batch_workspace_bytes(int32_t ncases, const lbfz_params* params, size_t* bytes);
+
+/* Create the grids from host FP64 initial fields phi[i], T[i], C[i] (as
+ * lbfz_create), their work tables and case table in the caller's workspace.
+ * Creates one internal HIP stream (default priority) used only to capture
+ * graphs; all work runs on `stream`.  Synchronises the stream.  Errors as
+ * lbfz_create, plus LBFZ_EINVAL for mixed storage or dim != 2. */
+int lbfz_batch_create(int32_t ncases, const lbfz_params* params, const double* const* phi,
+                      const double* const* T, const double* const* C, void* d_workspace,
+                      size_t ws_bytes, void* stream, lbfz_batch** out);
+
+/* Autotuner: for every group, time each candidate launch configuration (tile
+ * height 4 or 8 rows; one block per work item or a persistent grid of 8 / 4
+ * blocks per CU) over trial_steps steps and keep the fastest.  The trial
+ * steps are real steps of every grid (4 * trial_steps in all).  Synchronises. */
+int lbfz_batch_tune(lbfz_batch* b, int32_t trial_steps);
+
+/* Advance every grid by nsteps (asynchronous on the stream). */
+int lbfz_batch_step(lbfz_batch* b, int64_t nsteps);
+
+/* The same with plain launches, one grid after the other (the reference the
+ * batched step is measured against). */
+int lbfz_batch_step_sequential(lbfz_batch* b, int64_t nsteps);
+
+/* Number of groups, and the configuration of one (any output may be NULL). */
+int lbfz_batch_groups(lbfz_batch* b);
+int lbfz_batch_group_config(lbfz_batch* b, int32_t group, int32_t* nx, int32_t* ny,
+                            int32_t* ncases, int32_t* tile_rows, int32_t* grid_blocks);
+
+/* Fields and totals of grid i, as lbfz_fields / lbfz_totals. */
+int lbfz_batch_fields(lbfz_batch* b, int32_t i, uint32_t field_mask, float* const* dst,
+                      int dst_is_device);
+int lbfz_batch_totals(lbfz_batch* b, int32_t i, lbfz_totals_t* out);
+
+/* Release the grids, graphs and the capture stream (not the workspace). */
+void lbfz_batch_destroy(lbfz_batch* b);
+
 /* Blocks until the handle's stream is idle. */
 int lbfz_sync(lbfz_handle* h);
 

@@ -43,15 +43,19 @@ namespace lbfz {
 
 namespace {
 
-#ifndef LBFZ_TY
-#define LBFZ_TY 4
-#endif
-constexpr int TX = 64, TY = LBFZ_TY, NT = TX * TY;
-static_assert(TX == 64, "one tile row per wave64");
-constexpr int HX = TX + 2, HY = TY + 2;  // closure ring
-constexpr int UX = TX + 4, UY = TY + 4;  // velocity ring
-constexpr int RING = 2 * HX + 2 * TY;
-static_assert(RING <= NT, "every ring slot needs a thread");
+// Tile geometry: 64 x TY nodes, one row per wave; TY is a template parameter
+// of the step (4 for the single-grid solver; the batched sweep chooses).
+constexpr int TX = 64;
+constexpr int HX = TX + 2;  // closure ring width
+constexpr int UX = TX + 4;  // velocity ring width
+template <int TY>
+struct Geo {
+  static constexpr int NT = TX * TY;
+  static constexpr int HY = TY + 2, UY = TY + 4;
+  static constexpr int RING = 2 * HX + 2 * TY;
+  static_assert(RING <= NT, "every ring slot needs a thread");
+};
+constexpr int TY_DEFAULT = 4;
 
 constexpr int PF = 0, PG = 5, PH = 14, PL = 19;  // FP32 layout: first plane of each set
 enum { SF = 0, SG = 1, SH = 2, SL = 3 };         // set index (16-bit layout: rest plane)
@@ -192,6 +196,7 @@ __device__ __forceinline__ void load_raw(const KParams& P, const Bufs& B, uint32
 // Closure of the node (mx, my) staged in closure-ring slot (lx, ly), from its
 // raw inputs and div u^{n-1} on the velocity ring.  A ghost slot (side != 0)
 // holds the mirror node with the wall's temperature transform.
+template <int UY>
 __device__ __forceinline__ Slot close_slot(const KParams& P, const Raw& r, int y0, int mx,
                                            int my, int side, int lx, int ly, float (*s_ux)[UX],
                                            float (*s_uy)[UX], float& Dout, Closure& cout) {
@@ -235,13 +240,14 @@ __device__ __forceinline__ Slot close_slot(const KParams& P, const Raw& r, int y
 #define LBFZ_OCC
 #endif
 
-template <bool DRY, int ST>
-__global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, StepArgs A) {
+// One tile of one step (the body of the single-grid and the batched kernels).
+template <bool DRY, int ST, int TY>
+__device__ __forceinline__ void step2d_tile(const KParams& P, const StepArgs& A, const int tile) {
+  constexpr int NT = Geo<TY>::NT, HY = Geo<TY>::HY, UY = Geo<TY>::UY, RING = Geo<TY>::RING;
   __shared__ float s_ux[UY][UX], s_uy[UY][UX];
   __shared__ float s_phi[HY][HX], s_T[HY][HX], s_C[HY][HX], s_fs[HY][HX], s_p[HY][HX];
   __shared__ double s_red[NT / 64];
 
-  const int tile = xcd_tile(blockIdx.x, P.nblk);
   const int bx = tile % P.nblk_x, by = tile / P.nblk_x;
   const int x0 = bx * TX, y0 = by * TY;
   const int tid = threadIdx.x, tx = tid & (TX - 1);
@@ -320,7 +326,7 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, StepArgs A) {
   Closure cl;
   {
     const Slot s =
-        close_slot(P, own, y0, omx, omy, oside, tx + 1, ty + 1, s_ux, s_uy, D, cl);
+        close_slot<UY>(P, own, y0, omx, omy, oside, tx + 1, ty + 1, s_ux, s_uy, D, cl);
     s_phi[ty + 1][tx + 1] = s.phi;
     s_T[ty + 1][tx + 1] = s.T;
     s_C[ty + 1][tx + 1] = s.C;
@@ -330,7 +336,8 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, StepArgs A) {
   if (has_ring) {
     float D2;
     Closure c2;
-    const Slot s = close_slot(P, ring, y0, rmx, rmy, rside, rlx, rly, s_ux, s_uy, D2, c2);
+    const Slot s =
+        close_slot<UY>(P, ring, y0, rmx, rmy, rside, rlx, rly, s_ux, s_uy, D2, c2);
     s_phi[rly][rlx] = s.phi;
     s_T[rly][rlx] = s.T;
     s_C[rly][rlx] = s.C;
@@ -613,6 +620,29 @@ __global__ __launch_bounds__(NT) LBFZ_OCC void k_step2d(KParams P, StepArgs A) {
   if (tid == 0) A.mpc_part[tile] += s;
 }
 
+template <bool DRY, int ST, int TY>
+__global__ __launch_bounds__(Geo<TY>::NT) LBFZ_OCC void k_step2d(KParams P, StepArgs A) {
+  step2d_tile<DRY, ST, TY>(P, A, xcd_tile(blockIdx.x, P.nblk));
+}
+
+// Batched sweep: every (case, tile) of one step of many grids in one launch.
+// Work item e = (case, tile) comes from a table built on the host (in an
+// XCD-aware order); a block processes items blockIdx.x, blockIdx.x +
+// gridDim.x, ... (persistent when the grid is smaller than the work), with
+// the case's parameters and the buffers of step parity `slot` read from the
+// case table (wave-uniform: scalar loads).
+template <int ST, int TY>
+__global__ __launch_bounds__(Geo<TY>::NT) void k_step2d_batch(
+    const BatchCase* __restrict__ cases, const int2* __restrict__ work, int nwork, int slot) {
+  for (int e = blockIdx.x; e < nwork; e += gridDim.x) {
+    const int2 w = work[e];
+    const int c = __builtin_amdgcn_readfirstlane(w.x);
+    const int tile = __builtin_amdgcn_readfirstlane(w.y);
+    step2d_tile<false, ST, TY>(cases[c].P, cases[c].A[slot], tile);
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
 // Equilibrium populations of the initial fields (u = 0, p = 0) and the zero
 // previous-level state.  16-bit: every moving population sits exactly at its
 // reference (offset 0), and the references phi, C, T are stored.
@@ -741,9 +771,10 @@ int grid_of(long N) { return (int)std::min<long>((N + 255) / 256, 65536); }
 
 }  // namespace
 
-int tiles2d(int nx, int ny, int* nbx, int* nby) {
+int tiles2d(int nx, int ny, int* nbx, int* nby, int ty) {
+  if (ty <= 0) ty = TY_DEFAULT;
   *nbx = (nx + TX - 1) / TX;
-  *nby = (ny + TY - 1) / TY;
+  *nby = (ny + ty - 1) / ty;
   return (*nbx) * (*nby);
 }
 
@@ -773,10 +804,18 @@ hipError_t launch_init2d(const KParams& P, int storage, const double* phi, const
 
 template <int ST>
 static void launch_step2d_st(const KParams& P, const StepArgs& A, bool dry, hipStream_t st) {
+  constexpr int NT = Geo<TY_DEFAULT>::NT;
   if (dry)
-    hipLaunchKernelGGL((k_step2d<true, ST>), dim3(P.nblk), dim3(NT), 0, st, P, A);
+    hipLaunchKernelGGL((k_step2d<true, ST, TY_DEFAULT>), dim3(P.nblk), dim3(NT), 0, st, P, A);
   else
-    hipLaunchKernelGGL((k_step2d<false, ST>), dim3(P.nblk), dim3(NT), 0, st, P, A);
+    hipLaunchKernelGGL((k_step2d<false, ST, TY_DEFAULT>), dim3(P.nblk), dim3(NT), 0, st, P, A);
+}
+
+template <int ST, int TY>
+static void launch_batch_st(const BatchCase* cases, const int2* work, int nwork, int grid,
+                            int slot, hipStream_t st) {
+  hipLaunchKernelGGL((k_step2d_batch<ST, TY>), dim3(grid), dim3(Geo<TY>::NT), 0, st, cases,
+                     work, nwork, slot);
 }
 
 hipError_t launch_step2d(const KParams& P, int storage, const StepArgs& A, bool dry,
@@ -785,6 +824,22 @@ hipError_t launch_step2d(const KParams& P, int storage, const StepArgs& A, bool 
     case LBFZ_STORE_F32: launch_step2d_st<LBFZ_STORE_F32>(P, A, dry, st); break;
     case LBFZ_STORE_F16: launch_step2d_st<LBFZ_STORE_F16>(P, A, dry, st); break;
     default: launch_step2d_st<LBFZ_STORE_BF16>(P, A, dry, st);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step2d_batch(int storage, int ty, const BatchCase* cases, const int2* work,
+                               int nwork, int grid, int slot, hipStream_t st) {
+  if (nwork <= 0) return hipSuccess;
+  if (grid <= 0 || grid > nwork) grid = nwork;
+  switch (storage * 16 + ty) {
+    case LBFZ_STORE_F32 * 16 + 4: launch_batch_st<LBFZ_STORE_F32, 4>(cases, work, nwork, grid, slot, st); break;
+    case LBFZ_STORE_F32 * 16 + 8: launch_batch_st<LBFZ_STORE_F32, 8>(cases, work, nwork, grid, slot, st); break;
+    case LBFZ_STORE_F16 * 16 + 4: launch_batch_st<LBFZ_STORE_F16, 4>(cases, work, nwork, grid, slot, st); break;
+    case LBFZ_STORE_F16 * 16 + 8: launch_batch_st<LBFZ_STORE_F16, 8>(cases, work, nwork, grid, slot, st); break;
+    case LBFZ_STORE_BF16 * 16 + 4: launch_batch_st<LBFZ_STORE_BF16, 4>(cases, work, nwork, grid, slot, st); break;
+    case LBFZ_STORE_BF16 * 16 + 8: launch_batch_st<LBFZ_STORE_BF16, 8>(cases, work, nwork, grid, slot, st); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -11,36 +11,11 @@
 
 #include "../../include/lbfz.h"
 #include "lbfz_common.hpp"
+#include "lbfz_handle.hpp"
 #include "lbfz_kernels.hpp"
 
 using namespace lbfz;
 
-struct lbfz_handle {
-  lbfz_params prm;
-  KParams kp;
-  hipStream_t stream;
-  char* ws;
-  size_t ws_bytes;
-  int storage;
-  float* pop[2];
-  float* p[3];     // FP32: two levels; 16-bit: three (p_ref)
-  float* u[2];
-  float* fs;       // 2D
-  float* phiP[2];  // 2D; FP32: [1] == [0] (updated in place)
-  float* CP[2];
-  float* T[2];     // 2D 16-bit only
-  float* cf[2];    // 3D closure fields (phi, T, C, f_s, div u planes) per level
-  bool narrow;     // 16-bit population storage
-  double* mpc_part;
-  double* tot_part;
-  double* red;
-  float* stage;
-  uint8_t* mask;
-  int cur;
-  int64_t step;
-  int ntiles;
-  int npop;
-};
 
 namespace {
 
@@ -208,6 +183,10 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ tot,
     if ((x) != hipSuccess) return LBFZ_EHIP; \
   } while (0)
 
+}  // namespace
+
+namespace lbfz {
+
 hipError_t launch_step(lbfz_handle* h, const StepArgs& a, bool dry) {
   if (h->prm.dim == 3) return launch_step3d(h->kp, h->storage, a, dry, h->stream);
   return launch_step2d(h->kp, h->storage, a, dry, h->stream);
@@ -250,7 +229,7 @@ StepArgs base_args(lbfz_handle* h) {
   return a;
 }
 
-}  // namespace
+}  // namespace lbfz
 
 extern "C" {
 

@@ -1,0 +1,384 @@
+// lbfz_batch.hip -- the batched sweep of the C ABI (include/lbfz.h): many
+// independent 2D grids, each a complete solver state (its own parameters,
+// size, buffers and totals), advanced together.
+//
+// Grids of equal size form a group.  One step of the batch is one launch of
+// k_step2d_batch per group over a work table of (grid, tile) items, with the
+// grids' kernel parameters and per-parity buffers in a device table; the
+// tile height (4 or 8 rows) and the launch shape (one block per item, or a
+// persistent grid of a few blocks per CU looping over the items) are chosen
+// per group by a timing search (lbfz_batch_tune).  Steps are replayed from a
+// HIP graph captured once per configuration, so a long run costs one graph
+// launch per graph_steps steps instead of one launch per group and step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/lbfz.h"
+#include "lbfz_common.hpp"
+#include "lbfz_handle.hpp"
+#include "lbfz_kernels.hpp"
+
+using namespace lbfz;
+
+namespace {
+
+constexpr int kGraphSteps = 12;  // steps per captured graph (a multiple of 2 and 3)
+constexpr int kTY[2] = {4, 8};
+
+struct Group {
+  int nx, ny;
+  std::vector<int> cases;
+  int nwork[2];      // work items at tile height kTY[v]
+  int2* work[2];     // device work tables
+  int ty_index = 0;  // chosen tile height (index into kTY)
+  int grid = 0;      // blocks per launch; 0: one per work item
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int slots_of(int storage) { return storage == LBFZ_STORE_F32 ? 2 : 6; }
+
+}  // namespace
+
+struct lbfz_batch {
+  int ncases = 0;
+  int storage = 0;
+  int L = 2;  // parity slots of the step arguments
+  std::vector<lbfz_handle*> h;
+  std::vector<Group> groups;
+  hipStream_t stream = nullptr;  // caller's
+  hipStream_t cap = nullptr;     // capture stream (internal)
+  BatchCase* d_cases = nullptr;
+  std::vector<BatchCase> cases;  // host copy of the table
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int64_t step = 0;
+};
+
+namespace {
+
+#define HIPCHK(x)                            \
+  do {                                       \
+    if ((x) != hipSuccess) return LBFZ_EHIP; \
+  } while (0)
+
+// Case table entry of grid i for tile height ty: the handle's parameters with
+// that tiling, and the step arguments of every parity slot.
+void fill_case(lbfz_batch* b, int i, int ty) {
+  lbfz_handle* h = b->h[i];
+  BatchCase& c = b->cases[i];
+  c.P = h->kp;
+  int nbx, nby;
+  c.P.nblk = tiles2d(h->kp.nx, h->kp.ny, &nbx, &nby, ty);
+  c.P.nblk_x = nbx;
+  c.P.nblk_y = nby;
+  const int cur = h->cur;
+  const int64_t step = h->step;
+  for (int k = 0; k < b->L; ++k) {
+    h->step = k;
+    h->cur = k & 1;
+    c.A[k] = base_args(h);
+  }
+  h->step = step;
+  h->cur = cur;
+}
+
+int upload_cases(lbfz_batch* b) {
+  for (auto& g : b->groups)
+    for (int i : g.cases) fill_case(b, i, kTY[g.ty_index]);
+  HIPCHK(hipMemcpyAsync(b->d_cases, b->cases.data(), sizeof(BatchCase) * b->ncases,
+                        hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return LBFZ_OK;
+}
+
+hipError_t launch_group(lbfz_batch* b, const Group& g, int64_t step, hipStream_t st) {
+  const int v = g.ty_index;
+  return launch_step2d_batch(b->storage, kTY[v], b->d_cases, g.work[v], g.nwork[v], g.grid,
+                             (int)(step % b->L), st);
+}
+
+void drop_graph(lbfz_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// Capture kGraphSteps steps (starting at a step that is 0 mod L) of every
+// group on the capture stream.
+int build_graph(lbfz_batch* b) {
+  drop_graph(b);
+  HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < kGraphSteps && e == hipSuccess; ++s)
+    for (auto& g : b->groups)
+      if (e == hipSuccess) e = launch_group(b, g, s, b->cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
+  if (e != hipSuccess || e2 != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return LBFZ_EHIP;
+  }
+  b->graph = graph;
+  if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+    drop_graph(b);
+    return LBFZ_EHIP;
+  }
+  return LBFZ_OK;
+}
+
+void sync_handles(lbfz_batch* b) {
+  for (lbfz_handle* h : b->h) {
+    h->step = b->step;
+    h->cur = (int)(b->step & 1);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbfz_batch_workspace_bytes(int32_t ncases, const lbfz_params* params, size_t* bytes) {
+  if (ncases <= 0 || !params || !bytes) return LBFZ_EINVAL;
+  size_t total = 0, items = 0;
+  for (int i = 0; i < ncases; ++i) {
+    if (params[i].dim != 2 || params[i].storage != params[0].storage) return LBFZ_EINVAL;
+    size_t w = 0;
+    const int rc = lbfz_workspace_bytes(&params[i], &w);
+    if (rc != LBFZ_OK) return rc;
+    total += align256(w);
+    int nbx, nby;
+    for (int ty : kTY) items += (size_t)tiles2d(params[i].nx, params[i].ny, &nbx, &nby, ty);
+  }
+  total += align256(sizeof(BatchCase) * (size_t)ncases);
+  total += align256(sizeof(int2) * items) + 256 * 2 * (size_t)ncases;
+  *bytes = total;
+  return LBFZ_OK;
+}
+
+int lbfz_batch_create(int32_t ncases, const lbfz_params* params, const double* const* phi,
+                      const double* const* T, const double* const* C, void* d_workspace,
+                      size_t ws_bytes, void* stream, lbfz_batch** out) {
+  if (!out) return LBFZ_EINVAL;
+  *out = nullptr;
+  size_t need = 0;
+  const int rc0 = lbfz_batch_workspace_bytes(ncases, params, &need);
+  if (rc0 != LBFZ_OK) return rc0;
+  if (!phi || !T || !C || !d_workspace) return LBFZ_EINVAL;
+  if (ws_bytes < need || ((uintptr_t)d_workspace & 255)) return LBFZ_ENOMEM;
+  lbfz_batch* b = new (std::nothrow) lbfz_batch;
+  if (!b) return LBFZ_ENOMEM;
+  b->ncases = ncases;
+  b->storage = params[0].storage;
+  b->L = slots_of(b->storage);
+  b->stream = (hipStream_t)stream;
+  char* q = (char*)d_workspace;
+  int rc = LBFZ_OK;
+  for (int i = 0; i < ncases && rc == LBFZ_OK; ++i) {
+    size_t w = 0;
+    lbfz_workspace_bytes(&params[i], &w);
+    lbfz_handle* h = nullptr;
+    rc = lbfz_create(&params[i], phi[i], T[i], C[i], nullptr, q, w, stream, &h);
+    if (rc == LBFZ_OK) b->h.push_back(h);
+    q += align256(w);
+  }
+  if (rc != LBFZ_OK) {
+    lbfz_batch_destroy(b);
+    return rc;
+  }
+  b->d_cases = (BatchCase*)q;
+  q += align256(sizeof(BatchCase) * (size_t)ncases);
+  b->cases.resize(ncases);
+  // groups of equal grid size, in order of first appearance
+  std::map<std::pair<int, int>, int> gid;
+  for (int i = 0; i < ncases; ++i) {
+    const auto key = std::make_pair(params[i].nx, params[i].ny);
+    auto it = gid.find(key);
+    if (it == gid.end()) {
+      it = gid.emplace(key, (int)b->groups.size()).first;
+      Group g;
+      g.nx = params[i].nx;
+      g.ny = params[i].ny;
+      b->groups.push_back(g);
+    }
+    b->groups[it->second].cases.push_back(i);
+  }
+  // work tables: (grid, tile) items in an XCD-aware order (item e runs on the
+  // XCD e % 8, which gets a contiguous band of the flat item list)
+  for (auto& g : b->groups) {
+    for (int v = 0; v < 2; ++v) {
+      int nbx, nby;
+      const int per = tiles2d(g.nx, g.ny, &nbx, &nby, kTY[v]);
+      std::vector<int2> flat;
+      flat.reserve((size_t)per * g.cases.size());
+      for (int c : g.cases)
+        for (int t = 0; t < per; ++t) flat.push_back(make_int2(c, t));
+      const int n = (int)flat.size();
+      std::vector<int2> tab(n);
+      const int band = n >> 3;
+      for (int e = 0; e < n; ++e)
+        tab[e] = (band == 0 || (n & 7)) ? flat[e] : flat[(e & 7) * band + (e >> 3)];
+      g.nwork[v] = n;
+      g.work[v] = (int2*)q;
+      q += align256(sizeof(int2) * (size_t)n);
+      if (hipMemcpyAsync(g.work[v], tab.data(), sizeof(int2) * n, hipMemcpyHostToDevice,
+                         b->stream) != hipSuccess ||
+          hipStreamSynchronize(b->stream) != hipSuccess) {
+        lbfz_batch_destroy(b);
+        return LBFZ_EHIP;
+      }
+    }
+  }
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    b->cap = nullptr;
+    lbfz_batch_destroy(b);
+    return LBFZ_EHIP;
+  }
+  rc = upload_cases(b);
+  if (rc != LBFZ_OK) {
+    lbfz_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return LBFZ_OK;
+}
+
+int lbfz_batch_tune(lbfz_batch* b, int32_t trial_steps) {
+  if (!b || trial_steps <= 0) return LBFZ_EINVAL;
+  // candidates: tile height x launch shape (one block per item, or a
+  // persistent grid of blocks_per_cu x 256 blocks)
+  struct Cand {
+    int v, per_cu;
+  };
+  const Cand cands[] = {{0, 0}, {1, 0}, {0, 8}, {1, 4}};
+  const int nc = (int)(sizeof(cands) / sizeof(cands[0]));
+  const int G = (int)b->groups.size();
+  std::vector<float> best(G, 1e30f);
+  std::vector<Cand> pick(G, cands[0]);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  // every group runs every candidate for trial_steps steps, so all grids
+  // advance by the same number of steps; the results do not depend on the
+  // candidate (the per-node arithmetic is the same)
+  for (int k = 0; k < nc; ++k) {
+    for (int gi = 0; gi < G; ++gi) {
+      Group& g = b->groups[gi];
+      g.ty_index = cands[k].v;
+      g.grid = cands[k].per_cu * 256;
+    }
+    int rc = upload_cases(b);
+    if (rc != LBFZ_OK) return rc;
+    for (int gi = 0; gi < G; ++gi) {
+      Group& g = b->groups[gi];
+      HIPCHK(hipEventRecord(e0, b->stream));
+      for (int s = 0; s < trial_steps; ++s) HIPCHK(launch_group(b, g, b->step + s, b->stream));
+      HIPCHK(hipEventRecord(e1, b->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best[gi]) {
+        best[gi] = ms;
+        pick[gi] = cands[k];
+      }
+    }
+    b->step += trial_steps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int gi = 0; gi < G; ++gi) {
+    b->groups[gi].ty_index = pick[gi].v;
+    b->groups[gi].grid = pick[gi].per_cu * 256;
+  }
+  drop_graph(b);
+  sync_handles(b);
+  return upload_cases(b);
+}
+
+int lbfz_batch_step(lbfz_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return LBFZ_EINVAL;
+  auto one = [&]() -> int {
+    for (auto& g : b->groups) HIPCHK(launch_group(b, g, b->step, b->stream));
+    b->step += 1;
+    return LBFZ_OK;
+  };
+  while (nsteps > 0 && b->step % kGraphSteps != 0) {
+    const int rc = one();
+    if (rc != LBFZ_OK) return rc;
+    --nsteps;
+  }
+  if (nsteps >= kGraphSteps) {
+    if (!b->exec) {
+      const int rc = build_graph(b);
+      if (rc != LBFZ_OK) return rc;
+    }
+    while (nsteps >= kGraphSteps) {
+      HIPCHK(hipGraphLaunch(b->exec, b->stream));
+      b->step += kGraphSteps;
+      nsteps -= kGraphSteps;
+    }
+  }
+  while (nsteps > 0) {
+    const int rc = one();
+    if (rc != LBFZ_OK) return rc;
+    --nsteps;
+  }
+  sync_handles(b);
+  return LBFZ_OK;
+}
+
+int lbfz_batch_step_sequential(lbfz_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return LBFZ_EINVAL;
+  sync_handles(b);
+  for (lbfz_handle* h : b->h) {
+    const int rc = lbfz_step(h, nsteps);
+    if (rc != LBFZ_OK) return rc;
+  }
+  b->step += nsteps;
+  sync_handles(b);
+  return LBFZ_OK;
+}
+
+int lbfz_batch_groups(lbfz_batch* b) { return b ? (int)b->groups.size() : LBFZ_EINVAL; }
+
+int lbfz_batch_group_config(lbfz_batch* b, int32_t group, int32_t* nx, int32_t* ny,
+                            int32_t* ncases, int32_t* tile_rows, int32_t* grid_blocks) {
+  if (!b || group < 0 || group >= (int)b->groups.size()) return LBFZ_EINVAL;
+  const Group& g = b->groups[group];
+  if (nx) *nx = g.nx;
+  if (ny) *ny = g.ny;
+  if (ncases) *ncases = (int32_t)g.cases.size();
+  if (tile_rows) *tile_rows = kTY[g.ty_index];
+  if (grid_blocks) *grid_blocks = g.grid;
+  return LBFZ_OK;
+}
+
+int lbfz_batch_fields(lbfz_batch* b, int32_t i, uint32_t field_mask, float* const* dst,
+                      int dst_is_device) {
+  if (!b || i < 0 || i >= b->ncases) return LBFZ_EINVAL;
+  sync_handles(b);
+  return lbfz_fields(b->h[i], field_mask, dst, dst_is_device);
+}
+
+int lbfz_batch_totals(lbfz_batch* b, int32_t i, lbfz_totals_t* out) {
+  if (!b || i < 0 || i >= b->ncases) return LBFZ_EINVAL;
+  sync_handles(b);
+  return lbfz_totals(b->h[i], out);
+}
+
+void lbfz_batch_destroy(lbfz_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (lbfz_handle* h : b->h) lbfz_destroy(h);
+  delete b;
+}
+
+}  // extern "C"

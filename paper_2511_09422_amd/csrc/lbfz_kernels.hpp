@@ -46,12 +46,22 @@ struct StateArgs {
   float *pA, *pB, *pC, *uA, *uB, *fs, *phiA, *CA, *TA, *DA;
 };
 
-int tiles2d(int nx, int ny, int* nbx, int* nby);
+// One grid of the batched sweep: its kernel parameters and the buffers of
+// each step parity slot (2 slots with FP32 storage, 6 with 16-bit storage,
+// whose pressure is triple-buffered).
+struct BatchCase {
+  KParams P;
+  StepArgs A[6];
+};
+
+int tiles2d(int nx, int ny, int* nbx, int* nby, int ty = 0);
 size_t pop_bytes2d(int storage, size_t ps);
 hipError_t launch_init2d(const KParams& P, int storage, const double* phi, const double* T,
                          const double* C, float* pop, const StateArgs& S, hipStream_t st);
 hipError_t launch_step2d(const KParams& P, int storage, const StepArgs& A, bool dry,
                          hipStream_t st);
+hipError_t launch_step2d_batch(int storage, int ty, const BatchCase* cases, const int2* work,
+                               int nwork, int grid, int slot, hipStream_t st);
 hipError_t launch_export2d(const KParams& P, int storage, const StepArgs& A, float* dst,
                            hipStream_t st);
 hipError_t launch_import2d(const KParams& P, int storage, const StepArgs& A, const float* src,

@@ -75,9 +75,28 @@ def lib() -> ctypes.CDLL:
         L.lbfz_destroy.restype = None
         L.lbfz_strerror.argtypes = [ctypes.c_int]
         L.lbfz_strerror.restype = ctypes.c_char_p
+        ip = ctypes.POINTER(ctypes.c_int32)
+        dpp = ctypes.POINTER(dp)
+        L.lbfz_batch_workspace_bytes.argtypes = [ctypes.c_int32, pp,
+                                                 ctypes.POINTER(ctypes.c_size_t)]
+        L.lbfz_batch_create.argtypes = [ctypes.c_int32, pp, dpp, dpp, dpp, vp, ctypes.c_size_t,
+                                        vp, ctypes.POINTER(vp)]
+        L.lbfz_batch_tune.argtypes = [vp, ctypes.c_int32]
+        L.lbfz_batch_step.argtypes = [vp, ctypes.c_int64]
+        L.lbfz_batch_step_sequential.argtypes = [vp, ctypes.c_int64]
+        L.lbfz_batch_groups.argtypes = [vp]
+        L.lbfz_batch_group_config.argtypes = [vp, ctypes.c_int32, ip, ip, ip, ip, ip]
+        L.lbfz_batch_fields.argtypes = [vp, ctypes.c_int32, ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+        L.lbfz_batch_totals.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(lbfz_totals_t)]
+        L.lbfz_batch_destroy.argtypes = [vp]
+        L.lbfz_batch_destroy.restype = None
         for nm in ("lbfz_workspace_bytes", "lbfz_create", "lbfz_step", "lbfz_fields",
                    "lbfz_totals", "lbfz_sync", "lbfz_state_floats", "lbfz_get_state",
-                   "lbfz_set_state"):
+                   "lbfz_set_state", "lbfz_batch_workspace_bytes", "lbfz_batch_create",
+                   "lbfz_batch_tune", "lbfz_batch_step", "lbfz_batch_step_sequential",
+                   "lbfz_batch_groups", "lbfz_batch_group_config", "lbfz_batch_fields",
+                   "lbfz_batch_totals"):
             getattr(L, nm).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -239,3 +258,128 @@ class Solver:
 
     def set_state(self, arr) -> None:
         lbfz_set_state(self._h, arr)
+
+
+# --------------------------------------------------------------------------
+# batched sweep
+
+def lbfz_batch_workspace_bytes(cfgs, storage: str = "f32") -> int:
+    P = (lbfz_params * len(cfgs))(*[make_params(c, storage) for c in cfgs])
+    n = ctypes.c_size_t()
+    _check(lib().lbfz_batch_workspace_bytes(len(cfgs), P, ctypes.byref(n)),
+           "lbfz_batch_workspace_bytes")
+    return n.value
+
+
+def lbfz_batch_create(cfgs, fields, ws_ptr: int, ws_bytes: int, stream_ptr: int,
+                      storage: str = "f32") -> ctypes.c_void_p:
+    """fields: one (phi, T, C) triple per grid."""
+    n = len(cfgs)
+    P = (lbfz_params * n)(*[make_params(c, storage) for c in cfgs])
+    dp = ctypes.POINTER(ctypes.c_double)
+    keep = [[np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in f] for f in fields]
+    ptrs = [(dp * n)(*[keep[i][k].ctypes.data_as(dp) for i in range(n)]) for k in range(3)]
+    b = ctypes.c_void_p()
+    rc = lib().lbfz_batch_create(n, P, ptrs[0], ptrs[1], ptrs[2], ctypes.c_void_p(ws_ptr),
+                                 ctypes.c_size_t(ws_bytes), ctypes.c_void_p(stream_ptr),
+                                 ctypes.byref(b))
+    _check(rc, "lbfz_batch_create")
+    return b
+
+
+def lbfz_batch_tune(b, trial_steps: int):
+    _check(lib().lbfz_batch_tune(b, int(trial_steps)), "lbfz_batch_tune")
+
+
+def lbfz_batch_step(b, nsteps: int):
+    _check(lib().lbfz_batch_step(b, int(nsteps)), "lbfz_batch_step")
+
+
+def lbfz_batch_step_sequential(b, nsteps: int):
+    _check(lib().lbfz_batch_step_sequential(b, int(nsteps)), "lbfz_batch_step_sequential")
+
+
+def lbfz_batch_groups(b) -> list:
+    n = lib().lbfz_batch_groups(b)
+    if n < 0:
+        raise LbfzError(n, "lbfz_batch_groups")
+    out = []
+    for g in range(n):
+        v = [ctypes.c_int32() for _ in range(5)]
+        _check(lib().lbfz_batch_group_config(b, g, *[ctypes.byref(x) for x in v]),
+               "lbfz_batch_group_config")
+        out.append(dict(zip(("nx", "ny", "ncases", "tile_rows", "grid_blocks"),
+                            [x.value for x in v])))
+    return out
+
+
+def lbfz_batch_fields(b, i: int, mask_bits: int, ptrs, dst_is_device: bool):
+    arr = (ctypes.c_void_p * len(FIELDS))(*[ctypes.c_void_p(p) for p in ptrs])
+    _check(lib().lbfz_batch_fields(b, int(i), ctypes.c_uint32(mask_bits), arr,
+                                   int(dst_is_device)), "lbfz_batch_fields")
+
+
+def lbfz_batch_totals(b, i: int) -> dict:
+    t = lbfz_totals_t()
+    _check(lib().lbfz_batch_totals(b, int(i), ctypes.byref(t)), "lbfz_batch_totals")
+    return {k: getattr(t, k) for k, _ in lbfz_totals_t._fields_}
+
+
+def lbfz_batch_destroy(b):
+    lib().lbfz_batch_destroy(b)
+
+
+class Batch:
+    """Many independent 2D grids on one GPU, advanced together (the batched
+    sweep).  ``cases``: a list of (params, phi, T, C)."""
+
+    def __init__(self, cases, device: int = 0, storage: str = "f32", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the lbfz solver runs on the GPU only")
+        self.cfgs = [dict(c[0]) for c in cases]
+        self.shapes = [(c["ny"], c["nx"]) for c in self.cfgs]
+        self.device = torch.device("cuda", device)
+        nbytes = lbfz_batch_workspace_bytes(self.cfgs, storage)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._b = lbfz_batch_create(self.cfgs, [c[1:] for c in cases],
+                                    self.workspace.data_ptr(), nbytes, self.stream.cuda_stream,
+                                    storage)
+
+    def close(self):
+        b = getattr(self, "_b", None)
+        if b is not None and b.value:
+            lbfz_batch_destroy(b)
+        self._b = None
+
+    def __del__(self):
+        self.close()
+
+    def tune(self, trial_steps: int = 8):
+        lbfz_batch_tune(self._b, trial_steps)
+
+    def step(self, n: int = 1):
+        lbfz_batch_step(self._b, n)
+
+    def step_sequential(self, n: int = 1):
+        lbfz_batch_step_sequential(self._b, n)
+
+    def groups(self) -> list:
+        return lbfz_batch_groups(self._b)
+
+    def fields(self, i: int, names=FIELDS) -> dict:
+        bits = 0
+        out = {}
+        ptrs = [0] * len(FIELDS)
+        for k, nm in enumerate(FIELDS):
+            if nm in names:
+                bits |= 1 << k
+                t = np.empty(self.shapes[i], dtype=np.float32)
+                out[nm] = t
+                ptrs[k] = t.ctypes.data
+        lbfz_batch_fields(self._b, i, bits, ptrs, False)
+        return out
+
+    def totals(self, i: int) -> dict:
+        return lbfz_batch_totals(self._b, i)
