@@ -1,0 +1,133 @@
+/*
+ * lbfz_nn.h -- C ABI of the kernels of the learned surrogate of the coupled
+ * LB freezing step (arXiv 2511.09422): a 3-level U-Net of 3x3 convolutions
+ * (32 / 64 / 128 channels, ReLU, 2x2 max pooling, nearest 2x upsampling,
+ * skip connections by channel concatenation, a 1x1 head) that maps the six
+ * fields phi, f_l, T, C, u_x, u_y of a crop of the 2D step to their change
+ * over 64 steps.  The paper itself has no learned component; the surrogate
+ * screens parameter sweeps of its model, with the LB step as the judge.
+ *
+ * Conventions (all calls):
+ *   - Activations and gradients: bf16, NHWC (pixel-major, channels
+ *     innermost), images B x H x W.  A tensor argument is (pointer, channel
+ *     stride cs, channel offset co): channels co .. co + C - 1 of every pixel,
+ *     pixels cs elements apart.  Channel counts, strides and offsets of
+ *     convolution operands are multiples of 8; pointers are 16-byte aligned.
+ *   - Weights: bf16 [N][taps][Cin] (taps 9: a 3x3 stencil with zero padding,
+ *     tap t at offset (t / 3 - 1, t % 3 - 1); taps 1: a 1x1 convolution); FP32
+ *     master weights, gradients and optimiser state.  Accumulation in FP32 on
+ *     the BF16 matrix cores.
+ *   - Device pointers only; the library allocates nothing.  Every call is
+ *     asynchronous on `stream` (a hipStream_t, NULL = default stream) and
+ *     returns 0 or a negative code: LBFZ_NN_EINVAL for an invalid argument,
+ *     LBFZ_NN_EHIP when a launch fails.
+ */
+#ifndef LBFZ_NN_H
+#define LBFZ_NN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { LBFZ_NN_OK = 0, LBFZ_NN_EINVAL = -1, LBFZ_NN_EHIP = -3 };
+
+/* Operands of a convolution. */
+typedef struct lbfz_conv_args {
+  const void* in;          /* forward: the layer input x; data gradient: dz (gradient at the
+                              layer's pre-activation); weight gradient: the layer input x   */
+  int32_t in_cs, in_co;    /* channel stride / offset of `in`                              */
+  int32_t Cin;             /* channels contracted per tap (forward / weight gradient: the
+                              layer's input channels; data gradient: its output channels) */
+  const void* w;           /* forward: W [N][taps][Cin]; data gradient: the transposed
+                              weights Wt [N][taps][Cin] (lbfz_nn_transpose_w); weight
+                              gradient: dz (N channels, channel stride dz_cs)             */
+  int32_t dz_cs;           /* weight gradient only                                         */
+  int32_t N;               /* output channels (weight gradient: the layer's outputs)       */
+  const float* bias;       /* forward: bias [N] or NULL; else NULL                         */
+  void* out;               /* forward / data gradient output (bf16, or FP32 if out_f32)    */
+  int32_t out_cs, out_co, out_f32;
+  int32_t relu;            /* forward: apply max(., 0) after the bias                      */
+  int32_t sign;            /* +1 forward (x at p + o(t)), -1 data gradient (dz at p - o(t)) */
+  int32_t B, H, W, taps;
+} lbfz_conv_args;
+
+/* Forward: out[p][n] = act(sum_{t,c} in[p + o(t)][c] W[n][t][c] + bias[n]);
+ * data gradient (sign -1, w = Wt): out[p][c'] = sum_{t,n} dz[p - o(t)][n]
+ * W[n][t][c'].  Implicit GEMM, M = pixels, N = a->N, K = taps * Cin. */
+int lbfz_nn_conv(const lbfz_conv_args* a, void* stream);
+
+/* Weight gradient dw[n][t][c] = sum_p dz[p][n] x[p + o(t)][c], FP32.  The
+ * pixel sum is split over nsplit block rows into part (nsplit * N * taps *
+ * Cin floats), then summed in a fixed order (deterministic). */
+int lbfz_nn_conv_wgrad(const lbfz_conv_args* a, float* part, int nsplit, float* dw, void* stream);
+
+/* Bias gradient db[c] = sum_p dz[p][c] (C <= 256 channels at stride cs), via
+ * nblocks partial rows in part (nblocks * C floats). */
+int lbfz_nn_bias_grad(const void* dz, long P, int cs, int C, float* part, int nblocks, float* db,
+                      void* stream);
+
+/* ReLU backward: dz = dy where y > 0 else 0 (y: the activated output). */
+int lbfz_nn_relu_bwd(const void* dy, int dy_cs, int dy_co, const void* y, int y_cs, int y_co,
+                     void* dz, int dz_cs, long P, int C, void* stream);
+
+/* 2x2 max pooling (stride 2) and its gradient (to the first maximum of each
+ * window; accumulate != 0 adds into dx instead of overwriting). */
+int lbfz_nn_maxpool2(const void* x, int x_cs, int x_co, void* y, int y_cs, int B, int H, int W,
+                     int C, void* stream);
+int lbfz_nn_maxpool2_bwd(const void* x, int x_cs, int x_co, const void* dy, int dy_cs, void* dx,
+                         int dx_cs, int dx_co, int accumulate, int B, int H, int W, int C,
+                         void* stream);
+
+/* Nearest 2x upsampling of a dense B x H x W x C tensor (to 2H x 2W) and its
+ * gradient (the sum over each 2x2 block). */
+int lbfz_nn_upsample2(const void* x, int B, int H, int W, int C, void* y, void* stream);
+int lbfz_nn_upsample2_bwd(const void* dy, int B, int H, int W, int C, void* dx, void* stream);
+
+/* n 32-bit words of p set to v (clears buffers without a runtime memset). */
+int lbfz_nn_fill_u32(void* p, long n, uint32_t v, void* stream);
+
+/* Mean squared error over the first C channels of out (FP32, stride out_cs)
+ * against tgt (FP32, C channels per pixel) into *loss (FP64, via nblocks
+ * partials in part); dout (bf16, stride out_cs, or NULL) = d loss / d out. */
+int lbfz_nn_mse(const float* out, int out_cs, const float* tgt, long P, int C, void* dout,
+                double* part, int nblocks, double* loss, void* stream);
+
+/* One Adam step (bias-corrected with the 1-based step number) on n FP32
+ * weights w with gradients g and moments m, v; wb (bf16, or NULL) receives
+ * the updated weights. */
+int lbfz_nn_adam(float* w, const float* g, float* m, float* v, void* wb, long n, float lr,
+                 float b1, float b2, float eps, int step, void* stream);
+
+int lbfz_nn_to_bf16(const float* src, void* dst, long n, void* stream);
+
+/* Wt[c][t][n] = W[n][t][c] (weights of the data-gradient convolution). */
+int lbfz_nn_transpose_w(const void* w, int N, int taps, int C, void* wt, void* stream);
+
+/* Network input from solver fields: nf FP32 planes of ny x nx (row-major),
+ * the S x S crop at (x0, y0) (periodic in x, clamped in y), normalised as
+ * (v - shift[f]) * scale[f], into image b of a bf16 NHWC tensor of cs
+ * channels (channels nf .. cs - 1 zero). */
+int lbfz_nn_pack_fields(const float* planes, int nf, int nx, int ny, int x0, int y0, int S,
+                        const float* shift, const float* scale, void* dst, int cs, int b,
+                        void* stream);
+
+/* Training target of the same crop: ((after - before) - shift[f]) * scale[f],
+ * FP32 [S * S][nf] for image b. */
+int lbfz_nn_pack_delta(const float* after, const float* before, int nf, int nx, int ny, int x0,
+                       int y0, int S, const float* shift, const float* scale, float* dst, int b,
+                       void* stream);
+
+/* Prediction of a whole grid from image b of the network output (FP32, stride
+ * out_cs, the grid itself as the image): pred[f] = before[f] + out[f] /
+ * scale[f] + shift[f], nf planes. */
+int lbfz_nn_apply_delta(const float* out, int out_cs, const float* before, int nf, int nx, int ny,
+                        const float* shift, const float* scale, float* pred, int b, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBFZ_NN_H */

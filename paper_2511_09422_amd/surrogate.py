@@ -1,0 +1,391 @@
+"""Learned surrogate of the coupled LB freezing step: a 3-level U-Net that maps
+the six fields (phi, f_l, T, C, u_x, u_y) of a 2D grid to their change over
+64 LB steps, built from the BF16 MFMA kernels of ``liblbfz.so``
+(``include/lbfz_nn.h``).  The binding marshals arguments only; PyTorch holds
+the device memory.
+
+Network (NHWC, bf16 activations, FP32 master weights; 3x3 convolutions with
+zero padding, ReLU after every convolution but the head):
+
+    X0 (16 ch: 6 fields + zero padding)
+    L1a 16->32, L1b 32->32 = S1 ........................ CAT1[:, 32:64]
+    maxpool -> L2a 32->64, L2b 64->64 = S2 .............. CAT2[:, 64:128]
+    maxpool -> L3a 64->128, L3b 128->128
+    upsample -> U2 128->64 ............................. CAT2[:, 0:64]
+    L4a 128->64, L4b 64->64
+    upsample -> U1 64->32 .............................. CAT1[:, 0:32]
+    L5a 64->32, L5b 32->32, head 1x1 32->8 (6 used), FP32 output
+
+The skip concatenations are channel slices of CAT1 / CAT2 written in place by
+the layers that produce them.  Screening: the prediction of a grid is
+accepted when its phase-field mass residual
+|sum dphi - (1 - rho_s / rho_l) sum df_s| / sum (1 + phi_in) / 2 is at most
+1e-3, else the grid is advanced by the LB step instead.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import lbfz
+
+NF = 6           # fields: phi, f_l, T, C, u_x, u_y
+CIN0 = 16        # padded input channels
+HEAD = 8         # padded head channels
+FIELD_NAMES = ("phi", "fl", "T", "C", "ux", "uy")
+
+
+class lbfz_conv_args(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_void_p), ("in_cs", ctypes.c_int32), ("in_co", ctypes.c_int32),
+                ("Cin", ctypes.c_int32), ("w", ctypes.c_void_p), ("dz_cs", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("bias", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("out_cs", ctypes.c_int32), ("out_co", ctypes.c_int32),
+                ("out_f32", ctypes.c_int32), ("relu", ctypes.c_int32), ("sign", ctypes.c_int32),
+                ("B", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("taps", ctypes.c_int32)]
+
+
+_nn = None
+
+
+def nnlib():
+    global _nn
+    if _nn is None:
+        L = lbfz.lib()
+        vp, i32, lg = ctypes.c_void_p, ctypes.c_int32, ctypes.c_long
+        f32, u32 = ctypes.c_float, ctypes.c_uint32
+        cp = ctypes.POINTER(lbfz_conv_args)
+        sig = {
+            "lbfz_nn_conv": [cp, vp],
+            "lbfz_nn_conv_wgrad": [cp, vp, i32, vp, vp],
+            "lbfz_nn_bias_grad": [vp, lg, i32, i32, vp, i32, vp, vp],
+            "lbfz_nn_relu_bwd": [vp, i32, i32, vp, i32, i32, vp, i32, lg, i32, vp],
+            "lbfz_nn_maxpool2": [vp, i32, i32, vp, i32, i32, i32, i32, i32, vp],
+            "lbfz_nn_maxpool2_bwd": [vp, i32, i32, vp, i32, vp, i32, i32, i32, i32, i32, i32, i32,
+                                     vp],
+            "lbfz_nn_upsample2": [vp, i32, i32, i32, i32, vp, vp],
+            "lbfz_nn_upsample2_bwd": [vp, i32, i32, i32, i32, vp, vp],
+            "lbfz_nn_fill_u32": [vp, lg, u32, vp],
+            "lbfz_nn_mse": [vp, i32, vp, lg, i32, vp, vp, i32, vp, vp],
+            "lbfz_nn_adam": [vp, vp, vp, vp, vp, lg, f32, f32, f32, f32, i32, vp],
+            "lbfz_nn_to_bf16": [vp, vp, lg, vp],
+            "lbfz_nn_transpose_w": [vp, i32, i32, i32, vp, vp],
+            "lbfz_nn_pack_fields": [vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, i32, i32, vp],
+            "lbfz_nn_pack_delta": [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, i32, vp],
+            "lbfz_nn_apply_delta": [vp, i32, vp, i32, i32, i32, vp, vp, vp, i32, vp],
+        }
+        for nm, args in sig.items():
+            fn = getattr(L, nm)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        _nn = L
+    return _nn
+
+
+def _ck(rc, where):
+    if rc != 0:
+        raise RuntimeError(f"{where} failed (code {rc})")
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def conv_args(x, x_cs, x_co, cin, w, n, out, out_cs, out_co, B, H, W, taps, bias=None,
+              relu=False, sign=1, out_f32=False, dz_cs=0):
+    a = lbfz_conv_args()
+    a.in_ = x.data_ptr()
+    a.in_cs, a.in_co, a.Cin = x_cs, x_co, cin
+    a.w = w.data_ptr()
+    a.dz_cs = dz_cs
+    a.N = n
+    a.bias = bias.data_ptr() if bias is not None else None
+    a.out = out.data_ptr() if out is not None else None
+    a.out_cs, a.out_co, a.out_f32 = out_cs, out_co, int(out_f32)
+    a.relu, a.sign = int(relu), sign
+    a.B, a.H, a.W, a.taps = B, H, W, taps
+    return a
+
+
+@dataclass
+class Layer:
+    name: str
+    cin: int
+    cout: int
+    taps: int
+    relu: bool
+    level: int        # 0: full size, 1: /2, 2: /4
+
+
+LAYERS = (
+    Layer("L1a", CIN0, 32, 9, True, 0), Layer("L1b", 32, 32, 9, True, 0),
+    Layer("L2a", 32, 64, 9, True, 1), Layer("L2b", 64, 64, 9, True, 1),
+    Layer("L3a", 64, 128, 9, True, 2), Layer("L3b", 128, 128, 9, True, 2),
+    Layer("U2", 128, 64, 9, True, 1), Layer("L4a", 128, 64, 9, True, 1),
+    Layer("L4b", 64, 64, 9, True, 1), Layer("U1", 64, 32, 9, True, 0),
+    Layer("L5a", 64, 32, 9, True, 0), Layer("L5b", 32, 32, 9, True, 0),
+    Layer("head", 32, HEAD, 1, False, 0),
+)
+
+
+def init_weights(seed: int = 0) -> dict:
+    """He-normal weights [cout][taps][cin] (zero for the padded input channels
+    and head outputs), zero biases; FP32 numpy."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for L in LAYERS:
+        fan_in = L.taps * (NF if L.name == "L1a" else L.cin)
+        w = rng.standard_normal((L.cout, L.taps, L.cin)) * np.sqrt(2.0 / fan_in)
+        if L.name == "L1a":
+            w[:, :, NF:] = 0.0
+        if L.name == "head":
+            w *= 0.1
+            w[NF:] = 0.0
+        out[L.name] = (w.astype(np.float32), np.zeros(L.cout, np.float32))
+    return out
+
+
+class UNet:
+    """The network on one GPU for batches of B images of S x S pixels."""
+
+    def __init__(self, weights: dict, B: int, S: int, device: int = 0, stream=None):
+        import torch
+        if S % 4:
+            raise ValueError("image side must be a multiple of 4")
+        self.torch = torch
+        self.dev = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        self.B, self.S = B, S
+        self.L = {L.name: L for L in LAYERS}
+        # parameters: one flat FP32 buffer (master), bf16 copy, grads, Adam moments
+        self.offsets = {}
+        n = 0
+        for L in LAYERS:
+            nw = L.cout * L.taps * L.cin
+            self.offsets[L.name] = (n, nw, n + nw, L.cout)
+            n += nw + L.cout
+        self.nparam = n
+        f = dict(dtype=torch.float32, device=self.dev)
+        self.wf = torch.zeros(n, **f)
+        host = np.zeros(n, np.float32)
+        for L in LAYERS:
+            o, nw, ob, nb = self.offsets[L.name]
+            w, b = weights[L.name]
+            host[o:o + nw] = w.reshape(-1)
+            host[ob:ob + nb] = b
+        self.wf.copy_(torch.from_numpy(host))
+        self.gf = torch.zeros(n, **f)
+        self.m = torch.zeros(n, **f)
+        self.v = torch.zeros(n, **f)
+        self.wb = torch.zeros(n, dtype=torch.bfloat16, device=self.dev)
+        self.wt = {L.name: torch.zeros(L.cout * L.taps * L.cin, dtype=torch.bfloat16,
+                                       device=self.dev) for L in LAYERS}
+        self.adam_step = 0
+        self._sync_bf16()
+        # activations and gradients
+        bf = dict(dtype=torch.bfloat16, device=self.dev)
+        s0, s1, s2 = S * S, (S // 2) ** 2, (S // 4) ** 2
+        t = {}
+        t["X0"] = torch.zeros(B * s0 * CIN0, **bf)
+        t["A1"] = torch.zeros(B * s0 * 32, **bf)
+        t["CAT1"] = torch.zeros(B * s0 * 64, **bf)
+        t["P1"] = torch.zeros(B * s1 * 32, **bf)
+        t["A2"] = torch.zeros(B * s1 * 64, **bf)
+        t["CAT2"] = torch.zeros(B * s1 * 128, **bf)
+        t["P2"] = torch.zeros(B * s2 * 64, **bf)
+        t["A3"] = torch.zeros(B * s2 * 128, **bf)
+        t["A3b"] = torch.zeros(B * s2 * 128, **bf)
+        t["U2"] = torch.zeros(B * s1 * 128, **bf)
+        t["A4"] = torch.zeros(B * s1 * 64, **bf)
+        t["A4b"] = torch.zeros(B * s1 * 64, **bf)
+        t["U1"] = torch.zeros(B * s0 * 64, **bf)
+        t["A5"] = torch.zeros(B * s0 * 32, **bf)
+        t["A5b"] = torch.zeros(B * s0 * 32, **bf)
+        t["OUT"] = torch.zeros(B * s0 * HEAD, **f)
+        # gradients (dX of each tensor) and pre-activation gradients (dz)
+        for k in ("A1", "CAT1", "P1", "A2", "CAT2", "P2", "A3", "A3b", "U2", "A4", "A4b", "U1",
+                  "A5", "A5b"):
+            t["d" + k] = torch.zeros_like(t[k])
+        t["dOUT"] = torch.zeros(B * s0 * HEAD, **bf)
+        t["dz"] = torch.zeros(B * s0 * 128, **bf)   # largest dz (reused per layer)
+        self.t = t
+        self.nsplit = 64
+        maxw = max(L.cout * L.taps * L.cin for L in LAYERS)
+        self.part = torch.zeros(self.nsplit * maxw, **f)
+        self.bpart = torch.zeros(256 * 256, **f)
+        self.lpart = torch.zeros(1024, dtype=torch.float64, device=self.dev)
+        self.loss_t = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        self.target = torch.zeros(B * s0 * NF, **f)
+
+    # ------------------------------------------------------------------ utils
+    @property
+    def st(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def _sync_bf16(self):
+        L = nnlib()
+        _ck(L.lbfz_nn_to_bf16(_p(self.wf), _p(self.wb), self.nparam, self.st), "to_bf16")
+        for Ly in LAYERS:
+            o, nw, _, _ = self.offsets[Ly.name]
+            _ck(L.lbfz_nn_transpose_w(ctypes.c_void_p(self.wb.data_ptr() + 2 * o), Ly.cout,
+                                      Ly.taps, Ly.cin, _p(self.wt[Ly.name]), self.st),
+                "transpose_w")
+
+    def _w(self, name):
+        o, nw, ob, nb = self.offsets[name]
+        return (ctypes.c_void_p(self.wb.data_ptr() + 2 * o),
+                ctypes.c_void_p(self.wf.data_ptr() + 4 * ob))
+
+    def _dims(self, level):
+        s = self.S >> level
+        return self.B, s, s
+
+    # ---------------------------------------------------------------- forward
+    def _conv(self, name, x, x_cs, x_co, out, out_cs, out_co, out_f32=False):
+        Ly = self.L[name]
+        B, H, W = self._dims(Ly.level)
+        wb, bias = self._w(name)
+        a = lbfz_conv_args()
+        a.in_, a.in_cs, a.in_co, a.Cin = x.data_ptr(), x_cs, x_co, Ly.cin
+        a.w, a.dz_cs, a.N = wb.value, 0, Ly.cout
+        a.bias, a.out = bias.value, out.data_ptr()
+        a.out_cs, a.out_co, a.out_f32 = out_cs, out_co, int(out_f32)
+        a.relu, a.sign = int(Ly.relu), 1
+        a.B, a.H, a.W, a.taps = B, H, W, Ly.taps
+        _ck(nnlib().lbfz_nn_conv(ctypes.byref(a), self.st), "conv " + name)
+
+    def forward(self):
+        """X0 -> OUT (FP32, HEAD channels)."""
+        L, t = nnlib(), self.t
+        B, S = self.B, self.S
+        self._conv("L1a", t["X0"], CIN0, 0, t["A1"], 32, 0)
+        self._conv("L1b", t["A1"], 32, 0, t["CAT1"], 64, 32)
+        _ck(L.lbfz_nn_maxpool2(_p(t["CAT1"]), 64, 32, _p(t["P1"]), 32, B, S, S, 32, self.st),
+            "pool1")
+        self._conv("L2a", t["P1"], 32, 0, t["A2"], 64, 0)
+        self._conv("L2b", t["A2"], 64, 0, t["CAT2"], 128, 64)
+        _ck(L.lbfz_nn_maxpool2(_p(t["CAT2"]), 128, 64, _p(t["P2"]), 64, B, S // 2, S // 2, 64,
+                               self.st), "pool2")
+        self._conv("L3a", t["P2"], 64, 0, t["A3"], 128, 0)
+        self._conv("L3b", t["A3"], 128, 0, t["A3b"], 128, 0)
+        _ck(L.lbfz_nn_upsample2(_p(t["A3b"]), B, S // 4, S // 4, 128, _p(t["U2"]), self.st), "up2")
+        self._conv("U2", t["U2"], 128, 0, t["CAT2"], 128, 0)
+        self._conv("L4a", t["CAT2"], 128, 0, t["A4"], 64, 0)
+        self._conv("L4b", t["A4"], 64, 0, t["A4b"], 64, 0)
+        _ck(L.lbfz_nn_upsample2(_p(t["A4b"]), B, S // 2, S // 2, 64, _p(t["U1"]), self.st), "up1")
+        self._conv("U1", t["U1"], 64, 0, t["CAT1"], 64, 0)
+        self._conv("L5a", t["CAT1"], 64, 0, t["A5"], 32, 0)
+        self._conv("L5b", t["A5"], 32, 0, t["A5b"], 32, 0)
+        self._conv("head", t["A5b"], 32, 0, t["OUT"], HEAD, 0, out_f32=True)
+
+    # --------------------------------------------------------------- backward
+    def _layer_bwd(self, name, x, x_cs, x_co, dy, dy_cs, dy_co, y, y_cs, y_co, dx, dx_cs,
+                   dx_co, need_dx=True):
+        """Gradients of one convolution: dz = relu'(y) dy, dW, db into gf, and
+        dx (overwritten) when need_dx."""
+        L, t = nnlib(), self.t
+        Ly = self.L[name]
+        B, H, W = self._dims(Ly.level)
+        P = B * H * W
+        N = Ly.cout
+        st = self.st
+        if Ly.relu:
+            dz = t["dz"]
+            _ck(L.lbfz_nn_relu_bwd(_p(dy), dy_cs, dy_co, _p(y), y_cs, y_co, _p(dz), N, P, N, st),
+                "relu_bwd " + name)
+            dz_p, dz_cs = dz, N
+        else:
+            if dy_co != 0:
+                raise ValueError("a head without activation reads its gradient at offset 0")
+            dz_p, dz_cs = dy, dy_cs
+        o, nw, ob, nb = self.offsets[name]
+        a = lbfz_conv_args()
+        a.in_, a.in_cs, a.in_co, a.Cin = x.data_ptr(), x_cs, x_co, Ly.cin
+        a.w, a.dz_cs, a.N = dz_p.data_ptr(), dz_cs, N
+        a.B, a.H, a.W, a.taps, a.sign = B, H, W, Ly.taps, 1
+        _ck(L.lbfz_nn_conv_wgrad(ctypes.byref(a), _p(self.part), self.nsplit,
+                                 ctypes.c_void_p(self.gf.data_ptr() + 4 * o), st),
+            "wgrad " + name)
+        _ck(L.lbfz_nn_bias_grad(_p(dz_p), P, dz_cs, N, _p(self.bpart), 256,
+                                ctypes.c_void_p(self.gf.data_ptr() + 4 * ob), st),
+            "bias_grad " + name)
+        if need_dx:
+            d = lbfz_conv_args()
+            d.in_, d.in_cs, d.in_co, d.Cin = dz_p.data_ptr(), dz_cs, 0, N
+            d.w, d.N = self.wt[name].data_ptr(), Ly.cin
+            d.out, d.out_cs, d.out_co, d.out_f32 = dx.data_ptr(), dx_cs, dx_co, 0
+            d.relu, d.sign = 0, -1
+            d.B, d.H, d.W, d.taps = B, H, W, Ly.taps
+            _ck(L.lbfz_nn_conv(ctypes.byref(d), st), "dgrad " + name)
+
+    def backward(self):
+        """Gradients of the loss (dOUT set by loss()) into gf."""
+        L, t = nnlib(), self.t
+        B, S = self.B, self.S
+        st = self.st
+        self._layer_bwd("head", t["A5b"], 32, 0, t["dOUT"], HEAD, 0, None, 0, 0, t["dA5b"], 32, 0)
+        self._layer_bwd("L5b", t["A5"], 32, 0, t["dA5b"], 32, 0, t["A5b"], 32, 0, t["dA5"], 32, 0)
+        self._layer_bwd("L5a", t["CAT1"], 64, 0, t["dA5"], 32, 0, t["A5"], 32, 0, t["dCAT1"], 64, 0)
+        self._layer_bwd("U1", t["U1"], 64, 0, t["dCAT1"], 64, 0, t["CAT1"], 64, 0, t["dU1"], 64, 0)
+        _ck(L.lbfz_nn_upsample2_bwd(_p(t["dU1"]), B, S // 2, S // 2, 64, _p(t["dA4b"]), st),
+            "up1_bwd")
+        self._layer_bwd("L4b", t["A4"], 64, 0, t["dA4b"], 64, 0, t["A4b"], 64, 0, t["dA4"], 64, 0)
+        self._layer_bwd("L4a", t["CAT2"], 128, 0, t["dA4"], 64, 0, t["A4"], 64, 0, t["dCAT2"], 128,
+                        0)
+        self._layer_bwd("U2", t["U2"], 128, 0, t["dCAT2"], 128, 0, t["CAT2"], 128, 0, t["dU2"],
+                        128, 0)
+        _ck(L.lbfz_nn_upsample2_bwd(_p(t["dU2"]), B, S // 4, S // 4, 128, _p(t["dA3b"]), st),
+            "up2_bwd")
+        self._layer_bwd("L3b", t["A3"], 128, 0, t["dA3b"], 128, 0, t["A3b"], 128, 0, t["dA3"],
+                        128, 0)
+        self._layer_bwd("L3a", t["P2"], 64, 0, t["dA3"], 128, 0, t["A3"], 128, 0, t["dP2"], 64, 0)
+        _ck(L.lbfz_nn_maxpool2_bwd(_p(t["CAT2"]), 128, 64, _p(t["dP2"]), 64, _p(t["dCAT2"]), 128,
+                                   64, 1, B, S // 2, S // 2, 64, st), "pool2_bwd")
+        self._layer_bwd("L2b", t["A2"], 64, 0, t["dCAT2"], 128, 64, t["CAT2"], 128, 64, t["dA2"],
+                        64, 0)
+        self._layer_bwd("L2a", t["P1"], 32, 0, t["dA2"], 64, 0, t["A2"], 64, 0, t["dP1"], 32, 0)
+        _ck(L.lbfz_nn_maxpool2_bwd(_p(t["CAT1"]), 64, 32, _p(t["dP1"]), 32, _p(t["dCAT1"]), 64,
+                                   32, 1, B, S, S, 32, st), "pool1_bwd")
+        self._layer_bwd("L1b", t["A1"], 32, 0, t["dCAT1"], 64, 32, t["CAT1"], 64, 32, t["dA1"], 32,
+                        0)
+        self._layer_bwd("L1a", t["X0"], CIN0, 0, t["dA1"], 32, 0, t["A1"], 32, 0, None, 0, 0,
+                        need_dx=False)
+
+    def loss(self, with_grad: bool = True) -> None:
+        """MSE of OUT's first NF channels against target (FP32 [P][NF]); the
+        value lands in loss_t (device), dOUT is set when with_grad."""
+        P = self.B * self.S * self.S
+        _ck(nnlib().lbfz_nn_mse(_p(self.t["OUT"]), HEAD, _p(self.target), P, NF,
+                                _p(self.t["dOUT"]) if with_grad else None, _p(self.lpart),
+                                1024, _p(self.loss_t), self.st), "mse")
+
+    def adam(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+        self.adam_step += 1
+        _ck(nnlib().lbfz_nn_adam(_p(self.wf), _p(self.gf), _p(self.m), _p(self.v), _p(self.wb),
+                                 self.nparam, lr, b1, b2, eps, self.adam_step, self.st), "adam")
+        for Ly in LAYERS:
+            o, nw, _, _ = self.offsets[Ly.name]
+            _ck(nnlib().lbfz_nn_transpose_w(ctypes.c_void_p(self.wb.data_ptr() + 2 * o), Ly.cout,
+                                            Ly.taps, Ly.cin, _p(self.wt[Ly.name]), self.st),
+                "transpose_w")
+
+    def weights(self) -> dict:
+        """Current FP32 weights as numpy, layout of init_weights."""
+        host = self.wf.cpu().numpy()
+        out = {}
+        for Ly in LAYERS:
+            o, nw, ob, nb = self.offsets[Ly.name]
+            out[Ly.name] = (host[o:o + nw].reshape(Ly.cout, Ly.taps, Ly.cin).copy(),
+                            host[ob:ob + nb].copy())
+        return out
+
+    def grads(self) -> dict:
+        host = self.gf.cpu().numpy()
+        out = {}
+        for Ly in LAYERS:
+            o, nw, ob, nb = self.offsets[Ly.name]
+            out[Ly.name] = (host[o:o + nw].reshape(Ly.cout, Ly.taps, Ly.cin).copy(),
+                            host[ob:ob + nb].copy())
+        return out

@@ -14,8 +14,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "lbfz.h")).read()
-    return sorted(set(re.findall(r"\b(lbfz_[a-z_]+)\s*\(", txt)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(lbfz_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol():
@@ -33,6 +38,17 @@ def test_params_struct_matches_header():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S).split("{", 1)[1]
     fields = re.findall(r"\b([a-zA-Z_][a-zA-Z0-9_]*)\s*(?:\[3\])?\s*[,;]", body)
     assert fields == [f for f, _ in lbfz.lbfz_params._fields_]
+
+
+def test_conv_args_struct_matches_header():
+    from paper_2511_09422_amd import surrogate
+    txt = open(os.path.join(ROOT, "include", "lbfz_nn.h")).read()
+    body = txt[txt.index("typedef struct lbfz_conv_args"):txt.index("} lbfz_conv_args;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S).split("{", 1)[1]
+    fields = re.findall(r"\b([a-zA-Z_][a-zA-Z0-9_]*)\s*[,;]", body)
+    mirror = [f.rstrip("_") for f, _ in surrogate.lbfz_conv_args._fields_]
+    assert fields == mirror
+    surrogate.nnlib()   # every kernel entry point binds
 
 
 def test_strerror_and_workspace_errors():

@@ -1,0 +1,195 @@
+"""BF16 MFMA kernels of the surrogate network against plain PyTorch CPU float64
+on the same bf16-rounded operands.
+
+Bars (relative to the largest reference value): forward and data-gradient
+outputs stored in bf16 within 6e-3 (bf16 rounding is 2^-9 of a value; the
+FP32 accumulation adds < 1e-5); FP32 outputs (weight gradients, head output)
+within 1e-4 (bf16 products are exact in FP32, the sums carry FP32 rounding of
+up to ~1e5 terms).  The whole network against the CPU reference with the same
+weights: loss within 1e-2, output within 3e-2, and every parameter gradient
+within 0.1 relative L2 with cosine similarity >= 0.995 -- the activations and
+the gradients flowing back are rounded to bf16 (2^-9) at every one of up to
+13 layers, so the first layers' gradients carry several percent of rounding
+(7.6e-2 measured for the first layer, the deepest in the backward chain)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16(a):
+    import torch
+    return torch.tensor(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a, np.float32)).to(dtype).cuda()
+
+
+def _rel(got, ref):
+    return float(np.abs(np.asarray(got, np.float64) - ref).max() / max(np.abs(ref).max(), 1e-30))
+
+
+@pytest.mark.parametrize("B,H,W,Cin,N,taps", [(2, 16, 16, 16, 32, 9), (1, 12, 20, 32, 40, 9),
+                                              (2, 8, 8, 64, 72, 9), (2, 16, 16, 32, 8, 1)])
+def test_conv_forward_and_gradients(B, H, W, Cin, N, taps):
+    import torch
+    import torch.nn.functional as F
+    from paper_2511_09422_amd import surrogate as sg
+    import ctypes
+    rng = np.random.default_rng(B * 1000 + H + Cin + N + taps)
+    x = _bf16(rng.standard_normal((B, H, W, Cin)))
+    w = _bf16(rng.standard_normal((N, taps, Cin)) / np.sqrt(taps * Cin))
+    bias = rng.standard_normal(N).astype(np.float32)
+    dz = _bf16(rng.standard_normal((B, H, W, N)))
+    k = 3 if taps == 9 else 1
+    tw = torch.tensor(np.transpose(w, (0, 2, 1)).reshape(N, Cin, k, k), requires_grad=True)
+    tx = torch.tensor(x).permute(0, 3, 1, 2).requires_grad_(True)
+    ty = F.conv2d(tx, tw, torch.tensor(bias, dtype=torch.float64), padding=k // 2)
+    ty.backward(torch.tensor(dz).permute(0, 3, 1, 2))
+    ref_y = ty.detach().permute(0, 2, 3, 1).numpy()
+    ref_dx = tx.grad.permute(0, 2, 3, 1).numpy()
+    ref_dw = np.transpose(tw.grad.numpy().reshape(N, Cin, -1), (0, 2, 1))
+
+    L = sg.nnlib()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    dx_, dw_, dz_ = _dev(x, torch.bfloat16), _dev(w, torch.bfloat16), _dev(dz, torch.bfloat16)
+    db = torch.tensor(bias).cuda()
+    for out_f32 in (False, True):
+        y = torch.zeros(B * H * W * N, dtype=torch.float32 if out_f32 else torch.bfloat16).cuda()
+        a = sg.conv_args(dx_, Cin, 0, Cin, dw_, N, y, N, 0, B, H, W, taps, bias=db,
+                         out_f32=out_f32)
+        assert L.lbfz_nn_conv(ctypes.byref(a), st) == 0
+        got = y.float().cpu().numpy().reshape(B, H, W, N)
+        tol = 1e-4 if out_f32 else 6e-3
+        assert _rel(got, ref_y) <= tol, (out_f32, _rel(got, ref_y))
+    # data gradient: transposed weights, negated offsets
+    wt = torch.zeros(N * taps * Cin, dtype=torch.bfloat16).cuda()
+    assert L.lbfz_nn_transpose_w(sg._p(dw_), N, taps, Cin, sg._p(wt), st) == 0
+    gx = torch.zeros(B * H * W * Cin, dtype=torch.bfloat16).cuda()
+    a = sg.conv_args(dz_, N, 0, N, wt, Cin, gx, Cin, 0, B, H, W, taps, sign=-1)
+    assert L.lbfz_nn_conv(ctypes.byref(a), st) == 0
+    assert _rel(gx.float().cpu().numpy().reshape(B, H, W, Cin), ref_dx) <= 6e-3
+    # weight gradient (FP32, split over pixels)
+    part = torch.zeros(16 * N * taps * Cin, dtype=torch.float32).cuda()
+    gw = torch.zeros(N * taps * Cin, dtype=torch.float32).cuda()
+    a = sg.conv_args(dx_, Cin, 0, Cin, dz_, N, None, 0, 0, B, H, W, taps, dz_cs=N)
+    assert L.lbfz_nn_conv_wgrad(ctypes.byref(a), sg._p(part), 16, sg._p(gw), st) == 0
+    assert _rel(gw.cpu().numpy().reshape(N, taps, Cin), ref_dw) <= 1e-4
+    # bias gradient
+    bpart = torch.zeros(8 * N, dtype=torch.float32).cuda()
+    gb = torch.zeros(N, dtype=torch.float32).cuda()
+    assert L.lbfz_nn_bias_grad(sg._p(dz_), B * H * W, N, N, sg._p(bpart), 8, sg._p(gb), st) == 0
+    assert _rel(gb.cpu().numpy(), dz.sum(axis=(0, 1, 2))) <= 1e-5
+
+
+def test_pool_and_upsample():
+    import torch
+    import torch.nn.functional as F
+    import ctypes
+    from paper_2511_09422_amd import surrogate as sg
+    rng = np.random.default_rng(5)
+    B, H, W, C = 2, 8, 12, 16
+    x = _bf16(rng.standard_normal((B, H, W, C)))
+    g = _bf16(rng.standard_normal((B, H // 2, W // 2, C)))
+    L = sg.nnlib()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    tx = torch.tensor(x).permute(0, 3, 1, 2).requires_grad_(True)
+    ty = F.max_pool2d(tx, 2)
+    ty.backward(torch.tensor(g).permute(0, 3, 1, 2))
+    dx_ = _dev(x, torch.bfloat16)
+    y = torch.zeros(B * (H // 2) * (W // 2) * C, dtype=torch.bfloat16).cuda()
+    assert L.lbfz_nn_maxpool2(sg._p(dx_), C, 0, sg._p(y), C, B, H, W, C, st) == 0
+    assert np.array_equal(y.float().cpu().numpy().reshape(B, H // 2, W // 2, C),
+                          ty.detach().permute(0, 2, 3, 1).numpy())
+    gx = torch.zeros(B * H * W * C, dtype=torch.bfloat16).cuda()
+    assert L.lbfz_nn_maxpool2_bwd(sg._p(dx_), C, 0, sg._p(_dev(g, torch.bfloat16)), C, sg._p(gx),
+                                  C, 0, 0, B, H, W, C, st) == 0
+    assert np.array_equal(gx.float().cpu().numpy().reshape(B, H, W, C),
+                          tx.grad.permute(0, 2, 3, 1).numpy())
+    # upsampling: forward and gradient
+    up = torch.zeros(B * 4 * H * W * C, dtype=torch.bfloat16).cuda()
+    assert L.lbfz_nn_upsample2(sg._p(dx_), B, H, W, C, sg._p(up), st) == 0
+    ref = F.interpolate(torch.tensor(x).permute(0, 3, 1, 2), scale_factor=2, mode="nearest")
+    assert np.array_equal(up.float().cpu().numpy().reshape(B, 2 * H, 2 * W, C),
+                          ref.permute(0, 2, 3, 1).numpy())
+    gu = _bf16(rng.standard_normal((B, 2 * H, 2 * W, C)))
+    gd = torch.zeros(B * H * W * C, dtype=torch.bfloat16).cuda()
+    assert L.lbfz_nn_upsample2_bwd(sg._p(_dev(gu, torch.bfloat16)), B, H, W, C, sg._p(gd), st) == 0
+    refg = gu.reshape(B, H, 2, W, 2, C).sum(axis=(2, 4))
+    assert _rel(gd.float().cpu().numpy().reshape(B, H, W, C), refg) <= 6e-3
+
+
+def test_unet_loss_and_gradients_against_cpu_reference():
+    import torch
+    from oracle import unet_ref
+    from paper_2511_09422_amd import surrogate as sg
+    B, S = 2, 32
+    rng = np.random.default_rng(11)
+    w = sg.init_weights(3)
+    for k in w:   # weights as the GPU sees them (bf16)
+        w[k] = (_bf16(w[k][0]).astype(np.float32), w[k][1] + 0.01 * rng.standard_normal(
+            w[k][1].shape).astype(np.float32))
+    x = np.zeros((B, S, S, sg.CIN0))
+    yy, xx = np.meshgrid(np.arange(S), np.arange(S), indexing="ij")
+    for c in range(sg.NF):
+        x[..., c] = np.sin(0.2 * (c + 1) * xx + 0.3 * yy)[None] + 0.3 * rng.standard_normal((B, S, S))
+    x = _bf16(x)
+    tgt = rng.standard_normal((B, S, S, sg.NF)) * 0.5
+    loss_ref, grads_ref, out_ref = unet_ref.loss_and_grads(x, w, tgt, sg.NF)
+
+    net = sg.UNet(w, B, S)
+    net.t["X0"].copy_(torch.tensor(x.reshape(-1), dtype=torch.float32).to(torch.bfloat16))
+    net.target.copy_(torch.tensor(tgt.reshape(-1), dtype=torch.float32))
+    net.forward()
+    net.loss()
+    net.backward()
+    torch.cuda.synchronize()
+    out = net.t["OUT"].cpu().numpy().reshape(B, S, S, sg.HEAD)
+    loss = float(net.loss_t.cpu().numpy()[0])
+    print(f"[unet] loss gpu {loss:.6f} cpu {loss_ref:.6f}; out rel {_rel(out, out_ref):.2e}",
+          flush=True)
+    assert abs(loss - loss_ref) <= 1e-2 * loss_ref
+    assert _rel(out, out_ref) <= 3e-2
+    g = net.grads()
+    bad = []
+    for name in g:
+        for j, part in enumerate(("w", "b")):
+            a, r = g[name][j].ravel(), grads_ref[name][j].ravel()
+            if name == "head":   # only the used outputs carry gradient
+                a, r = g[name][j][:sg.NF].ravel(), grads_ref[name][j][:sg.NF].ravel()
+            rel = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+            cos = float(a @ r / max(np.linalg.norm(a) * np.linalg.norm(r), 1e-30))
+            print(f"[unet] grad {name}.{part} rel L2 {rel:.2e} cos {cos:.5f}", flush=True)
+            if rel > 0.1 or cos < 0.995:
+                bad.append((name, part, rel, cos))
+    assert not bad, bad
+
+
+def test_training_reduces_loss():
+    import torch
+    from paper_2511_09422_amd import surrogate as sg
+    B, S = 4, 64
+    rng = np.random.default_rng(2)
+    net = sg.UNet(sg.init_weights(0), B, S)
+    yy, xx = np.meshgrid(np.arange(S), np.arange(S), indexing="ij")
+    x = np.zeros((B, S, S, sg.CIN0), np.float32)
+    tgt = np.zeros((B, S, S, sg.NF), np.float32)
+    for b in range(B):
+        for c in range(sg.NF):
+            ph = rng.uniform(0, 6)
+            x[b, :, :, c] = np.sin(0.1 * (c + 1) * xx + 0.07 * yy + ph)
+            tgt[b, :, :, c] = 0.5 * np.cos(0.1 * (c + 1) * xx + 0.07 * yy + ph)
+    net.t["X0"].copy_(torch.tensor(x.reshape(-1)).to(torch.bfloat16))
+    net.target.copy_(torch.tensor(tgt.reshape(-1)))
+    losses = []
+    for it in range(60):
+        net.forward()
+        net.loss()
+        net.backward()
+        net.adam(2e-3)
+        losses.append(float(net.loss_t.cpu().numpy()[0]))
+    print(f"[unet] training loss {losses[0]:.4f} -> {losses[-1]:.4f}", flush=True)
+    assert np.isfinite(losses).all()
+    assert losses[-1] < 0.25 * losses[0]
