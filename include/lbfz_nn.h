@@ -90,10 +90,11 @@ int lbfz_nn_upsample2_bwd(const void* dy, int B, int H, int W, int C, void* dx, 
 int lbfz_nn_fill_u32(void* p, long n, uint32_t v, void* stream);
 
 /* Mean squared error over the first C channels of out (FP32, stride out_cs)
- * against tgt (FP32, C channels per pixel) into *loss (FP64, via nblocks
- * partials in part); dout (bf16, stride out_cs, or NULL) = d loss / d out. */
-int lbfz_nn_mse(const float* out, int out_cs, const float* tgt, long P, int C, void* dout,
-                double* part, int nblocks, double* loss, void* stream);
+ * against tgt (FP32, C channels per pixel), channel c weighted by wch[c]
+ * (device array, or NULL for 1), into *loss (FP64, via nblocks partials in
+ * part); dout (bf16, stride out_cs, or NULL) = d loss / d out. */
+int lbfz_nn_mse(const float* out, int out_cs, const float* tgt, long P, int C, const float* wch,
+                void* dout, double* part, int nblocks, double* loss, void* stream);
 
 /* One Adam step (bias-corrected with the 1-based step number) on n FP32
  * weights w with gradients g and moments m, v; wb (bf16, or NULL) receives
@@ -114,17 +115,19 @@ int lbfz_nn_pack_fields(const float* planes, int nf, int nx, int ny, int x0, int
                         const float* shift, const float* scale, void* dst, int cs, int b,
                         void* stream);
 
-/* Training target of the same crop: ((after - before) - shift[f]) * scale[f],
- * FP32 [S * S][nf] for image b. */
+/* Training target of the same crop: ((after - resid[f] before) - shift[f]) *
+ * scale[f], FP32 [S * S][nf] for image b; resid[f] = 1 learns the change of
+ * field f, 0 its new value (device arrays of nf floats). */
 int lbfz_nn_pack_delta(const float* after, const float* before, int nf, int nx, int ny, int x0,
-                       int y0, int S, const float* shift, const float* scale, float* dst, int b,
-                       void* stream);
+                       int y0, int S, const float* shift, const float* scale, const float* resid,
+                       float* dst, int b, void* stream);
 
 /* Prediction of a whole grid from image b of the network output (FP32, stride
- * out_cs, the grid itself as the image): pred[f] = before[f] + out[f] /
- * scale[f] + shift[f], nf planes. */
+ * out_cs, the grid itself as the image): pred[f] = resid[f] before[f] +
+ * out[f] / scale[f] + shift[f], nf planes. */
 int lbfz_nn_apply_delta(const float* out, int out_cs, const float* before, int nf, int nx, int ny,
-                        const float* shift, const float* scale, float* pred, int b, void* stream);
+                        const float* shift, const float* scale, const float* resid, float* pred,
+                        int b, void* stream);
 
 #ifdef __cplusplus
 }

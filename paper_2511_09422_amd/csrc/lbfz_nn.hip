@@ -290,10 +290,12 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, long n, uint32_t v) {
 }
 
 // Mean squared error over the first C channels of out (FP32, channel stride
-// out_cs) against target (FP32, C channels); dout = d loss / d out (bf16,
-// channel stride out_cs, zero beyond C); per-block loss partials in FP64.
+// out_cs) against target (FP32, C channels), channel c weighted by wch[c] (or
+// 1); dout = d loss / d out (bf16, channel stride out_cs, zero beyond C);
+// per-block loss partials in FP64.
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out, int out_cs,
                                              const float* __restrict__ tgt, long P, int C,
+                                             const float* __restrict__ wch,
                                              bf16* __restrict__ dout, double* __restrict__ part) {
   __shared__ double red[256];
   const double inv = 1.0 / ((double)P * C);
@@ -304,9 +306,10 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out, int 
     const int c = (int)(i - p * out_cs);
     float g = 0.0f;
     if (c < C) {
+      const float wc = wch ? wch[c] : 1.0f;
       const float d = out[i] - tgt[p * C + c];
-      acc += (double)d * d;
-      g = (float)(2.0 * inv) * d;
+      acc += (double)wc * d * d;
+      g = (float)(2.0 * inv) * wc * d;
     }
     if (dout) dout[i] = (bf16)g;
   }
@@ -383,12 +386,12 @@ __global__ void k_pack_fields(const float* __restrict__ planes, int nf, int nx, 
   }
 }
 
-// Target of a crop: ((after - before) - shift[f]) * scale[f], FP32 [S*S][nf]
-// for image b.
+// Target of a crop: ((after - resid[f] before) - shift[f]) * scale[f], FP32
+// [S*S][nf] for image b (resid 1: the change is learned, 0: the new value).
 __global__ void k_pack_delta(const float* __restrict__ after, const float* __restrict__ before,
                              int nf, int nx, int ny, int x0, int y0, int S,
                              const float* __restrict__ shift, const float* __restrict__ scale,
-                             float* __restrict__ dst, int b) {
+                             const float* __restrict__ resid, float* __restrict__ dst, int b) {
   const long n = (long)S * S;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
        i += (long)gridDim.x * blockDim.x) {
@@ -396,23 +399,24 @@ __global__ void k_pack_delta(const float* __restrict__ after, const float* __res
     const int gx = (x0 + x) % nx, gy = min(max(y0 + y, 0), ny - 1);
     for (int f = 0; f < nf; ++f) {
       const long o = (long)f * nx * ny + (long)gy * nx + gx;
-      dst[((long)b * n + i) * nf + f] = ((after[o] - before[o]) - shift[f]) * scale[f];
+      dst[((long)b * n + i) * nf + f] = ((after[o] - resid[f] * before[o]) - shift[f]) * scale[f];
     }
   }
 }
 
 // Prediction of a whole grid from the network output of image b (FP32,
-// channel stride out_cs): pred[f] = before[f] + out[f] / scale[f] + shift[f].
+// channel stride out_cs): pred[f] = resid[f] before[f] + out[f] / scale[f] +
+// shift[f].
 __global__ void k_apply_delta(const float* __restrict__ out, int out_cs,
                               const float* __restrict__ before, int nf, int nx, int ny,
                               const float* __restrict__ shift, const float* __restrict__ scale,
-                              float* __restrict__ pred, int b) {
+                              const float* __restrict__ resid, float* __restrict__ pred, int b) {
   const long n = (long)nx * ny;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
        i += (long)gridDim.x * blockDim.x)
     for (int f = 0; f < nf; ++f)
-      pred[(long)f * n + i] =
-          before[(long)f * n + i] + out[((long)b * n + i) * out_cs + f] / scale[f] + shift[f];
+      pred[(long)f * n + i] = resid[f] * before[(long)f * n + i] +
+                              out[((long)b * n + i) * out_cs + f] / scale[f] + shift[f];
 }
 
 int grid_for(long n) { return (int)std::min<long>((n + 255) / 256, 16384); }
@@ -524,12 +528,12 @@ int lbfz_nn_fill_u32(void* p, long n, uint32_t v, void* stream) {
   HCHK();
 }
 
-int lbfz_nn_mse(const float* out, int out_cs, const float* tgt, long P, int C, void* dout,
-                double* part, int nblocks, double* loss, void* stream) {
+int lbfz_nn_mse(const float* out, int out_cs, const float* tgt, long P, int C, const float* wch,
+                void* dout, double* part, int nblocks, double* loss, void* stream) {
   if (!out || !tgt || !part || !loss || C <= 0 || C > out_cs || nblocks <= 0)
     return LBFZ_NN_EINVAL;
   hipLaunchKernelGGL(k_mse, dim3(nblocks), dim3(256), 0, (hipStream_t)stream, out, out_cs, tgt, P,
-                     C, static_cast<bf16*>(dout), part);
+                     C, wch, static_cast<bf16*>(dout), part);
   if (hipGetLastError() != hipSuccess) return LBFZ_NN_EHIP;
   hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, (hipStream_t)stream, part, nblocks, loss);
   HCHK();
@@ -571,21 +575,22 @@ int lbfz_nn_pack_fields(const float* planes, int nf, int nx, int ny, int x0, int
 }
 
 int lbfz_nn_pack_delta(const float* after, const float* before, int nf, int nx, int ny, int x0,
-                       int y0, int S, const float* shift, const float* scale, float* dst, int b,
-                       void* stream) {
-  if (!after || !before || !shift || !scale || !dst || S <= 0) return LBFZ_NN_EINVAL;
+                       int y0, int S, const float* shift, const float* scale, const float* resid,
+                       float* dst, int b, void* stream) {
+  if (!after || !before || !shift || !scale || !resid || !dst || S <= 0) return LBFZ_NN_EINVAL;
   hipLaunchKernelGGL(k_pack_delta, dim3(grid_for((long)S * S)), dim3(256), 0,
-                     (hipStream_t)stream, after, before, nf, nx, ny, x0, y0, S, shift, scale, dst,
-                     b);
+                     (hipStream_t)stream, after, before, nf, nx, ny, x0, y0, S, shift, scale,
+                     resid, dst, b);
   HCHK();
 }
 
 int lbfz_nn_apply_delta(const float* out, int out_cs, const float* before, int nf, int nx, int ny,
-                        const float* shift, const float* scale, float* pred, int b,
-                        void* stream) {
-  if (!out || !before || !shift || !scale || !pred) return LBFZ_NN_EINVAL;
+                        const float* shift, const float* scale, const float* resid, float* pred,
+                        int b, void* stream) {
+  if (!out || !before || !shift || !scale || !resid || !pred) return LBFZ_NN_EINVAL;
   hipLaunchKernelGGL(k_apply_delta, dim3(grid_for((long)nx * ny)), dim3(256), 0,
-                     (hipStream_t)stream, out, out_cs, before, nf, nx, ny, shift, scale, pred, b);
+                     (hipStream_t)stream, out, out_cs, before, nf, nx, ny, shift, scale, resid,
+                     pred, b);
   HCHK();
 }
 

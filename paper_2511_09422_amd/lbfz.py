@@ -381,5 +381,15 @@ class Batch:
         lbfz_batch_fields(self._b, i, bits, ptrs, False)
         return out
 
+    def fields_to_device(self, i: int, planes) -> None:
+        """The first len(planes) fields of grid i (order FIELDS) into the given
+        device tensors (asynchronous on the stream)."""
+        bits = 0
+        ptrs = [0] * len(FIELDS)
+        for k, t in enumerate(planes):
+            bits |= 1 << k
+            ptrs[k] = t.data_ptr()
+        lbfz_batch_fields(self._b, i, bits, ptrs, True)
+
     def totals(self, i: int) -> dict:
         return lbfz_batch_totals(self._b, i)

@@ -7,7 +7,7 @@ the device memory.
 Network (NHWC, bf16 activations, FP32 master weights; 3x3 convolutions with
 zero padding, ReLU after every convolution but the head):
 
-    X0 (16 ch: 6 fields + zero padding)
+    X0 (16 ch: phi, f_l, T, C, u_x, u_y, u_z = 0, p + zero padding)
     L1a 16->32, L1b 32->32 = S1 ........................ CAT1[:, 32:64]
     maxpool -> L2a 32->64, L2b 64->64 = S2 .............. CAT2[:, 64:128]
     maxpool -> L3a 64->128, L3b 128->128
@@ -31,7 +31,8 @@ import numpy as np
 
 from . import lbfz
 
-NF = 6           # fields: phi, f_l, T, C, u_x, u_y
+NF = 6           # predicted fields: phi, f_l, T, C, u_x, u_y
+NIN = 8          # input planes: the six, u_z (zero in 2D) and the pressure p
 CIN0 = 16        # padded input channels
 HEAD = 8         # padded head channels
 FIELD_NAMES = ("phi", "fl", "T", "C", "ux", "uy")
@@ -68,13 +69,14 @@ def nnlib():
             "lbfz_nn_upsample2": [vp, i32, i32, i32, i32, vp, vp],
             "lbfz_nn_upsample2_bwd": [vp, i32, i32, i32, i32, vp, vp],
             "lbfz_nn_fill_u32": [vp, lg, u32, vp],
-            "lbfz_nn_mse": [vp, i32, vp, lg, i32, vp, vp, i32, vp, vp],
+            "lbfz_nn_mse": [vp, i32, vp, lg, i32, vp, vp, vp, i32, vp, vp],
             "lbfz_nn_adam": [vp, vp, vp, vp, vp, lg, f32, f32, f32, f32, i32, vp],
             "lbfz_nn_to_bf16": [vp, vp, lg, vp],
             "lbfz_nn_transpose_w": [vp, i32, i32, i32, vp, vp],
             "lbfz_nn_pack_fields": [vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, i32, i32, vp],
-            "lbfz_nn_pack_delta": [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, i32, vp],
-            "lbfz_nn_apply_delta": [vp, i32, vp, i32, i32, i32, vp, vp, vp, i32, vp],
+            "lbfz_nn_pack_delta": [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, i32,
+                                   vp],
+            "lbfz_nn_apply_delta": [vp, i32, vp, i32, i32, i32, vp, vp, vp, vp, i32, vp],
         }
         for nm, args in sig.items():
             fn = getattr(L, nm)
@@ -136,10 +138,10 @@ def init_weights(seed: int = 0) -> dict:
     rng = np.random.default_rng(seed)
     out = {}
     for L in LAYERS:
-        fan_in = L.taps * (NF if L.name == "L1a" else L.cin)
+        fan_in = L.taps * (NIN if L.name == "L1a" else L.cin)
         w = rng.standard_normal((L.cout, L.taps, L.cin)) * np.sqrt(2.0 / fan_in)
         if L.name == "L1a":
-            w[:, :, NF:] = 0.0
+            w[:, :, NIN:] = 0.0
         if L.name == "head":
             w *= 0.1
             w[NF:] = 0.0
@@ -353,13 +355,14 @@ class UNet:
         self._layer_bwd("L1a", t["X0"], CIN0, 0, t["dA1"], 32, 0, t["A1"], 32, 0, None, 0, 0,
                         need_dx=False)
 
-    def loss(self, with_grad: bool = True) -> None:
-        """MSE of OUT's first NF channels against target (FP32 [P][NF]); the
-        value lands in loss_t (device), dOUT is set when with_grad."""
+    def loss(self, with_grad: bool = True, channel_weights=None) -> None:
+        """MSE of OUT's first NF channels against target (FP32 [P][NF]), each
+        channel weighted (device FP32 [NF], or None for 1); the value lands in
+        loss_t (device), dOUT is set when with_grad."""
         P = self.B * self.S * self.S
         _ck(nnlib().lbfz_nn_mse(_p(self.t["OUT"]), HEAD, _p(self.target), P, NF,
-                                _p(self.t["dOUT"]) if with_grad else None, _p(self.lpart),
-                                1024, _p(self.loss_t), self.st), "mse")
+                                _p(channel_weights), _p(self.t["dOUT"]) if with_grad else None,
+                                _p(self.lpart), 1024, _p(self.loss_t), self.st), "mse")
 
     def adam(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
         self.adam_step += 1
@@ -389,3 +392,140 @@ class UNet:
             out[Ly.name] = (host[o:o + nw].reshape(Ly.cout, Ly.taps, Ly.cin).copy(),
                             host[ob:ob + nb].copy())
         return out
+
+
+# ---------------------------------------------------------------------------
+# data, training and screening
+
+STRIDE = 64      # LB steps spanned by one prediction
+MASS_TOL = 1e-3  # screening: largest accepted phase-field mass residual
+
+
+def generate_snapshots(case_ids, side: int, nsnap: int, device: int = 0, storage: str = "f32"):
+    """Run the LB step (batched, on the GPU) for the sweep grids case_ids with
+    their side replaced by `side`, and keep the NIN input planes every STRIDE
+    steps: a device tensor [ncases][nsnap][NIN][side][side] FP32 (snapshot 0 =
+    the initial state).  Returns (snapshots, params of each grid)."""
+    import torch
+    from .workloads import sweep_case
+    cases = [sweep_case(k, side=side) for k in case_ids]
+    b = lbfz.Batch(cases, device=device, storage=storage)
+    snaps = torch.zeros((len(cases), nsnap, NIN, side, side), dtype=torch.float32,
+                        device=b.device)
+    for s in range(nsnap):
+        if s:
+            b.step(STRIDE)
+        for i in range(len(cases)):
+            b.fields_to_device(i, [snaps[i, s, f] for f in range(NIN)])
+    torch.cuda.synchronize()
+    bad = sum(b.totals(i)["nonfinite"] for i in range(len(cases)))
+    b.close()
+    if bad:
+        raise RuntimeError("non-finite LB state while generating snapshots")
+    return snaps, [c[0] for c in cases]
+
+
+# 1: the network learns the change of the field over STRIDE steps (phi, f_l,
+# T, C evolve slowly); 0: its new value (the velocity relaxes within a few
+# steps to the flow the slow fields drive, so its change is as large as itself)
+RESIDUAL = (1.0, 1.0, 1.0, 1.0, 0.0, 0.0)
+# loss weight per field: the velocity 64 steps ahead is largely unpredictable
+# from one snapshot (grid-scale currents decorrelate within the stride), so
+# it is weighted down to keep its irreducible error from swamping the rest
+LOSS_WEIGHT = (1.0, 1.0, 1.0, 1.0, 0.1, 0.1)
+
+
+class Normaliser:
+    """Per-field shift / scale of the network input (the fields) and of its
+    target (the change over STRIDE steps, or the new value -- RESIDUAL), from a
+    snapshot tensor [grids][snapshots][NF][S][S]."""
+
+    def __init__(self, snaps):
+        import torch
+        x = snaps[:, :-1].transpose(0, 2).reshape(NIN, -1)
+        r = torch.tensor(RESIDUAL, dtype=snaps.dtype, device=snaps.device)
+        d = (snaps[:, 1:, :NF] - r[None, None, :, None, None] * snaps[:, :-1, :NF])
+        d = d.transpose(0, 2).reshape(NF, -1)
+        self.in_shift = x.mean(dim=1)
+        self.in_scale = 1.0 / x.std(dim=1).clamp_min(1e-12)
+        self.d_shift = d.mean(dim=1)
+        self.d_scale = 1.0 / d.std(dim=1).clamp_min(1e-12)
+        self.resid = r
+        for k in ("in_shift", "in_scale", "d_shift", "d_scale", "resid"):
+            setattr(self, k, getattr(self, k).to(torch.float32).contiguous())
+
+
+def load_pairs(net: UNet, snaps, norm: Normaliser, pairs) -> None:
+    """Images b = 0..len(pairs)-1 of the network input and target from the
+    (grid, snapshot) pairs: input = snapshot s, target = snapshot s+1 minus s."""
+    L = nnlib()
+    S = net.S
+    for b, (i, s) in enumerate(pairs):
+        before, after = snaps[i, s], snaps[i, s + 1]
+        _ck(L.lbfz_nn_pack_fields(_p(before), NIN, S, S, 0, 0, S, _p(norm.in_shift),
+                                  _p(norm.in_scale), _p(net.t["X0"]), CIN0, b, net.st),
+            "pack_fields")
+        _ck(L.lbfz_nn_pack_delta(_p(after), _p(before), NF, S, S, 0, 0, S, _p(norm.d_shift),
+                                 _p(norm.d_scale), _p(norm.resid), _p(net.target), b, net.st),
+            "pack_delta")
+
+
+def train(net: UNet, snaps, norm: Normaliser, iters: int, lr: float = 1e-3, seed: int = 0,
+          log_every: int = 0):
+    """Adam on the MSE of the normalised change, random (grid, snapshot)
+    pairs, cosine-decayed learning rate.  Returns the loss history."""
+    import math
+    import torch
+    rng = np.random.default_rng(seed)
+    ng, ns = snaps.shape[0], snaps.shape[1] - 1
+    wch = torch.tensor(LOSS_WEIGHT, dtype=torch.float32, device=net.dev)
+    hist = []
+    for it in range(iters):
+        pairs = [(int(rng.integers(ng)), int(rng.integers(ns))) for _ in range(net.B)]
+        load_pairs(net, snaps, norm, pairs)
+        net.forward()
+        net.loss(channel_weights=wch)
+        net.backward()
+        net.adam(lr * 0.5 * (1.0 + math.cos(math.pi * it / max(iters, 1))))
+        if log_every and (it % log_every == 0 or it == iters - 1):
+            hist.append((it, float(net.loss_t.cpu().numpy()[0])))
+    return hist
+
+
+def predict(net: UNet, snaps, norm: Normaliser, pairs, out):
+    """Predicted fields after STRIDE steps for the (grid, snapshot) pairs into
+    out [len(pairs)][NF][S][S] (device, FP32)."""
+    L = nnlib()
+    S = net.S
+    for b, (i, s) in enumerate(pairs):
+        _ck(L.lbfz_nn_pack_fields(_p(snaps[i, s]), NIN, S, S, 0, 0, S, _p(norm.in_shift),
+                                  _p(norm.in_scale), _p(net.t["X0"]), CIN0, b, net.st),
+            "pack_fields")
+    net.forward()
+    for b, (i, s) in enumerate(pairs):
+        _ck(L.lbfz_nn_apply_delta(_p(net.t["OUT"]), HEAD, _p(snaps[i, s]), NF, S, S,
+                                  _p(norm.d_shift), _p(norm.d_scale), _p(norm.resid), _p(out[b]),
+                                  b, net.st), "apply_delta")
+
+
+def mass_residual(before, after, ratio: float) -> float:
+    """|sum dphi - ratio * sum df_s| / sum (1 + phi_in) / 2, with f_s = 1 - f_l
+    and ratio = 1 - rho_s / rho_l (fields [NF][S][S], any device)."""
+    dphi = float((after[0] - before[0]).double().sum())
+    dfs = -float((after[1] - before[1]).double().sum())
+    denom = float(((1.0 + before[0].double()) * 0.5).sum())
+    return abs(dphi - ratio * dfs) / max(denom, 1e-30)
+
+
+def solute_drift(before, after) -> float:
+    """|sum C_after - sum C_before| / sum C_before: the LB step conserves the
+    solute exactly (to FP32 rounding), so a prediction's drift measures its
+    error in the one field with an exact budget."""
+    c0 = float(before[3].double().sum())
+    return abs(float(after[3].double().sum()) - c0) / max(abs(c0), 1e-30)
+
+
+def rel_l2(a, b) -> list:
+    """Per-field ||a - b|| / ||b|| over [NF][...] tensors."""
+    return [float((a[f] - b[f]).double().norm() / (b[f].double().norm() + 1e-30))
+            for f in range(NF)]

@@ -107,18 +107,28 @@ def droplet_3d(n: int = 256, R: float = 64.0, imp_R: float = 12.0, seed: int = 1
 SWEEP_SIDES = (64, 128, 256, 512)
 
 
-def sweep_case(k: int, **over):
-    """Case k of the parameter sweep: default_rng(1000 + k) draws, in order,
-    the side in {64, 128, 256, 512}, the Marangoni coefficient in [0, 5e-4]
-    (sigma_T = -coefficient), the Stefan number in [0.5, 2], the solid/liquid
-    density ratio in [0.85, 1.0] and the initial solute C0 in [0, 0.1]; the
-    droplet radius is side/4.  Returns (params, phi, T, C)."""
+def sweep_params(k: int):
+    """The draws of sweep case k: (side, Marangoni coefficient, Stefan number,
+    rho_s / rho_l, C0), from default_rng(1000 + k) in that order."""
     rng = np.random.default_rng(1000 + k)
     side = int(rng.choice(SWEEP_SIDES))
     coef = float(rng.uniform(0.0, 5e-4))
     ste = float(rng.uniform(0.5, 2.0))
     rr = float(rng.uniform(0.85, 1.0))
     c0 = float(rng.uniform(0.0, 0.1))
+    return side, coef, ste, rr, c0
+
+
+def sweep_case(k: int, side: int = 0, **over):
+    """Case k of the parameter sweep: default_rng(1000 + k) draws, in order,
+    the side in {64, 128, 256, 512}, the Marangoni coefficient in [0, 5e-4]
+    (sigma_T = -coefficient), the Stefan number in [0.5, 2], the solid/liquid
+    density ratio in [0.85, 1.0] and the initial solute C0 in [0, 0.1]; the
+    droplet radius is side/4.  side != 0 keeps the other draws and replaces
+    the side (the surrogate's training and held-out grids).  Returns
+    (params, phi, T, C)."""
+    s, coef, ste, rr, c0 = sweep_params(k)
+    side = side or s
     p, phi, T, C = droplet_2d(side, side, R=side / 4.0, seed=1000 + k, C0=c0,
                               sigma_T=-coef, latent=1.0 / ste, rho_s=rr, **over)
     p["case"] = k
