@@ -52,6 +52,10 @@ typedef struct lbfz_conv_args {
   int32_t relu;            /* forward: apply max(., 0) after the bias                      */
   int32_t sign;            /* +1 forward (x at p + o(t)), -1 data gradient (dz at p - o(t)) */
   int32_t B, H, W, taps;
+  int32_t up;              /* forward / weight gradient: 1 = `in` is a B x (H/2) x (W/2)
+                              image read through nearest 2x upsampling (pixel (y, x) takes
+                              (y/2, x/2); H, W even), 0 = `in` is B x H x W.  Must be 0 for
+                              the data gradient                                             */
 } lbfz_conv_args;
 
 /* Forward: out[p][n] = act(sum_{t,c} in[p + o(t)][c] W[n][t][c] + bias[n]);
@@ -74,7 +78,8 @@ int lbfz_nn_relu_bwd(const void* dy, int dy_cs, int dy_co, const void* y, int y_
                      void* dz, int dz_cs, long P, int C, void* stream);
 
 /* 2x2 max pooling (stride 2) and its gradient (to the first maximum of each
- * window; accumulate != 0 adds into dx instead of overwriting). */
+ * window; accumulate != 0 adds into dx instead of overwriting).  C, channel
+ * strides and offsets multiples of 8; H, W even. */
 int lbfz_nn_maxpool2(const void* x, int x_cs, int x_co, void* y, int y_cs, int B, int H, int W,
                      int C, void* stream);
 int lbfz_nn_maxpool2_bwd(const void* x, int x_cs, int x_co, const void* dy, int dy_cs, void* dx,
@@ -82,7 +87,7 @@ int lbfz_nn_maxpool2_bwd(const void* x, int x_cs, int x_co, const void* dy, int 
                          void* stream);
 
 /* Nearest 2x upsampling of a dense B x H x W x C tensor (to 2H x 2W) and its
- * gradient (the sum over each 2x2 block). */
+ * gradient (the sum over each 2x2 block); C a multiple of 8. */
 int lbfz_nn_upsample2(const void* x, int B, int H, int W, int C, void* y, void* stream);
 int lbfz_nn_upsample2_bwd(const void* dy, int B, int H, int W, int C, void* dx, void* stream);
 

@@ -5,9 +5,11 @@
 // Tensors are NHWC bf16 (channels innermost, a multiple of 8), weights
 // [out channel][tap][in channel] bf16 with FP32 master copies, accumulation in
 // FP32.  Convolutions are implicit GEMMs on the BF16 matrix cores
-// (v_mfma_f32_32x32x16_bf16): a 256-thread block computes a 64 x 64 output
-// tile as 2 x 2 waves of 32 x 32, staging 64 x 32 slices of both operands in
-// LDS per K step.
+// (v_mfma_f32_32x32x16_bf16).  Forward and data gradient: a 256-thread block
+// computes a 128 x 128, 256 x 64 or 256 x 32 output tile (by the layer's
+// width), 64 x 64 or 64 x 32 per wave, with the next K slice prefetched into
+// registers during the MFMAs of the current one.  Weight gradient: 64 x 64
+// tiles, 2 x 2 waves of 32 x 32, 32-deep K slices.
 //   forward        out[p][n]  = sum_{t, c} in[p + o(t)][c] W[n][t][c]   (M = pixels)
 //   data gradient  din[p][c]  = sum_{t, n} dz[p - o(t)][n] W[n][t][c]   (same kernel,
 //                  weights transposed to Wt[c][t][n], offsets negated)
@@ -40,15 +42,17 @@ __device__ __forceinline__ void tap_offset(int taps, int t, int sign, int& dy, i
   }
 }
 
-// 16 bytes (8 bf16) of channel data at pixel (b, y, x) shifted by (dy, dx);
-// zero outside the image.
+// 16 bytes (8 bf16) of channel data at pixel (b, y, x) shifted by (dy, dx) of
+// an H x W image; zero outside the image.  up: the tensor holds the
+// (H/2) x (W/2) image that nearest 2x upsampling maps onto H x W.
 __device__ __forceinline__ uint4 load_px8(const bf16* __restrict__ t, int cs, int coff, int c,
                                           int b, int y, int x, int dy, int dx, int H, int W,
-                                          bool ok) {
+                                          bool ok, bool up) {
   const int yy = y + dy, xx = x + dx;
   if (!ok || yy < 0 || yy >= H || xx < 0 || xx >= W) return make_uint4(0, 0, 0, 0);
-  const size_t o = ((size_t)(b * H + yy) * W + xx) * cs + coff + c;
-  return *reinterpret_cast<const uint4*>(t + o);
+  const size_t px = up ? ((size_t)(b * (H >> 1) + (yy >> 1)) * (W >> 1) + (xx >> 1))
+                       : ((size_t)(b * H + yy) * W + xx);
+  return *reinterpret_cast<const uint4*>(t + px * cs + coff + c);
 }
 
 __device__ __forceinline__ f32x16 mfma_tile(const bf16 (*As)[LDK], const bf16 (*Bs)[LDK], int wm,
@@ -70,52 +74,164 @@ __device__ __forceinline__ int acc_row(int r, int lane) {
 }
 
 // Forward / data-gradient convolution (M = pixels, N = a.N, K = taps * a.Cin).
+// A block of 4 waves computes a BM x BN output tile; wave w owns a
+// (32 FM) x (32 FN) sub-tile (FM x FN accumulators of 32 x 32) at wave
+// position (w % WGM, w / WGM).  K advances in slices of KS = 32: each thread
+// loads its 16-byte chunks of the next slice (chunk q = tid % 4 of rows
+// tid / 4 + 64 j) into registers while the waves run the 2 x FM x FN MFMAs of
+// the current slice from LDS, so the global latency hides behind the matrix
+// work (a 64-deep slice doubles the LDS per block and measured slower: fewer
+// blocks per CU).  Consecutive M tiles go to one XCD (blocks are dealt to the
+// 8 XCDs round-robin), so the rows a 3 x 3 stencil re-reads from the
+// neighbouring tiles hit the same L2.  The bf16 output tile is staged in LDS
+// and written as whole 16-byte channel groups.
+constexpr int KS = 32, LDS_K = KS + 8;      // LDS rows padded by 16 B
+constexpr int CPR = KS / 8, RPP = 256 / CPR;   // 16-byte chunks per row, rows per pass
+
+template <int FM, int FN, int WGM, int WGN>
 __global__ __launch_bounds__(256) void k_conv(lbfz_conv_args a) {
-  __shared__ __align__(16) bf16 As[BM][LDK];
-  __shared__ __align__(16) bf16 Bs[BN][LDK];
+  static_assert(WGM * WGN == 4, "4 waves");
+  constexpr int BM_ = 32 * FM * WGM, BN_ = 32 * FN * WGN;
+  // 16-byte chunks per thread and slice (B: the last pass may be partial)
+  constexpr int AR = BM_ / RPP, BR = (BN_ + RPP - 1) / RPP;
+  constexpr int A_EL = BM_ * LDS_K, B_EL = BN_ * LDS_K;
+  constexpr int O_EL = BM_ * (BN_ + 8);  // the bf16 output tile, staged for the stores
+  constexpr int SM_EL = (A_EL + B_EL) > O_EL ? (A_EL + B_EL) : O_EL;
+  __shared__ __align__(16) bf16 smem[SM_EL];
+  bf16 (*As)[LDS_K] = reinterpret_cast<bf16 (*)[LDS_K]>(smem);
+  bf16 (*Bs)[LDS_K] = reinterpret_cast<bf16 (*)[LDS_K]>(smem + A_EL);
   const int M = a.B * a.H * a.W, K = a.taps * a.Cin;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int nbm = gridDim.x;
+  int bx = blockIdx.x;
+  if ((nbm & 7) == 0) bx = (bx & 7) * (nbm >> 3) + (bx >> 3);
+  const int m0 = bx * BM_, n0 = blockIdx.y * BN_;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int wm = (wave % WGM) * 32 * FM, wn = (wave / WGM) * 32 * FN;
   const bf16* __restrict__ in = static_cast<const bf16*>(a.in);
   const bf16* __restrict__ wt = static_cast<const bf16*>(a.w);
-  // this thread's loader slot: tile row lr, 8 k values from lk
-  const int lr = tid >> 2, lk = (tid & 3) * 8;
-  const int p = m0 + lr;
-  const bool pok = p < M;
-  const int px = p % a.W, py = (p / a.W) % a.H, pb = p / (a.W * a.H);
-  const int n = n0 + lr;
-  const bool nok = n < a.N;
-  f32x16 acc = {};
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    const int k = k0 + lk;
-    uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
-    if (k < K) {
-      const int t = k / a.Cin, c = k - t * a.Cin;
-      int dy, dx;
-      tap_offset(a.taps, t, a.sign, dy, dx);
-      va = load_px8(in, a.in_cs, a.in_co, c, pb, py, px, dy, dx, a.H, a.W, pok);
-      if (nok) vb = *reinterpret_cast<const uint4*>(wt + (size_t)n * K + k);
+  const int q = tid % CPR, r0 = tid / CPR;
+  int pp[AR], py[AR], px[AR];
+#pragma unroll
+  for (int j = 0; j < AR; ++j) {
+    const int p = m0 + r0 + RPP * j;
+    pp[j] = p < M ? p : -1;
+    const int rem = p % (a.H * a.W);
+    py[j] = rem / a.W;
+    px[j] = rem - py[j] * a.W;
+  }
+  uint4 ra[AR], rb[BR];
+  auto gload = [&](int k0) {
+    const int k = k0 + 8 * q;
+    const bool kok = k < K;
+    int t = 0, c = 0;
+    if (kok) {
+      t = k / a.Cin;
+      c = k - t * a.Cin;
     }
+    int dy, dx;
+    tap_offset(a.taps, t, a.sign, dy, dx);
+#pragma unroll
+    for (int j = 0; j < AR; ++j) {
+      const int yy = py[j] + dy, xx = px[j] + dx;
+      ra[j] = make_uint4(0, 0, 0, 0);
+      if (kok && pp[j] >= 0 && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+        // source pixel: the shifted one, or under upsampling its parent in
+        // the half-resolution image (image base pp - py W - px, a multiple of 4)
+        const int src = a.up ? ((pp[j] - py[j] * a.W - px[j]) >> 2) + (yy >> 1) * (a.W >> 1) +
+                                   (xx >> 1)
+                             : pp[j] + dy * a.W + dx;
+        ra[j] = *reinterpret_cast<const uint4*>(in + (size_t)src * a.in_cs + a.in_co + c);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < BR; ++j) {
+      const int rr = r0 + RPP * j, n = n0 + rr;
+      rb[j] = make_uint4(0, 0, 0, 0);
+      if (kok && rr < BN_ && n < a.N) rb[j] = *reinterpret_cast<const uint4*>(wt + (size_t)n * K + k);
+    }
+  };
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += KS) {
+    __syncthreads();  // the previous slice's fragments have been read
+#pragma unroll
+    for (int j = 0; j < AR; ++j) *reinterpret_cast<uint4*>(&As[r0 + RPP * j][8 * q]) = ra[j];
+#pragma unroll
+    for (int j = 0; j < BR; ++j)
+      if (r0 + RPP * j < BN_) *reinterpret_cast<uint4*>(&Bs[r0 + RPP * j][8 * q]) = rb[j];
     __syncthreads();
-    *reinterpret_cast<uint4*>(&As[lr][lk]) = va;
-    *reinterpret_cast<uint4*>(&Bs[lr][lk]) = vb;
-    __syncthreads();
-    acc = mfma_tile(As, Bs, wm, wn, lane, acc);
+    if (k0 + KS < K) gload(k0 + KS);
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 16) {
+      bf16x8 fa[FM], fb[FN];
+      const int kc = kk + 8 * (lane >> 5);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        fa[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 32 * i + (lane & 31)][kc]);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        fb[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 32 * j + (lane & 31)][kc]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
   }
   const float* bias = a.bias;
+  if (!a.out_f32 && a.N % 8 == 0 && a.out_cs % 8 == 0 && a.out_co % 8 == 0) {
+    // stage the bf16 tile in LDS, then write whole 16-byte channel groups
+    constexpr int OS = BN_ + 8;
+    bf16* Os = smem;
+    __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int pm = m0 + wm + acc_row(r, lane), cn = n0 + wn + (lane & 31);
-    if (pm < M && cn < a.N) {
-      float v = acc[r];
-      if (bias) v += bias[cn];
-      if (a.relu) v = fmaxf(v, 0.0f);
-      const size_t o = (size_t)pm * a.out_cs + a.out_co + cn;
-      if (a.out_f32)
-        static_cast<float*>(a.out)[o] = v;
-      else
-        static_cast<bf16*>(a.out)[o] = (bf16)v;
+    for (int j = 0; j < FN; ++j) {
+      const int col = wn + 32 * j + (lane & 31);
+      const float bv = (bias && n0 + col < a.N) ? bias[n0 + col] : 0.0f;
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          float v = acc[i][j][r] + bv;
+          if (a.relu) v = fmaxf(v, 0.0f);
+          Os[(wm + 32 * i + acc_row(r, lane)) * OS + col] = (bf16)v;
+        }
+    }
+    __syncthreads();
+    constexpr int GPR = BN_ / 8;  // 16-byte groups per tile row
+    for (int g = tid; g < BM_ * GPR; g += 256) {
+      const int row = g / GPR, cg = g - row * GPR;
+      const int pm = m0 + row, cn = n0 + 8 * cg;
+      if (pm < M && cn < a.N)
+        *reinterpret_cast<uint4*>(static_cast<bf16*>(a.out) + (size_t)pm * a.out_cs + a.out_co +
+                                  cn) = *reinterpret_cast<const uint4*>(&Os[row * OS + 8 * cg]);
+    }
+    return;
+  }
+  // FP32 output or unaligned channels: direct stores
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int cn = n0 + wn + 32 * j + (lane & 31);
+    if (cn >= a.N) continue;
+    const float bv = bias ? bias[cn] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int pm = m0 + wm + 32 * i + acc_row(r, lane);
+        if (pm >= M) continue;
+        float v = acc[i][j][r] + bv;
+        if (a.relu) v = fmaxf(v, 0.0f);
+        const size_t o = (size_t)pm * a.out_cs + a.out_co + cn;
+        if (a.out_f32)
+          static_cast<float*>(a.out)[o] = v;
+        else
+          static_cast<bf16*>(a.out)[o] = (bf16)v;
+      }
     }
   }
 }
@@ -150,7 +266,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(lbfz_conv_args a, float* __r
     uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
     if (pok && am < a.N)
       va = *reinterpret_cast<const uint4*>(dz + (size_t)p * a.dz_cs + am);
-    if (bn < NW) vb = load_px8(in, a.in_cs, a.in_co, bc, pb, py, px, bdy, bdx, a.H, a.W, pok);
+    if (bn < NW)
+      vb = load_px8(in, a.in_cs, a.in_co, bc, pb, py, px, bdy, bdx, a.H, a.W, pok, a.up != 0);
     __syncthreads();
     const bf16* ea = reinterpret_cast<const bf16*>(&va);
     const bf16* eb = reinterpret_cast<const bf16*>(&vb);
@@ -206,80 +323,128 @@ __global__ void k_relu_bwd(const bf16* __restrict__ dy, int dy_cs, int dy_co,
 }
 
 // 2x2 max pooling (stride 2) and its gradient (to the first maximum).
+// Pooling and upsampling work on 8-channel (16-byte) groups: thread i takes
+// group i % (C / 8) of output pixel i / (C / 8).  Channel counts, strides and
+// offsets are multiples of 8 (checked by the callers).
+union V8 {
+  uint4 u;
+  bf16 h[8];
+};
+
+__device__ __forceinline__ V8 ld8(const bf16* p) {
+  V8 v;
+  v.u = *reinterpret_cast<const uint4*>(p);
+  return v;
+}
+
+__device__ __forceinline__ void st8(bf16* p, const V8& v) {
+  *reinterpret_cast<uint4*>(p) = v.u;
+}
+
+// 2x2 max pooling, stride 2.
 __global__ void k_maxpool2(const bf16* __restrict__ x, int x_cs, int x_co, bf16* __restrict__ y,
                            int y_cs, int B, int H, int W, int C) {
-  const int Ho = H / 2, Wo = W / 2;
-  const long n = (long)B * Ho * Wo * C;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-       i += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(i % C);
-    const long q = i / C;
-    const int xo = (int)(q % Wo), yo = (int)((q / Wo) % Ho), b = (int)(q / ((long)Wo * Ho));
-    float m = -3.0e38f;
+  const int Ho = H / 2, Wo = W / 2, G = C / 8;
+  const int n = B * Ho * Wo * G;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int g = i % G, q = i / G;
+    const int xo = q % Wo, t = q / Wo, yo = t % Ho, b = t / Ho;
+    const size_t p0 = (size_t)(b * H + 2 * yo) * W + 2 * xo;
+    const size_t px[4] = {p0, p0 + 1, p0 + W, p0 + W + 1};
+    float m[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) m[e] = -3.0e38f;
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const long px = ((long)(b * H + 2 * yo + (j >> 1)) * W + 2 * xo + (j & 1));
-      m = fmaxf(m, (float)x[px * x_cs + x_co + c]);
+      const V8 v = ld8(x + px[j] * x_cs + x_co + 8 * g);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) m[e] = fmaxf(m[e], (float)v.h[e]);
     }
-    y[q * y_cs + c] = (bf16)m;
+    V8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o.h[e] = (bf16)m[e];
+    st8(y + (size_t)q * y_cs + 8 * g, o);
   }
 }
 
+// Its gradient: each window's gradient goes to its first maximum.
 __global__ void k_maxpool2_bwd(const bf16* __restrict__ x, int x_cs, int x_co,
                                const bf16* __restrict__ dy, int dy_cs, bf16* __restrict__ dx,
                                int dx_cs, int dx_co, int accumulate, int B, int H, int W, int C) {
-  const int Ho = H / 2, Wo = W / 2;
-  const long n = (long)B * Ho * Wo * C;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-       i += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(i % C);
-    const long q = i / C;
-    const int xo = (int)(q % Wo), yo = (int)((q / Wo) % Ho), b = (int)(q / ((long)Wo * Ho));
-    long px[4];
-    int arg = 0;
-    float m = -3.0e38f;
+  const int Ho = H / 2, Wo = W / 2, G = C / 8;
+  const int n = B * Ho * Wo * G;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int g = i % G, q = i / G;
+    const int xo = q % Wo, t = q / Wo, yo = t % Ho, b = t / Ho;
+    const size_t p0 = (size_t)(b * H + 2 * yo) * W + 2 * xo;
+    const size_t px[4] = {p0, p0 + 1, p0 + W, p0 + W + 1};
+    float m[8];
+    int arg[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      m[e] = -3.0e38f;
+      arg[e] = 0;
+    }
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-      px[j] = ((long)(b * H + 2 * yo + (j >> 1)) * W + 2 * xo + (j & 1));
-      const float v = (float)x[px[j] * x_cs + x_co + c];
-      if (v > m) {
-        m = v;
-        arg = j;
+      const V8 v = ld8(x + px[j] * x_cs + x_co + 8 * g);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float f = (float)v.h[e];
+        if (f > m[e]) {
+          m[e] = f;
+          arg[e] = j;
+        }
       }
     }
-    const float g = (float)dy[q * dy_cs + c];
+    const V8 gv = ld8(dy + (size_t)q * dy_cs + 8 * g);
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-      bf16* d = dx + px[j] * dx_cs + dx_co + c;
-      const float add = j == arg ? g : 0.0f;
-      *d = (bf16)(accumulate ? (float)*d + add : add);
+      bf16* d = dx + px[j] * dx_cs + dx_co + 8 * g;
+      V8 o = accumulate ? ld8(d) : V8{};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float add = arg[e] == j ? (float)gv.h[e] : 0.0f;
+        o.h[e] = (bf16)(accumulate ? (float)o.h[e] + add : add);
+      }
+      st8(d, o);
     }
   }
 }
 
-// Nearest 2x upsampling and its gradient (sum of the four children).
+// Nearest 2x upsampling of a dense H x W x C image and its gradient (the sum
+// of the four children).
 __global__ void k_upsample2(const bf16* __restrict__ x, int B, int H, int W, int C,
                             bf16* __restrict__ y) {
-  const int Ho = 2 * H, Wo = 2 * W;
-  const long n = (long)B * Ho * Wo * C;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-       i += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(i % C);
-    const long q = i / C;
-    const int xo = (int)(q % Wo), yo = (int)((q / Wo) % Ho), b = (int)(q / ((long)Wo * Ho));
-    y[i] = x[((long)(b * H + yo / 2) * W + xo / 2) * C + c];
+  const int Ho = 2 * H, Wo = 2 * W, G = C / 8;
+  const int n = B * Ho * Wo * G;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int g = i % G, q = i / G;
+    const int xo = q % Wo, t = q / Wo, yo = t % Ho, b = t / Ho;
+    st8(y + (size_t)q * C + 8 * g, ld8(x + ((size_t)(b * H + yo / 2) * W + xo / 2) * C + 8 * g));
   }
 }
 
 __global__ void k_upsample2_bwd(const bf16* __restrict__ dy, int B, int H, int W, int C,
                                 bf16* __restrict__ dx) {
-  const long n = (long)B * H * W * C;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-       i += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(i % C);
-    const long q = i / C;
-    const int x = (int)(q % W), y = (int)((q / W) % H), b = (int)(q / ((long)W * H));
-    float v = 0.0f;
-    for (int j = 0; j < 4; ++j)
-      v += (float)dy[((long)(b * 2 * H + 2 * y + (j >> 1)) * (2 * W) + 2 * x + (j & 1)) * C + c];
-    dx[i] = (bf16)v;
+  const int G = C / 8;
+  const int n = B * H * W * G;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int g = i % G, q = i / G;
+    const int x = q % W, t = q / W, y = t % H, b = t / H;
+    const size_t p0 = (size_t)(b * 2 * H + 2 * y) * (2 * W) + 2 * x;
+    const size_t px[4] = {p0, p0 + 1, p0 + 2 * W, p0 + 2 * W + 1};
+    float v[8] = {};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const V8 a = ld8(dy + px[j] * C + 8 * g);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] += (float)a.h[e];
+    }
+    V8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o.h[e] = (bf16)v[e];
+    st8(dx + (size_t)q * C + 8 * g, o);
   }
 }
 
@@ -421,6 +586,11 @@ __global__ void k_apply_delta(const float* __restrict__ out, int out_cs,
 
 int grid_for(long n) { return (int)std::min<long>((n + 255) / 256, 16384); }
 
+// 8-channel groups: C, the channel stride and the offset multiples of 8
+bool groups_ok(int C, int cs, int co) {
+  return C > 0 && C % 8 == 0 && cs % 8 == 0 && co % 8 == 0 && co + C <= cs;
+}
+
 }  // namespace
 
 extern "C" {
@@ -432,14 +602,28 @@ extern "C" {
 
 static bool conv_ok(const lbfz_conv_args* a) {
   return a && a->in && a->w && a->B > 0 && a->H > 0 && a->W > 0 && (a->taps == 1 || a->taps == 9) &&
-         a->Cin > 0 && a->Cin % 8 == 0 && a->N > 0 && a->in_cs % 8 == 0 && a->in_co % 8 == 0;
+         a->Cin > 0 && a->Cin % 8 == 0 && a->N > 0 && a->in_cs % 8 == 0 && a->in_co % 8 == 0 &&
+         (a->up == 0 || (a->up == 1 && a->H % 2 == 0 && a->W % 2 == 0));
 }
 
 int lbfz_nn_conv(const lbfz_conv_args* a, void* stream) {
-  if (!conv_ok(a) || !a->out || (a->sign != 1 && a->sign != -1)) return LBFZ_NN_EINVAL;
+  if (!conv_ok(a) || !a->out || (a->sign != 1 && a->sign != -1) || (a->up && a->sign != 1))
+    return LBFZ_NN_EINVAL;
   const long M = (long)a->B * a->H * a->W;
-  const dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((a->N + BN - 1) / BN));
-  hipLaunchKernelGGL(k_conv, grid, dim3(256), 0, (hipStream_t)stream, *a);
+  if (M >= (1L << 30)) return LBFZ_NN_EINVAL;
+  // tile shape by output width: 128 x 128 (N a multiple of 128), 256 x 64
+  // (a multiple of 64), else 256 x 32 (column blocks of 32)
+  const hipStream_t st = (hipStream_t)stream;
+  if (a->N % 128 == 0) {
+    const dim3 grid((unsigned)((M + 127) / 128), (unsigned)(a->N / 128));
+    hipLaunchKernelGGL((k_conv<2, 2, 2, 2>), grid, dim3(256), 0, st, *a);
+  } else if (a->N % 64 == 0) {
+    const dim3 grid((unsigned)((M + 255) / 256), (unsigned)(a->N / 64));
+    hipLaunchKernelGGL((k_conv<2, 2, 4, 1>), grid, dim3(256), 0, st, *a);
+  } else {
+    const dim3 grid((unsigned)((M + 255) / 256), (unsigned)((a->N + 31) / 32));
+    hipLaunchKernelGGL((k_conv<2, 1, 4, 1>), grid, dim3(256), 0, st, *a);
+  }
   HCHK();
 }
 
@@ -485,8 +669,10 @@ int lbfz_nn_relu_bwd(const void* dy, int dy_cs, int dy_co, const void* y, int y_
 
 int lbfz_nn_maxpool2(const void* x, int x_cs, int x_co, void* y, int y_cs, int B, int H, int W,
                      int C, void* stream) {
-  if (!x || !y || H % 2 || W % 2 || C <= 0) return LBFZ_NN_EINVAL;
-  const long n = (long)B * (H / 2) * (W / 2) * C;
+  if (!x || !y || H % 2 || W % 2 || !groups_ok(C, x_cs, x_co) || !groups_ok(C, y_cs, 0))
+    return LBFZ_NN_EINVAL;
+  const long n = (long)B * (H / 2) * (W / 2) * (C / 8);
+  if (n >= (1L << 31) || (long)B * H * W >= (1L << 31)) return LBFZ_NN_EINVAL;
   hipLaunchKernelGGL(k_maxpool2, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
                      static_cast<const bf16*>(x), x_cs, x_co, static_cast<bf16*>(y), y_cs, B, H,
                      W, C);
@@ -496,8 +682,11 @@ int lbfz_nn_maxpool2(const void* x, int x_cs, int x_co, void* y, int y_cs, int B
 int lbfz_nn_maxpool2_bwd(const void* x, int x_cs, int x_co, const void* dy, int dy_cs, void* dx,
                          int dx_cs, int dx_co, int accumulate, int B, int H, int W, int C,
                          void* stream) {
-  if (!x || !dy || !dx || H % 2 || W % 2 || C <= 0) return LBFZ_NN_EINVAL;
-  const long n = (long)B * (H / 2) * (W / 2) * C;
+  if (!x || !dy || !dx || H % 2 || W % 2 || !groups_ok(C, x_cs, x_co) ||
+      !groups_ok(C, dy_cs, 0) || !groups_ok(C, dx_cs, dx_co))
+    return LBFZ_NN_EINVAL;
+  const long n = (long)B * (H / 2) * (W / 2) * (C / 8);
+  if (n >= (1L << 31) || (long)B * H * W >= (1L << 31)) return LBFZ_NN_EINVAL;
   hipLaunchKernelGGL(k_maxpool2_bwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
                      static_cast<const bf16*>(x), x_cs, x_co, static_cast<const bf16*>(dy), dy_cs,
                      static_cast<bf16*>(dx), dx_cs, dx_co, accumulate, B, H, W, C);
@@ -505,16 +694,18 @@ int lbfz_nn_maxpool2_bwd(const void* x, int x_cs, int x_co, const void* dy, int 
 }
 
 int lbfz_nn_upsample2(const void* x, int B, int H, int W, int C, void* y, void* stream) {
-  if (!x || !y || C <= 0) return LBFZ_NN_EINVAL;
-  const long n = (long)B * 4 * H * W * C;
+  if (!x || !y || !groups_ok(C, C, 0)) return LBFZ_NN_EINVAL;
+  const long n = (long)B * 4 * H * W * (C / 8);
+  if (n >= (1L << 31) || (long)B * 4 * H * W >= (1L << 31)) return LBFZ_NN_EINVAL;
   hipLaunchKernelGGL(k_upsample2, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
                      static_cast<const bf16*>(x), B, H, W, C, static_cast<bf16*>(y));
   HCHK();
 }
 
 int lbfz_nn_upsample2_bwd(const void* dy, int B, int H, int W, int C, void* dx, void* stream) {
-  if (!dy || !dx || C <= 0) return LBFZ_NN_EINVAL;
-  const long n = (long)B * H * W * C;
+  if (!dy || !dx || !groups_ok(C, C, 0)) return LBFZ_NN_EINVAL;
+  const long n = (long)B * H * W * (C / 8);
+  if (n >= (1L << 31) || (long)B * 4 * H * W >= (1L << 31)) return LBFZ_NN_EINVAL;
   hipLaunchKernelGGL(k_upsample2_bwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
                      static_cast<const bf16*>(dy), B, H, W, C, static_cast<bf16*>(dx));
   HCHK();

@@ -36,6 +36,8 @@ NIN = 8          # input planes: the six, u_z (zero in 2D) and the pressure p
 CIN0 = 16        # padded input channels
 HEAD = 8         # padded head channels
 FIELD_NAMES = ("phi", "fl", "T", "C", "ux", "uy")
+LBFZ_NN_EINVAL = -1  # codes of the lbfz_nn_* calls (include/lbfz_nn.h)
+LBFZ_NN_EHIP = -3
 
 
 class lbfz_conv_args(ctypes.Structure):
@@ -45,7 +47,7 @@ class lbfz_conv_args(ctypes.Structure):
                 ("out_cs", ctypes.c_int32), ("out_co", ctypes.c_int32),
                 ("out_f32", ctypes.c_int32), ("relu", ctypes.c_int32), ("sign", ctypes.c_int32),
                 ("B", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
-                ("taps", ctypes.c_int32)]
+                ("taps", ctypes.c_int32), ("up", ctypes.c_int32)]
 
 
 _nn = None
@@ -96,7 +98,7 @@ def _p(t):
 
 
 def conv_args(x, x_cs, x_co, cin, w, n, out, out_cs, out_co, B, H, W, taps, bias=None,
-              relu=False, sign=1, out_f32=False, dz_cs=0):
+              relu=False, sign=1, out_f32=False, dz_cs=0, up=False):
     a = lbfz_conv_args()
     a.in_ = x.data_ptr()
     a.in_cs, a.in_co, a.Cin = x_cs, x_co, cin
@@ -108,6 +110,7 @@ def conv_args(x, x_cs, x_co, cin, w, n, out, out_cs, out_co, B, H, W, taps, bias
     a.out_cs, a.out_co, a.out_f32 = out_cs, out_co, int(out_f32)
     a.relu, a.sign = int(relu), sign
     a.B, a.H, a.W, a.taps = B, H, W, taps
+    a.up = int(up)
     return a
 
 
@@ -199,17 +202,17 @@ class UNet:
         t["P2"] = torch.zeros(B * s2 * 64, **bf)
         t["A3"] = torch.zeros(B * s2 * 128, **bf)
         t["A3b"] = torch.zeros(B * s2 * 128, **bf)
-        t["U2"] = torch.zeros(B * s1 * 128, **bf)
         t["A4"] = torch.zeros(B * s1 * 64, **bf)
         t["A4b"] = torch.zeros(B * s1 * 64, **bf)
-        t["U1"] = torch.zeros(B * s0 * 64, **bf)
         t["A5"] = torch.zeros(B * s0 * 32, **bf)
         t["A5b"] = torch.zeros(B * s0 * 32, **bf)
         t["OUT"] = torch.zeros(B * s0 * HEAD, **f)
         # gradients (dX of each tensor) and pre-activation gradients (dz)
-        for k in ("A1", "CAT1", "P1", "A2", "CAT2", "P2", "A3", "A3b", "U2", "A4", "A4b", "U1",
-                  "A5", "A5b"):
+        for k in ("A1", "CAT1", "P1", "A2", "CAT2", "P2", "A3", "A3b", "A4", "A4b", "A5", "A5b"):
             t["d" + k] = torch.zeros_like(t[k])
+        # gradients at the up-convolutions' (full) resolution
+        t["dU2"] = torch.zeros(B * s1 * 128, **bf)
+        t["dU1"] = torch.zeros(B * s0 * 64, **bf)
         t["dOUT"] = torch.zeros(B * s0 * HEAD, **bf)
         t["dz"] = torch.zeros(B * s0 * 128, **bf)   # largest dz (reused per layer)
         self.t = t
@@ -245,7 +248,7 @@ class UNet:
         return self.B, s, s
 
     # ---------------------------------------------------------------- forward
-    def _conv(self, name, x, x_cs, x_co, out, out_cs, out_co, out_f32=False):
+    def _conv(self, name, x, x_cs, x_co, out, out_cs, out_co, out_f32=False, up=False):
         Ly = self.L[name]
         B, H, W = self._dims(Ly.level)
         wb, bias = self._w(name)
@@ -255,7 +258,7 @@ class UNet:
         a.bias, a.out = bias.value, out.data_ptr()
         a.out_cs, a.out_co, a.out_f32 = out_cs, out_co, int(out_f32)
         a.relu, a.sign = int(Ly.relu), 1
-        a.B, a.H, a.W, a.taps = B, H, W, Ly.taps
+        a.B, a.H, a.W, a.taps, a.up = B, H, W, Ly.taps, int(up)
         _ck(nnlib().lbfz_nn_conv(ctypes.byref(a), self.st), "conv " + name)
 
     def forward(self):
@@ -272,21 +275,22 @@ class UNet:
                                self.st), "pool2")
         self._conv("L3a", t["P2"], 64, 0, t["A3"], 128, 0)
         self._conv("L3b", t["A3"], 128, 0, t["A3b"], 128, 0)
-        _ck(L.lbfz_nn_upsample2(_p(t["A3b"]), B, S // 4, S // 4, 128, _p(t["U2"]), self.st), "up2")
-        self._conv("U2", t["U2"], 128, 0, t["CAT2"], 128, 0)
+        # the up-convolutions read the half-resolution tensor through nearest 2x
+        # upsampling inside the convolution's loads
+        self._conv("U2", t["A3b"], 128, 0, t["CAT2"], 128, 0, up=True)
         self._conv("L4a", t["CAT2"], 128, 0, t["A4"], 64, 0)
         self._conv("L4b", t["A4"], 64, 0, t["A4b"], 64, 0)
-        _ck(L.lbfz_nn_upsample2(_p(t["A4b"]), B, S // 2, S // 2, 64, _p(t["U1"]), self.st), "up1")
-        self._conv("U1", t["U1"], 64, 0, t["CAT1"], 64, 0)
+        self._conv("U1", t["A4b"], 64, 0, t["CAT1"], 64, 0, up=True)
         self._conv("L5a", t["CAT1"], 64, 0, t["A5"], 32, 0)
         self._conv("L5b", t["A5"], 32, 0, t["A5b"], 32, 0)
         self._conv("head", t["A5b"], 32, 0, t["OUT"], HEAD, 0, out_f32=True)
 
     # --------------------------------------------------------------- backward
     def _layer_bwd(self, name, x, x_cs, x_co, dy, dy_cs, dy_co, y, y_cs, y_co, dx, dx_cs,
-                   dx_co, need_dx=True):
+                   dx_co, need_dx=True, up=False):
         """Gradients of one convolution: dz = relu'(y) dy, dW, db into gf, and
-        dx (overwritten) when need_dx."""
+        dx (overwritten, at the layer's resolution) when need_dx; up: x is the
+        half-resolution tensor the layer reads through 2x upsampling."""
         L, t = nnlib(), self.t
         Ly = self.L[name]
         B, H, W = self._dims(Ly.level)
@@ -306,7 +310,7 @@ class UNet:
         a = lbfz_conv_args()
         a.in_, a.in_cs, a.in_co, a.Cin = x.data_ptr(), x_cs, x_co, Ly.cin
         a.w, a.dz_cs, a.N = dz_p.data_ptr(), dz_cs, N
-        a.B, a.H, a.W, a.taps, a.sign = B, H, W, Ly.taps, 1
+        a.B, a.H, a.W, a.taps, a.sign, a.up = B, H, W, Ly.taps, 1, int(up)
         _ck(L.lbfz_nn_conv_wgrad(ctypes.byref(a), _p(self.part), self.nsplit,
                                  ctypes.c_void_p(self.gf.data_ptr() + 4 * o), st),
             "wgrad " + name)
@@ -330,14 +334,15 @@ class UNet:
         self._layer_bwd("head", t["A5b"], 32, 0, t["dOUT"], HEAD, 0, None, 0, 0, t["dA5b"], 32, 0)
         self._layer_bwd("L5b", t["A5"], 32, 0, t["dA5b"], 32, 0, t["A5b"], 32, 0, t["dA5"], 32, 0)
         self._layer_bwd("L5a", t["CAT1"], 64, 0, t["dA5"], 32, 0, t["A5"], 32, 0, t["dCAT1"], 64, 0)
-        self._layer_bwd("U1", t["U1"], 64, 0, t["dCAT1"], 64, 0, t["CAT1"], 64, 0, t["dU1"], 64, 0)
+        self._layer_bwd("U1", t["A4b"], 64, 0, t["dCAT1"], 64, 0, t["CAT1"], 64, 0, t["dU1"], 64, 0,
+                        up=True)
         _ck(L.lbfz_nn_upsample2_bwd(_p(t["dU1"]), B, S // 2, S // 2, 64, _p(t["dA4b"]), st),
             "up1_bwd")
         self._layer_bwd("L4b", t["A4"], 64, 0, t["dA4b"], 64, 0, t["A4b"], 64, 0, t["dA4"], 64, 0)
         self._layer_bwd("L4a", t["CAT2"], 128, 0, t["dA4"], 64, 0, t["A4"], 64, 0, t["dCAT2"], 128,
                         0)
-        self._layer_bwd("U2", t["U2"], 128, 0, t["dCAT2"], 128, 0, t["CAT2"], 128, 0, t["dU2"],
-                        128, 0)
+        self._layer_bwd("U2", t["A3b"], 128, 0, t["dCAT2"], 128, 0, t["CAT2"], 128, 0, t["dU2"],
+                        128, 0, up=True)
         _ck(L.lbfz_nn_upsample2_bwd(_p(t["dU2"]), B, S // 4, S // 4, 128, _p(t["dA3b"]), st),
             "up2_bwd")
         self._layer_bwd("L3b", t["A3"], 128, 0, t["dA3b"], 128, 0, t["A3b"], 128, 0, t["dA3"],

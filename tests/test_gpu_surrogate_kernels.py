@@ -31,8 +31,15 @@ def _rel(got, ref):
     return float(np.abs(np.asarray(got, np.float64) - ref).max() / max(np.abs(ref).max(), 1e-30))
 
 
+# the forward runs a 256 x 32, 256 x 64 or 128 x 128 tile by N (and the data
+# gradient by Cin): the cases cover each shape with pixel counts that leave a
+# ragged last tile, K slices that cross taps (Cin 16, 32, 96) and a K tail
+# (K = 9 * 96 is not a multiple of the 64-deep slice)
 @pytest.mark.parametrize("B,H,W,Cin,N,taps", [(2, 16, 16, 16, 32, 9), (1, 12, 20, 32, 40, 9),
-                                              (2, 8, 8, 64, 72, 9), (2, 16, 16, 32, 8, 1)])
+                                              (2, 8, 8, 64, 72, 9), (2, 16, 16, 32, 8, 1),
+                                              (1, 20, 24, 32, 64, 9), (1, 10, 30, 64, 128, 9),
+                                              (1, 9, 14, 96, 32, 9), (2, 6, 11, 192, 64, 9),
+                                              (1, 16, 24, 128, 256, 9)])
 def test_conv_forward_and_gradients(B, H, W, Cin, N, taps):
     import torch
     import torch.nn.functional as F
@@ -82,6 +89,46 @@ def test_conv_forward_and_gradients(B, H, W, Cin, N, taps):
     gb = torch.zeros(N, dtype=torch.float32).cuda()
     assert L.lbfz_nn_bias_grad(sg._p(dz_), B * H * W, N, N, sg._p(bpart), 8, sg._p(gb), st) == 0
     assert _rel(gb.cpu().numpy(), dz.sum(axis=(0, 1, 2))) <= 1e-5
+
+
+@pytest.mark.parametrize("B,h,w,Cin,N", [(2, 6, 10, 64, 32), (1, 5, 8, 128, 64)])
+def test_conv_reading_through_upsampling(B, h, w, Cin, N):
+    """up = 1: the convolution of the nearest-2x-upsampled input, read from the
+    half-resolution tensor, against upsample-then-convolve on the CPU (forward
+    and weight gradient)."""
+    import torch
+    import torch.nn.functional as F
+    from paper_2511_09422_amd import surrogate as sg
+    import ctypes
+    rng = np.random.default_rng(77 + Cin)
+    H, W = 2 * h, 2 * w
+    x = _bf16(rng.standard_normal((B, h, w, Cin)))
+    w9 = _bf16(rng.standard_normal((N, 9, Cin)) / np.sqrt(9 * Cin))
+    dz = _bf16(rng.standard_normal((B, H, W, N)))
+    xu = torch.tensor(x).permute(0, 3, 1, 2)
+    xu = F.interpolate(xu, scale_factor=2, mode="nearest").requires_grad_(True)
+    tw = torch.tensor(np.transpose(w9, (0, 2, 1)).reshape(N, Cin, 3, 3), requires_grad=True)
+    ty = F.conv2d(xu, tw, padding=1)
+    ty.backward(torch.tensor(dz).permute(0, 3, 1, 2))
+    ref_y = ty.detach().permute(0, 2, 3, 1).numpy()
+    ref_dw = np.transpose(tw.grad.numpy().reshape(N, Cin, 9), (0, 2, 1))
+    L = sg.nnlib()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    dx_, dw_, dz_ = _dev(x, torch.bfloat16), _dev(w9, torch.bfloat16), _dev(dz, torch.bfloat16)
+    y = torch.zeros(B * H * W * N, dtype=torch.float32).cuda()
+    a = sg.conv_args(dx_, Cin, 0, Cin, dw_, N, y, N, 0, B, H, W, 9, out_f32=True, up=True)
+    assert L.lbfz_nn_conv(ctypes.byref(a), st) == 0
+    assert _rel(y.cpu().numpy().reshape(B, H, W, N), ref_y) <= 1e-4
+    part = torch.zeros(16 * N * 9 * Cin, dtype=torch.float32).cuda()
+    gw = torch.zeros(N * 9 * Cin, dtype=torch.float32).cuda()
+    a = sg.conv_args(dx_, Cin, 0, Cin, dz_, N, None, 0, 0, B, H, W, 9, dz_cs=N, up=True)
+    assert L.lbfz_nn_conv_wgrad(ctypes.byref(a), sg._p(part), 16, sg._p(gw), st) == 0
+    assert _rel(gw.cpu().numpy().reshape(N, 9, Cin), ref_dw) <= 1e-4
+    # the data gradient has no upsampled form; odd sizes are refused
+    a = sg.conv_args(dz_, N, 0, N, dw_, Cin, y, Cin, 0, B, H, W, 9, sign=-1, up=True)
+    assert L.lbfz_nn_conv(ctypes.byref(a), st) == sg.LBFZ_NN_EINVAL
+    a = sg.conv_args(dx_, Cin, 0, Cin, dw_, N, y, N, 0, B, H - 1, W, 9, up=True)
+    assert L.lbfz_nn_conv(ctypes.byref(a), st) == sg.LBFZ_NN_EINVAL
 
 
 def test_pool_and_upsample():
