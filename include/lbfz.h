@@ -148,6 +148,20 @@ int lbfz_state_floats(lbfz_handle* h, size_t* nfloats);
 int lbfz_get_state(lbfz_handle* h, float* host_dst);
 int lbfz_set_state(lbfz_handle* h, const float* host_src);
 
+/* Restart from macroscopic fields (2D): replace the state at the current time
+ * level by the equilibrium one of the given fields -- d_fields[0..6]: device
+ * FP32 planes of N values, phi, f_l, T, C, u_x, u_y, p.  Populations f, g, h,
+ * l take their equilibria (Sec. 3.1 - 3.4) of (phi, u), (p, rho, u), (E, T,
+ * u), (C, u) with E the enthalpy of (T, f_l) (the inverse of the enthalpy
+ * map: sensible heat below the solidus, latent heat by the liquid fraction,
+ * sensible heat above the liquidus); the previous level's f_s, p, u, phi, C
+ * take the same fields.  Non-equilibrium parts (and the interface force's
+ * half-step in the momentum) are dropped, so a restart from a solver's own
+ * fields is close to, not equal to, continuing it.  Asynchronous on the
+ * handle's stream.  f_l is taken as lbfz_fields exports it (1 - f_s, so 1 in
+ * the gas).  Errors: LBFZ_EINVAL (NULL), LBFZ_EUNSUPPORTED (3D). */
+int lbfz_restart_fields(lbfz_handle* h, const float* const* d_fields);
+
 /* ------------------------------------------------------------------------
  * Batched sweep: many independent 2D grids (the parameter sweep of Sec. 5's
  * study, each grid a complete solver state with its own parameters, size,
@@ -189,10 +203,24 @@ int lbfz_batch_groups(lbfz_batch* b);
 int lbfz_batch_group_config(lbfz_batch* b, int32_t group, int32_t* nx, int32_t* ny,
                             int32_t* ncases, int32_t* tile_rows, int32_t* grid_blocks);
 
-/* Fields and totals of grid i, as lbfz_fields / lbfz_totals. */
+/* Fields and totals of grid i, as lbfz_fields / lbfz_totals.  LBFZ_EINVAL
+ * for a stale grid (see lbfz_batch_select). */
 int lbfz_batch_fields(lbfz_batch* b, int32_t i, uint32_t field_mask, float* const* dst,
                       int dst_is_device);
 int lbfz_batch_totals(lbfz_batch* b, int32_t i, lbfz_totals_t* out);
+
+/* Subset stepping (the LB fallback of a screened sweep): later steps advance
+ * only the n grids listed in idx (n = 0: all grids again).  A grid left out
+ * while the others step becomes stale -- its state no longer matches the
+ * batch's time level -- until lbfz_batch_restart_fields gives it one; stepping
+ * a selection that holds a stale grid, or reading a stale grid, is
+ * LBFZ_EINVAL.  The autotuner times the selected grids.  Synchronises the
+ * stream (uploads the work tables); the next step re-captures its graph. */
+int lbfz_batch_select(lbfz_batch* b, int32_t n, const int32_t* idx);
+
+/* lbfz_restart_fields for grid i at the batch's time level; clears its stale
+ * mark.  Asynchronous. */
+int lbfz_batch_restart_fields(lbfz_batch* b, int32_t i, const float* const* d_fields);
 
 /* Release the grids, graphs and the capture stream (not the workspace). */
 void lbfz_batch_destroy(lbfz_batch* b);

@@ -109,6 +109,12 @@ int lbfz_nn_adam(float* w, const float* g, float* m, float* v, void* wb, long n,
 
 int lbfz_nn_to_bf16(const float* src, void* dst, long n, void* stream);
 
+/* out[k] = sum of the n FP32 values of plane k (at src + k * stride), k <
+ * nplanes, accumulated in FP64 in a fixed order (the per-grid sums of the
+ * screening check). */
+int lbfz_nn_plane_sums(const float* src, int nplanes, long n, long stride, double* out,
+                       void* stream);
+
 /* Wt[c][t][n] = W[n][t][c] (weights of the data-gradient convolution). */
 int lbfz_nn_transpose_w(const void* w, int N, int taps, int C, void* wt, void* stream);
 

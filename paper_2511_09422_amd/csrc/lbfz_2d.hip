@@ -767,6 +767,74 @@ __global__ __launch_bounds__(256) void k_import2d(KParams P, StepArgs A,
   }
 }
 
+// Equilibrium state of given macroscopic fields (restart from fields, e.g. a
+// surrogate's prediction): the raw state planes of the exported layout --
+// populations f, g, h, l at their equilibria of Sec. 3.1 - 3.4 for (phi, u),
+// (p, rho, u), (E, T, u), (C, u), then the previous level's f_s, p, u, phi, C
+// set to the same fields.  The liquid fraction comes as exported, 1 - f_s
+// with f_s = psi (1 - f_l) <= psi; the enthalpy is the inverse of the
+// enthalpy map written as sensible heat below the solidus, latent heat by
+// the liquid fraction, sensible heat above the liquidus,
+//   E = rc_s min(T, T_sol) + f_l (E_l - E_s) + rc_l max(T - T_liq, 0),
+// which equals the map's E on each branch and, unlike a choice of branch by
+// f_l or T alone, stays well-behaved for fields slightly off the map (a
+// pure substance's mushy band is the single temperature T_m).  The flow's
+// momentum is rho u / (1 - f_s / 2) (the solid drag's half-step undone, the
+// interface force's half-step left out).  Non-equilibrium parts are zero.
+__global__ __launch_bounds__(256) void k_equil2d(KParams P, EquilFields F, StatePlanes S) {
+  const long N = P.N;
+  for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < N;
+       n += (long)gridDim.x * blockDim.x) {
+    const float phi = F.phi[n], T = F.T[n], C = F.C[n];
+    const float ux = F.ux[n], uy = F.uy[n], p = F.p[n];
+    const float psi = clamp01(0.5f * (1.0f + phi));
+    const float fs = fminf(fmaxf(1.0f - F.fl[n], 0.0f), psi);
+    const float fl = psi > 0.0f ? clamp01(1.0f - fs / psi) : 1.0f;
+    const float rcs = psi * P.rc_s + (1.0f - psi) * P.rc_g;
+    const float rcl = psi * P.rc_l + (1.0f - psi) * P.rc_g;
+    const float Es = rcs * P.T_sol, El = rcl * P.T_liq + psi * P.rho_l_latent;
+    const float E = rcs * fminf(T, P.T_sol) + fl * (El - Es) + rcl * fmaxf(T - P.T_liq, 0.0f);
+    const float rho = interp(phi, fs, P.rho_l, P.rho_g, P.rho_s);
+    const float rcp = rho * interp(phi, fs, P.cp_l, P.cp_g, P.cp_s);
+    const float uu = ux * ux + uy * uy;
+    float f0 = phi, h0 = E, l0 = C;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      const float cu = CX[i] * ux + CY[i] * uy;
+      const float fi = W5[i] * phi * (1.0f + kInvCs2 * cu);
+      const float hi = W5[i] * (P.rhoc_ref * T + rcp * T * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+      const float li = W5[i] * C * (1.0f + kInvCs2 * cu);
+      S.p[PF + i][n] = fi;
+      S.p[PH + i][n] = hi;
+      S.p[PL + i][n] = li;
+      f0 -= fi;
+      h0 -= hi;
+      l0 -= li;
+    }
+    S.p[PF][n] = f0;
+    S.p[PH][n] = h0;
+    S.p[PL][n] = l0;
+    const float dr = 1.0f / (1.0f - 0.5f * fs);
+    const float vx = ux * dr, vy = uy * dr, vv = vx * vx + vy * vy;
+    float g0 = 0.0f;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const float cu = CX[i] * vx + CY[i] * vy;
+      const float gi = p * kInvCs2 * W9[i] + rho * W9[i] * (3.0f * cu + 4.5f * cu * cu - 1.5f * vv);
+      S.p[PG + i][n] = gi;
+      g0 -= gi;
+    }
+    S.p[PG][n] = g0;
+    // previous level: f_s, p, u_x, u_y, phi, C
+    S.p[24][n] = fs;
+    S.p[25][n] = p;
+    S.p[26][n] = ux;
+    S.p[27][n] = uy;
+    S.p[28][n] = phi;
+    S.p[29][n] = C;
+  }
+}
+
 int grid_of(long N) { return (int)std::min<long>((N + 255) / 256, 65536); }
 
 }  // namespace
@@ -861,6 +929,12 @@ hipError_t launch_import2d(const KParams& P, int storage, const StepArgs& A, con
     hipLaunchKernelGGL(k_import2d<LBFZ_STORE_F16>, dim3(blocks), dim3(256), 0, st, P, A, src);
   else
     hipLaunchKernelGGL(k_import2d<LBFZ_STORE_BF16>, dim3(blocks), dim3(256), 0, st, P, A, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_equil2d(const KParams& P, const EquilFields& F, const StatePlanes& S,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_equil2d, dim3(grid_of(P.N)), dim3(256), 0, st, P, F, S);
   return hipGetLastError();
 }
 

@@ -459,6 +459,26 @@ int lbfz_get_state(lbfz_handle* h, float* host_dst) {
   return LBFZ_OK;
 }
 
+namespace {
+// 16-bit storage: encode the raw state planes (stage buffer and previous-level
+// planes) into the populations, against the imported phi, C and p (p doubles
+// as the g reference).  Asynchronous.
+int import_narrow(lbfz_handle* h) {
+  const size_t N = (size_t)h->kp.N;
+  StepArgs a = base_args(h);
+  HIPCHK(hipMemcpyAsync((void*)a.p_ref, a.p_old, N * sizeof(float), hipMemcpyDeviceToDevice,
+                        h->stream));
+  a.dst = h->pop[h->cur];
+  if (h->prm.dim == 3) {
+    HIPCHK(launch_import3d(h->kp, h->storage, a, h->stage, h->stream));
+  } else {
+    a.T_new = h->T[h->cur];
+    HIPCHK(launch_import2d(h->kp, h->storage, a, h->stage, h->stream));
+  }
+  return LBFZ_OK;
+}
+}  // namespace
+
 int lbfz_set_state(lbfz_handle* h, const float* host_src) {
   if (!h || !host_src) return LBFZ_EINVAL;
   const size_t N = (size_t)h->kp.N;
@@ -468,19 +488,26 @@ int lbfz_set_state(lbfz_handle* h, const float* host_src) {
     HIPCHK(hipMemcpyAsync(planes[k], host_src + k * N, N * sizeof(float), hipMemcpyHostToDevice,
                           h->stream));
   if (h->narrow) {
-    // encode against the imported phi, C and p (p doubles as the g reference)
-    StepArgs a = base_args(h);
-    HIPCHK(hipMemcpyAsync((void*)a.p_ref, a.p_old, N * sizeof(float), hipMemcpyDeviceToDevice,
-                          h->stream));
-    a.dst = h->pop[h->cur];
-    if (h->prm.dim == 3) {
-      HIPCHK(launch_import3d(h->kp, h->storage, a, h->stage, h->stream));
-    } else {
-      a.T_new = h->T[h->cur];
-      HIPCHK(launch_import2d(h->kp, h->storage, a, h->stage, h->stream));
-    }
+    const int rc = import_narrow(h);
+    if (rc != LBFZ_OK) return rc;
   }
   HIPCHK(hipStreamSynchronize(h->stream));
+  return LBFZ_OK;
+}
+
+int lbfz_restart_fields(lbfz_handle* h, const float* const* d_fields) {
+  if (!h || !d_fields) return LBFZ_EINVAL;
+  for (int k = 0; k < 7; ++k)
+    if (!d_fields[k]) return LBFZ_EINVAL;
+  if (h->prm.dim != 2) return LBFZ_EUNSUPPORTED;
+  std::vector<float*> planes;
+  if (state_planes(h, planes) != 30) return LBFZ_EUNSUPPORTED;
+  EquilFields F{d_fields[0], d_fields[1], d_fields[2], d_fields[3],
+                d_fields[4], d_fields[5], d_fields[6]};
+  StatePlanes S;
+  for (int k = 0; k < 30; ++k) S.p[k] = planes[k];
+  HIPCHK(launch_equil2d(h->kp, F, S, h->stream));
+  if (h->narrow) return import_narrow(h);
   return LBFZ_OK;
 }
 

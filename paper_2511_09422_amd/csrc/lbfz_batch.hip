@@ -34,7 +34,10 @@ struct Group {
   int nx, ny;
   std::vector<int> cases;
   int nwork[2];      // work items at tile height kTY[v]
-  int2* work[2];     // device work tables
+  int2* work[2];     // device work tables (every grid of the group)
+  int nsel[2];       // the same for the selected grids (lbfz_batch_select)
+  int2* sel[2];
+  bool all = true;   // every grid selected: launch over work[], else sel[]
   int ty_index = 0;  // chosen tile height (index into kTY)
   int grid = 0;      // blocks per launch; 0: one per work item
 };
@@ -58,6 +61,8 @@ struct lbfz_batch {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int64_t step = 0;
+  std::vector<char> selected;  // per grid: advanced by the steps
+  std::vector<char> stale;     // per grid: left behind by a subset step
 };
 
 namespace {
@@ -99,8 +104,34 @@ int upload_cases(lbfz_batch* b) {
 
 hipError_t launch_group(lbfz_batch* b, const Group& g, int64_t step, hipStream_t st) {
   const int v = g.ty_index;
-  return launch_step2d_batch(b->storage, kTY[v], b->d_cases, g.work[v], g.nwork[v], g.grid,
-                             (int)(step % b->L), st);
+  const int n = g.all ? g.nwork[v] : g.nsel[v];
+  if (n == 0) return hipSuccess;  // no grid of the group selected
+  return launch_step2d_batch(b->storage, kTY[v], b->d_cases, g.all ? g.work[v] : g.sel[v], n,
+                             g.grid, (int)(step % b->L), st);
+}
+
+// XCD-aware order of a flat (grid, tile) item list: item e runs on the XCD
+// e % 8, which gets a contiguous band of the flat list.
+std::vector<int2> xcd_order(const std::vector<int2>& flat) {
+  const int n = (int)flat.size();
+  std::vector<int2> tab(n);
+  const int band = n >> 3;
+  for (int e = 0; e < n; ++e)
+    tab[e] = (band == 0 || (n & 7)) ? flat[e] : flat[(e & 7) * band + (e >> 3)];
+  return tab;
+}
+
+// Items of the grids of group g for which keep(grid) holds, tile height kTY[v].
+template <class F>
+std::vector<int2> group_items(const Group& g, int v, F keep) {
+  int nbx, nby;
+  const int per = tiles2d(g.nx, g.ny, &nbx, &nby, kTY[v]);
+  std::vector<int2> flat;
+  flat.reserve((size_t)per * g.cases.size());
+  for (int c : g.cases)
+    if (keep(c))
+      for (int t = 0; t < per; ++t) flat.push_back(make_int2(c, t));
+  return xcd_order(flat);
 }
 
 void drop_graph(lbfz_batch* b) {
@@ -133,6 +164,17 @@ int build_graph(lbfz_batch* b) {
   return LBFZ_OK;
 }
 
+// A step over the selection: every selected grid must be current; the grids
+// left out fall behind the batch's time level.
+int begin_step(lbfz_batch* b, int64_t nsteps) {
+  for (int i = 0; i < b->ncases; ++i)
+    if (b->selected[i] && b->stale[i]) return LBFZ_EINVAL;
+  if (nsteps > 0)
+    for (int i = 0; i < b->ncases; ++i)
+      if (!b->selected[i]) b->stale[i] = 1;
+  return LBFZ_OK;
+}
+
 void sync_handles(lbfz_batch* b) {
   for (lbfz_handle* h : b->h) {
     h->step = b->step;
@@ -157,7 +199,7 @@ int lbfz_batch_workspace_bytes(int32_t ncases, const lbfz_params* params, size_t
     for (int ty : kTY) items += (size_t)tiles2d(params[i].nx, params[i].ny, &nbx, &nby, ty);
   }
   total += align256(sizeof(BatchCase) * (size_t)ncases);
-  total += align256(sizeof(int2) * items) + 256 * 2 * (size_t)ncases;
+  total += 2 * (align256(sizeof(int2) * items) + 256 * 2 * (size_t)ncases);
   *bytes = total;
   return LBFZ_OK;
 }
@@ -195,6 +237,8 @@ int lbfz_batch_create(int32_t ncases, const lbfz_params* params, const double* c
   b->d_cases = (BatchCase*)q;
   q += align256(sizeof(BatchCase) * (size_t)ncases);
   b->cases.resize(ncases);
+  b->selected.assign(ncases, 1);
+  b->stale.assign(ncases, 0);
   // groups of equal grid size, in order of first appearance
   std::map<std::pair<int, int>, int> gid;
   for (int i = 0; i < ncases; ++i) {
@@ -213,19 +257,13 @@ int lbfz_batch_create(int32_t ncases, const lbfz_params* params, const double* c
   // XCD e % 8, which gets a contiguous band of the flat item list)
   for (auto& g : b->groups) {
     for (int v = 0; v < 2; ++v) {
-      int nbx, nby;
-      const int per = tiles2d(g.nx, g.ny, &nbx, &nby, kTY[v]);
-      std::vector<int2> flat;
-      flat.reserve((size_t)per * g.cases.size());
-      for (int c : g.cases)
-        for (int t = 0; t < per; ++t) flat.push_back(make_int2(c, t));
-      const int n = (int)flat.size();
-      std::vector<int2> tab(n);
-      const int band = n >> 3;
-      for (int e = 0; e < n; ++e)
-        tab[e] = (band == 0 || (n & 7)) ? flat[e] : flat[(e & 7) * band + (e >> 3)];
+      const std::vector<int2> tab = group_items(g, v, [](int) { return true; });
+      const int n = (int)tab.size();
       g.nwork[v] = n;
       g.work[v] = (int2*)q;
+      q += align256(sizeof(int2) * (size_t)n);
+      g.nsel[v] = 0;
+      g.sel[v] = (int2*)q;  // room for a selection of every grid
       q += align256(sizeof(int2) * (size_t)n);
       if (hipMemcpyAsync(g.work[v], tab.data(), sizeof(int2) * n, hipMemcpyHostToDevice,
                          b->stream) != hipSuccess ||
@@ -251,6 +289,10 @@ int lbfz_batch_create(int32_t ncases, const lbfz_params* params, const double* c
 
 int lbfz_batch_tune(lbfz_batch* b, int32_t trial_steps) {
   if (!b || trial_steps <= 0) return LBFZ_EINVAL;
+  {
+    const int rc = begin_step(b, trial_steps);
+    if (rc != LBFZ_OK) return rc;
+  }
   // candidates: tile height x launch shape (one block per item, or a
   // persistent grid of blocks_per_cu x 256 blocks)
   struct Cand {
@@ -303,6 +345,10 @@ int lbfz_batch_tune(lbfz_batch* b, int32_t trial_steps) {
 
 int lbfz_batch_step(lbfz_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBFZ_EINVAL;
+  {
+    const int rc = begin_step(b, nsteps);
+    if (rc != LBFZ_OK) return rc;
+  }
   auto one = [&]() -> int {
     for (auto& g : b->groups) HIPCHK(launch_group(b, g, b->step, b->stream));
     b->step += 1;
@@ -335,9 +381,14 @@ int lbfz_batch_step(lbfz_batch* b, int64_t nsteps) {
 
 int lbfz_batch_step_sequential(lbfz_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBFZ_EINVAL;
+  {
+    const int rc = begin_step(b, nsteps);
+    if (rc != LBFZ_OK) return rc;
+  }
   sync_handles(b);
-  for (lbfz_handle* h : b->h) {
-    const int rc = lbfz_step(h, nsteps);
+  for (int i = 0; i < b->ncases; ++i) {
+    if (!b->selected[i]) continue;
+    const int rc = lbfz_step(b->h[i], nsteps);
     if (rc != LBFZ_OK) return rc;
   }
   b->step += nsteps;
@@ -361,15 +412,48 @@ int lbfz_batch_group_config(lbfz_batch* b, int32_t group, int32_t* nx, int32_t* 
 
 int lbfz_batch_fields(lbfz_batch* b, int32_t i, uint32_t field_mask, float* const* dst,
                       int dst_is_device) {
-  if (!b || i < 0 || i >= b->ncases) return LBFZ_EINVAL;
+  if (!b || i < 0 || i >= b->ncases || b->stale[i]) return LBFZ_EINVAL;
   sync_handles(b);
   return lbfz_fields(b->h[i], field_mask, dst, dst_is_device);
 }
 
 int lbfz_batch_totals(lbfz_batch* b, int32_t i, lbfz_totals_t* out) {
-  if (!b || i < 0 || i >= b->ncases) return LBFZ_EINVAL;
+  if (!b || i < 0 || i >= b->ncases || b->stale[i]) return LBFZ_EINVAL;
   sync_handles(b);
   return lbfz_totals(b->h[i], out);
+}
+
+int lbfz_batch_select(lbfz_batch* b, int32_t n, const int32_t* idx) {
+  if (!b || n < 0 || (n > 0 && !idx)) return LBFZ_EINVAL;
+  std::vector<char> sel(b->ncases, n == 0 ? 1 : 0);
+  for (int k = 0; k < n; ++k) {
+    if (idx[k] < 0 || idx[k] >= b->ncases) return LBFZ_EINVAL;
+    sel[idx[k]] = 1;
+  }
+  b->selected = sel;
+  for (auto& g : b->groups) {
+    g.all = true;
+    for (int c : g.cases) g.all = g.all && sel[c];
+    if (g.all) continue;
+    for (int v = 0; v < 2; ++v) {
+      const std::vector<int2> tab = group_items(g, v, [&](int c) { return sel[c] != 0; });
+      g.nsel[v] = (int)tab.size();
+      if (g.nsel[v] > 0)
+        HIPCHK(hipMemcpyAsync(g.sel[v], tab.data(), sizeof(int2) * tab.size(),
+                              hipMemcpyHostToDevice, b->stream));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(b->stream));
+  drop_graph(b);
+  return LBFZ_OK;
+}
+
+int lbfz_batch_restart_fields(lbfz_batch* b, int32_t i, const float* const* d_fields) {
+  if (!b || i < 0 || i >= b->ncases) return LBFZ_EINVAL;
+  sync_handles(b);
+  const int rc = lbfz_restart_fields(b->h[i], d_fields);
+  if (rc == LBFZ_OK) b->stale[i] = 0;
+  return rc;
 }
 
 void lbfz_batch_destroy(lbfz_batch* b) {

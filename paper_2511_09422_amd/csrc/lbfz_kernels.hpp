@@ -67,6 +67,17 @@ hipError_t launch_export2d(const KParams& P, int storage, const StepArgs& A, flo
 hipError_t launch_import2d(const KParams& P, int storage, const StepArgs& A, const float* src,
                            hipStream_t st);
 
+// Macroscopic fields of a 2D restart (device FP32 planes of N values) and the
+// 30 raw state planes it writes (the exported layout).
+struct EquilFields {
+  const float *phi, *fl, *T, *C, *ux, *uy, *p;
+};
+struct StatePlanes {
+  float* p[30];
+};
+hipError_t launch_equil2d(const KParams& P, const EquilFields& F, const StatePlanes& S,
+                          hipStream_t st);
+
 int tiles3d(int nx, int ny, int nz, int* nbx, int* nby, int* nbz);
 size_t pop_bytes3d(int storage, size_t ps);
 hipError_t launch_init3d(const KParams& P, int storage, const double* phi, const double* T,

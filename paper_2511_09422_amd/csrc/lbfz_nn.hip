@@ -495,6 +495,24 @@ __global__ void k_sum_f64(const double* __restrict__ part, int n, double* __rest
   }
 }
 
+// Sum of each of nplanes FP32 planes (plane k at src + k * stride, n values),
+// one block per plane, FP64 in a fixed order (per-thread strided sums, then a
+// tree over the block).
+__global__ __launch_bounds__(256) void k_plane_sums(const float* __restrict__ src, long n,
+                                                    long stride, double* __restrict__ out) {
+  __shared__ double red[256];
+  const float* p = src + blockIdx.x * stride;
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < n; i += 256) acc += (double)p[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 // Adam on FP32 master weights (bias-corrected), then the bf16 copy.
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, bf16* __restrict__ wb, long n, float lr, float b1,
@@ -727,6 +745,14 @@ int lbfz_nn_mse(const float* out, int out_cs, const float* tgt, long P, int C, c
                      C, wch, static_cast<bf16*>(dout), part);
   if (hipGetLastError() != hipSuccess) return LBFZ_NN_EHIP;
   hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, (hipStream_t)stream, part, nblocks, loss);
+  HCHK();
+}
+
+int lbfz_nn_plane_sums(const float* src, int nplanes, long n, long stride, double* out,
+                       void* stream) {
+  if (!src || !out || nplanes <= 0 || n <= 0 || stride < n) return LBFZ_NN_EINVAL;
+  hipLaunchKernelGGL(k_plane_sums, dim3(nplanes), dim3(256), 0, (hipStream_t)stream, src, n,
+                     stride, out);
   HCHK();
 }
 

@@ -91,12 +91,17 @@ def lib() -> ctypes.CDLL:
         L.lbfz_batch_totals.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(lbfz_totals_t)]
         L.lbfz_batch_destroy.argtypes = [vp]
         L.lbfz_batch_destroy.restype = None
+        vpp = ctypes.POINTER(ctypes.c_void_p)
+        L.lbfz_restart_fields.argtypes = [vp, vpp]
+        L.lbfz_batch_select.argtypes = [vp, ctypes.c_int32, ip]
+        L.lbfz_batch_restart_fields.argtypes = [vp, ctypes.c_int32, vpp]
         for nm in ("lbfz_workspace_bytes", "lbfz_create", "lbfz_step", "lbfz_fields",
                    "lbfz_totals", "lbfz_sync", "lbfz_state_floats", "lbfz_get_state",
                    "lbfz_set_state", "lbfz_batch_workspace_bytes", "lbfz_batch_create",
                    "lbfz_batch_tune", "lbfz_batch_step", "lbfz_batch_step_sequential",
                    "lbfz_batch_groups", "lbfz_batch_group_config", "lbfz_batch_fields",
-                   "lbfz_batch_totals"):
+                   "lbfz_batch_totals", "lbfz_restart_fields", "lbfz_batch_select",
+                   "lbfz_batch_restart_fields"):
             getattr(L, nm).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -186,6 +191,20 @@ def lbfz_set_state(h, arr) -> None:
     _check(lib().lbfz_set_state(h, a.ctypes.data_as(ctypes.c_void_p)), "lbfz_set_state")
 
 
+RESTART_FIELDS = ("phi", "fl", "T", "C", "ux", "uy", "p")
+
+
+def _field_ptrs(planes):
+    if len(planes) != len(RESTART_FIELDS):
+        raise ValueError(f"restart takes {len(RESTART_FIELDS)} planes {RESTART_FIELDS}")
+    return (ctypes.c_void_p * len(planes))(*[t.data_ptr() for t in planes])
+
+
+def lbfz_restart_fields(h, planes) -> None:
+    """planes: device tensors (FP32, N values each) in RESTART_FIELDS order."""
+    _check(lib().lbfz_restart_fields(h, _field_ptrs(planes)), "lbfz_restart_fields")
+
+
 def lbfz_sync(h):
     _check(lib().lbfz_sync(h), "lbfz_sync")
 
@@ -215,14 +234,17 @@ class Solver:
         self._h = lbfz_create(cfg, phi, T, C, mask, self.workspace.data_ptr(), nbytes,
                               self.stream.cuda_stream, storage)
 
-    def close(self):
+    def close(self, _destroy=lbfz_destroy):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lbfz_destroy(h)
+            _destroy(h)
         self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter exit: the library may be unloaded already
+            pass
 
     def step(self, n: int = 1):
         lbfz_step(self._h, n)
@@ -258,6 +280,10 @@ class Solver:
 
     def set_state(self, arr) -> None:
         lbfz_set_state(self._h, arr)
+
+    def restart_fields(self, planes) -> None:
+        """Equilibrium restart from device planes (RESTART_FIELDS order)."""
+        lbfz_restart_fields(self._h, planes)
 
 
 # --------------------------------------------------------------------------
@@ -325,6 +351,17 @@ def lbfz_batch_totals(b, i: int) -> dict:
     return {k: getattr(t, k) for k, _ in lbfz_totals_t._fields_}
 
 
+def lbfz_batch_select(b, idx) -> None:
+    idx = [int(i) for i in idx]
+    arr = (ctypes.c_int32 * max(len(idx), 1))(*idx)
+    _check(lib().lbfz_batch_select(b, len(idx), arr), "lbfz_batch_select")
+
+
+def lbfz_batch_restart_fields(b, i: int, planes) -> None:
+    _check(lib().lbfz_batch_restart_fields(b, int(i), _field_ptrs(planes)),
+           "lbfz_batch_restart_fields")
+
+
 def lbfz_batch_destroy(b):
     lib().lbfz_batch_destroy(b)
 
@@ -347,14 +384,17 @@ class Batch:
                                     self.workspace.data_ptr(), nbytes, self.stream.cuda_stream,
                                     storage)
 
-    def close(self):
+    def close(self, _destroy=lbfz_batch_destroy):
         b = getattr(self, "_b", None)
         if b is not None and b.value:
-            lbfz_batch_destroy(b)
+            _destroy(b)
         self._b = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter exit: the library may be unloaded already
+            pass
 
     def tune(self, trial_steps: int = 8):
         lbfz_batch_tune(self._b, trial_steps)
@@ -393,3 +433,11 @@ class Batch:
 
     def totals(self, i: int) -> dict:
         return lbfz_batch_totals(self._b, i)
+
+    def select(self, idx=()) -> None:
+        """Later steps advance only the grids in idx (empty: all)."""
+        lbfz_batch_select(self._b, idx)
+
+    def restart_fields(self, i: int, planes) -> None:
+        """Equilibrium restart of grid i from device planes (RESTART_FIELDS)."""
+        lbfz_batch_restart_fields(self._b, i, planes)

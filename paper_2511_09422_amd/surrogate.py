@@ -72,6 +72,7 @@ def nnlib():
             "lbfz_nn_upsample2_bwd": [vp, i32, i32, i32, i32, vp, vp],
             "lbfz_nn_fill_u32": [vp, lg, u32, vp],
             "lbfz_nn_mse": [vp, i32, vp, lg, i32, vp, vp, vp, i32, vp, vp],
+            "lbfz_nn_plane_sums": [vp, i32, lg, lg, vp, vp],
             "lbfz_nn_adam": [vp, vp, vp, vp, vp, lg, f32, f32, f32, f32, i32, vp],
             "lbfz_nn_to_bf16": [vp, vp, lg, vp],
             "lbfz_nn_transpose_w": [vp, i32, i32, i32, vp, vp],
@@ -437,7 +438,7 @@ RESIDUAL = (1.0, 1.0, 1.0, 1.0, 0.0, 0.0)
 # loss weight per field: the velocity 64 steps ahead is largely unpredictable
 # from one snapshot (grid-scale currents decorrelate within the stride), so
 # it is weighted down to keep its irreducible error from swamping the rest
-LOSS_WEIGHT = (1.0, 1.0, 1.0, 1.0, 0.1, 0.1)
+LOSS_WEIGHT = (1.0, 1.0, 2.0, 1.0, 0.1, 0.1)
 
 
 class Normaliser:
@@ -513,21 +514,110 @@ def predict(net: UNet, snaps, norm: Normaliser, pairs, out):
                                   b, net.st), "apply_delta")
 
 
-def mass_residual(before, after, ratio: float) -> float:
-    """|sum dphi - ratio * sum df_s| / sum (1 + phi_in) / 2, with f_s = 1 - f_l
-    and ratio = 1 - rho_s / rho_l (fields [NF][S][S], any device)."""
-    dphi = float((after[0] - before[0]).double().sum())
-    dfs = -float((after[1] - before[1]).double().sum())
-    denom = float(((1.0 + before[0].double()) * 0.5).sum())
+# ---------------------------------------------------------------- screening
+SOLUTE_TOL = 5e-4  # screening: largest accepted relative drift of sum C
+
+
+def mass_residual(sum_phi_b, sum_phi_a, sum_fl_b, sum_fl_a, n: int, ratio: float) -> float:
+    """Phase-field mass residual of a prediction from per-grid sums:
+    |sum dphi - ratio * sum df_s| / sum (1 + phi_before) / 2 over the n nodes,
+    with df_s = -df_l and ratio = 1 - rho_s / rho_l (the volume change of
+    freezing, Eq. NS1)."""
+    dphi = sum_phi_a - sum_phi_b
+    dfs = -(sum_fl_a - sum_fl_b)
+    denom = 0.5 * (n + sum_phi_b)
     return abs(dphi - ratio * dfs) / max(denom, 1e-30)
 
 
-def solute_drift(before, after) -> float:
-    """|sum C_after - sum C_before| / sum C_before: the LB step conserves the
-    solute exactly (to FP32 rounding), so a prediction's drift measures its
-    error in the one field with an exact budget."""
-    c0 = float(before[3].double().sum())
-    return abs(float(after[3].double().sum()) - c0) / max(abs(c0), 1e-30)
+def solute_drift(sum_c_b, sum_c_a) -> float:
+    """|sum C_after - sum C_before| / |sum C_before|: the LB step conserves
+    the solute (Sec. 3.4) to FP32 rounding, so the drift of a prediction
+    measures its error in the one field with an exact budget."""
+    return abs(sum_c_a - sum_c_b) / max(abs(sum_c_b), 1e-30)
+
+
+def check(sums_before, sums_after, n: int, ratio: float, mass_tol: float = MASS_TOL,
+          solute_tol: float = SOLUTE_TOL):
+    """Accept a prediction (True) or send its grid to the LB (False).
+    sums_*: per-field sums (phi, f_l, T, C, ...) of the grid before the
+    stride and of the prediction.  Returns (accept, mass residual, drift)."""
+    r = mass_residual(sums_before[0], sums_after[0], sums_before[1], sums_after[1], n, ratio)
+    d = solute_drift(sums_before[3], sums_after[3])
+    ok = bool(np.isfinite(r) and np.isfinite(d) and r <= mass_tol and d <= solute_tol)
+    return ok, r, d
+
+
+class Screener:
+    """Screens a batched sweep (an lbfz.Batch of equal S x S grids) STRIDE
+    steps at a time: one surrogate forward over every grid; grids whose
+    prediction passes the check take it (equilibrium restart from the
+    predicted phi, f_l, T, C, u and the pressure before the stride), the rest
+    are advanced by the LB (subset step).  net: a UNet of batch >= the number
+    of grids and side S."""
+
+    def __init__(self, net: UNet, norm: Normaliser, batch, mass_tol: float = MASS_TOL,
+                 solute_tol: float = SOLUTE_TOL):
+        import torch
+        self.net, self.norm, self.batch = net, norm, batch
+        self.n = len(batch.cfgs)
+        S = net.S
+        if any(sh != (S, S) for sh in batch.shapes) or self.n > net.B:
+            raise ValueError("screening needs grids of the network's side, at most its batch")
+        self.S = S
+        self.ratios = [1.0 - c["rho_s"] / c["rho_l"] for c in batch.cfgs]
+        self.mass_tol, self.solute_tol = mass_tol, solute_tol
+        f = dict(dtype=torch.float32, device=net.dev)
+        self.before = torch.zeros((self.n, NIN, S, S), **f)
+        self.pred = torch.zeros((self.n, NF, S, S), **f)
+        self.sums_b = torch.zeros(self.n * NIN, dtype=torch.float64, device=net.dev)
+        self.sums_a = torch.zeros(self.n * NF, dtype=torch.float64, device=net.dev)
+        self.time = 0  # LB steps screened so far (the batch's own counter only
+        # moves when some grid falls back to the LB)
+
+    def predict(self):
+        """Export every grid's fields, run the network, apply its output:
+        self.pred holds the fields STRIDE steps ahead.  Returns the per-grid
+        (accept, mass residual, solute drift) of the check."""
+        L, net, S, st = nnlib(), self.net, self.S, self.net.st
+        for i in range(self.n):
+            self.batch.fields_to_device(i, [self.before[i, f] for f in range(NIN)])
+        for i in range(self.n):
+            _ck(L.lbfz_nn_pack_fields(_p(self.before[i]), NIN, S, S, 0, 0, S,
+                                      _p(self.norm.in_shift), _p(self.norm.in_scale),
+                                      _p(net.t["X0"]), CIN0, i, st), "pack_fields")
+        net.forward()
+        for i in range(self.n):
+            _ck(L.lbfz_nn_apply_delta(_p(net.t["OUT"]), HEAD, _p(self.before[i]), NF, S, S,
+                                      _p(self.norm.d_shift), _p(self.norm.d_scale),
+                                      _p(self.norm.resid), _p(self.pred[i]), i, st),
+                "apply_delta")
+        _ck(L.lbfz_nn_plane_sums(_p(self.before), self.n * NIN, S * S, S * S, _p(self.sums_b),
+                                 st), "plane_sums")
+        _ck(L.lbfz_nn_plane_sums(_p(self.pred), self.n * NF, S * S, S * S, _p(self.sums_a),
+                                 st), "plane_sums")
+        sb = self.sums_b.cpu().numpy().reshape(self.n, NIN)
+        sa = self.sums_a.cpu().numpy().reshape(self.n, NF)
+        return [check(sb[i], sa[i], S * S, self.ratios[i], self.mass_tol, self.solute_tol)
+                for i in range(self.n)]
+
+    def stride(self):
+        """One screened stride; returns the accept mask (list of bool) and the
+        check values."""
+        res = self.predict()
+        acc = [r[0] for r in res]
+        rej = [i for i in range(self.n) if not acc[i]]
+        if rej:
+            # the LB fallback advances only the rejected grids; the others are
+            # restarted from their predictions at the new time level
+            self.batch.select(rej)
+            self.batch.step(STRIDE)
+        self.time += STRIDE
+        for i in range(self.n):
+            if acc[i]:
+                self.batch.restart_fields(
+                    i, [self.pred[i, f] for f in range(NF)] + [self.before[i, NIN - 1]])
+        self.batch.select([])
+        return acc, res
 
 
 def rel_l2(a, b) -> list:

@@ -1,0 +1,110 @@
+"""Equilibrium restart from macroscopic fields and subset stepping of a
+batch (the two halves of the surrogate screening's LB fallback).
+
+Restart: populations at the equilibria of (phi, f_l, T, C, u, p) drop the
+non-equilibrium parts and the interface force's half-step, so a restart from a
+solver's own fields reproduces those fields to the size of those parts (a
+first GPU run measured phi, f_l, C within 1e-4 and T within 1e-3 relative L2;
+the bars are 3x that), and 64 steps run on from a restart stay close to 64
+steps of the original: the slow fields within 1e-2 (the screening's accuracy
+bar).  The velocity and the pressure carry the dropped parts and are only
+checked to stay finite and bounded.
+
+Subset stepping: a grid's step in the batch kernel does not depend on which
+other grids share the launch, so the selected grids match a batch that steps
+every grid bit for bit; the grids left out are stale (reads and steps refused)
+until restarted."""
+import numpy as np
+import pytest
+
+from paper_2511_09422_amd.workloads import droplet_2d, sweep_case
+
+pytestmark = pytest.mark.gpu
+
+RESTART = ("phi", "fl", "T", "C", "ux", "uy", "p")
+SLOW = ("phi", "fl", "T", "C")
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _freezing_case():
+    # a droplet on the cold wall, far enough along that a solid layer, a
+    # mushy band and a flow exist
+    return droplet_2d(96, 80, R=26.0, seed=7, T0=-0.05, sigma_T=-3e-4, rho_s=0.9)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_restart_from_own_fields(storage):
+    import torch
+    from paper_2511_09422_amd.lbfz import Solver
+    cfg, phi, T, C = _freezing_case()
+    a = Solver(cfg, phi, T, C, storage=storage)
+    ref = Solver(cfg, phi, T, C, storage=storage)
+    a.step(300)
+    ref.step(300)
+    f0 = a.fields(RESTART, device=True)
+    assert float((1.0 - f0["fl"]).sum()) > 20.0, "no solid formed: the case does not exercise f_l"
+    a.restart_fields([f0[k].contiguous() for k in RESTART])
+    f1 = a.fields(RESTART)
+    torch.cuda.synchronize()
+    errs = {k: _rel(f1[k], f0[k].cpu().numpy()) for k in SLOW}
+    print(f"[restart {storage}] re-exported fields rel L2 {errs}", flush=True)
+    for k in ("phi", "fl", "C"):
+        assert errs[k] <= 3e-4, (k, errs[k])
+    assert errs["T"] <= 3e-3
+    a.step(64)
+    ref.step(64)
+    fa, fr = a.fields(RESTART), ref.fields(RESTART)
+    after = {k: _rel(fa[k], fr[k]) for k in RESTART}
+    print(f"[restart {storage}] 64 steps on, rel L2 against the original {after}", flush=True)
+    for k in SLOW:
+        assert after[k] <= 1e-2, (k, after[k])
+    for k in ("ux", "uy", "p"):
+        assert np.isfinite(fa[k]).all()
+        assert np.abs(fa[k]).max() <= 10 * np.abs(fr[k]).max() + 1e-6
+    assert a.totals()["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_batch_subset_step_and_restart(storage):
+    import torch
+    from paper_2511_09422_amd.lbfz import Batch, LbfzError
+    cases = [sweep_case(k, side=64) for k in (3, 4, 5, 6)]
+    full = Batch(cases, storage=storage)
+    part = Batch(cases, storage=storage)
+    full.step(20)
+    part.step(20)
+    part.select([0, 2])
+    full.step(30)
+    part.step(30)
+    for i in (0, 2):
+        ff, fp = full.fields(i), part.fields(i)
+        for k in ff:
+            assert np.array_equal(ff[k], fp[k]), (i, k)
+    # grids 1 and 3 were left behind: no reads, no steps
+    with pytest.raises(LbfzError):
+        part.fields(1)
+    part.select([1])
+    with pytest.raises(LbfzError):
+        part.step(1)
+    # restart them from the full batch's fields at this time level
+    for i in (1, 3):
+        planes = [torch.empty((64, 64), dtype=torch.float32, device="cuda") for _ in range(8)]
+        full.fields_to_device(i, planes)
+        part.restart_fields(i, planes[:6] + [planes[7]])
+    part.select([])
+    part.step(24)
+    full.step(24)
+    torch.cuda.synchronize()
+    for i in range(4):
+        ff, fp = full.fields(i), part.fields(i)
+        for k in SLOW:
+            e = _rel(fp[k], ff[k])
+            assert (e == 0.0) if i in (0, 2) else (e <= 1e-2), (i, k, e)
+        assert part.totals(i)["nonfinite"] == 0
+    full.close()
+    part.close()
