@@ -215,7 +215,8 @@ int lbfz_batch_totals(lbfz_batch* b, int32_t i, lbfz_totals_t* out);
  * batch's time level -- until lbfz_batch_restart_fields gives it one; stepping
  * a selection that holds a stale grid, or reading a stale grid, is
  * LBFZ_EINVAL.  The autotuner times the selected grids.  Synchronises the
- * stream (uploads the work tables); the next step re-captures its graph. */
+ * stream (uploads the work tables); a subset is stepped with plain launches,
+ * the full selection with its captured graph. */
 int lbfz_batch_select(lbfz_batch* b, int32_t n, const int32_t* idx);
 
 /* lbfz_restart_fields for grid i at the batch's time level; clears its stale

@@ -68,8 +68,9 @@ int lbfz_nn_conv(const lbfz_conv_args* a, void* stream);
  * Cin floats), then summed in a fixed order (deterministic). */
 int lbfz_nn_conv_wgrad(const lbfz_conv_args* a, float* part, int nsplit, float* dw, void* stream);
 
-/* Bias gradient db[c] = sum_p dz[p][c] (C <= 256 channels at stride cs), via
- * nblocks partial rows in part (nblocks * C floats). */
+/* Bias gradient db[c] = sum_p dz[p][c] (C <= 256 channels at stride cs, both
+ * multiples of 8), via nblocks partial rows in part (nblocks * C floats),
+ * summed in a fixed order. */
 int lbfz_nn_bias_grad(const void* dz, long P, int cs, int C, float* part, int nblocks, float* db,
                       void* stream);
 

@@ -359,7 +359,11 @@ int lbfz_batch_step(lbfz_batch* b, int64_t nsteps) {
     if (rc != LBFZ_OK) return rc;
     --nsteps;
   }
-  if (nsteps >= kGraphSteps) {
+  // graphs for the full selection only: a subset (the screening's fallback)
+  // changes every stride, and its launches are cheaper than a capture
+  bool all = true;
+  for (char c : b->selected) all = all && c;
+  if (all && nsteps >= kGraphSteps) {
     if (!b->exec) {
       const int rc = build_graph(b);
       if (rc != LBFZ_OK) return rc;
@@ -444,7 +448,8 @@ int lbfz_batch_select(lbfz_batch* b, int32_t n, const int32_t* idx) {
     }
   }
   HIPCHK(hipStreamSynchronize(b->stream));
-  drop_graph(b);
+  // the captured graph (all grids, full work tables) stays valid: subsets
+  // are stepped with plain launches
   return LBFZ_OK;
 }
 

@@ -286,7 +286,25 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(lbfz_conv_args a, float* __r
   }
 }
 
-// dst[i] = sum over s of part[s][i] (fixed order), optionally scaled.
+// 8-channel (16-byte) groups of bf16 activations: pooling, upsampling and the
+// bias gradient move whole groups (channel counts, strides and offsets are
+// multiples of 8, checked by the callers).
+union V8 {
+  uint4 u;
+  bf16 h[8];
+};
+
+__device__ __forceinline__ V8 ld8(const bf16* p) {
+  V8 v;
+  v.u = *reinterpret_cast<const uint4*>(p);
+  return v;
+}
+
+__device__ __forceinline__ void st8(bf16* p, const V8& v) {
+  *reinterpret_cast<uint4*>(p) = v.u;
+}
+
+// dst[i] = sum over s of part[s][i] (fixed order).
 __global__ void k_sum_splits(const float* __restrict__ part, int nsplit, long n,
                              float* __restrict__ dst) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
@@ -297,15 +315,51 @@ __global__ void k_sum_splits(const float* __restrict__ part, int nsplit, long n,
   }
 }
 
-// Bias gradient partials: part[blk][c] = sum over the block's pixels of dz[p][c].
+// dst[i] = sum over s of part[s][i] for a short vector (n small, many
+// splits): one block per element, the splits strided over the threads, then
+// a tree over the block (a fixed order).
+__global__ __launch_bounds__(256) void k_sum_splits_small(const float* __restrict__ part,
+                                                          int nsplit, int n,
+                                                          float* __restrict__ dst) {
+  __shared__ float red[256];
+  const int i = blockIdx.x;
+  float v = 0.0f;
+  for (int s = threadIdx.x; s < nsplit; s += 256) v += part[(size_t)s * n + i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dst[i] = red[0];
+}
+
+// Bias gradient partials: part[blk][c] = sum over the block's pixels of
+// dz[p][c].  Thread t takes the 8-channel group t % G (G = C / 8) of pixels
+// pb + t / G, pb + t / G + 256 / G, ... (16-byte loads); the 256 / G lanes of
+// a group are then summed in LDS in a fixed order.
 __global__ __launch_bounds__(256) void k_bias_grad(const bf16* __restrict__ dz, int P, int cs,
                                                    int C, int pper, float* __restrict__ part) {
-  const int c = threadIdx.x;
-  if (c >= C) return;
+  __shared__ float red[256 * 8];
+  const int G = C / 8, R = 256 / G;
+  const int t = threadIdx.x, g = t % G, r = t / G;
   const int pb = blockIdx.x * pper, pe = min(pb + pper, P);
-  float v = 0.0f;
-  for (int p = pb; p < pe; ++p) v += (float)dz[(size_t)p * cs + c];
-  part[(size_t)blockIdx.x * C + c] = v;
+  float v[8] = {};
+  if (r < R)
+    for (int p = pb + r; p < pe; p += R) {
+      const V8 a = ld8(dz + (size_t)p * cs + 8 * g);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] += (float)a.h[e];
+    }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) red[t * 8 + e] = (r < R) ? v[e] : 0.0f;
+  __syncthreads();
+  if (t < C) {
+    const int gg = t / 8, e = t % 8;
+    float s = 0.0f;
+    for (int rr = 0; rr < R; ++rr) s += red[(rr * G + gg) * 8 + e];
+    part[(size_t)blockIdx.x * C + t] = s;
+  }
 }
 
 // dz = dy where y > 0, else 0 (ReLU backward; y: the activated output).
@@ -323,24 +377,8 @@ __global__ void k_relu_bwd(const bf16* __restrict__ dy, int dy_cs, int dy_co,
 }
 
 // 2x2 max pooling (stride 2) and its gradient (to the first maximum).
-// Pooling and upsampling work on 8-channel (16-byte) groups: thread i takes
-// group i % (C / 8) of output pixel i / (C / 8).  Channel counts, strides and
-// offsets are multiples of 8 (checked by the callers).
-union V8 {
-  uint4 u;
-  bf16 h[8];
-};
-
-__device__ __forceinline__ V8 ld8(const bf16* p) {
-  V8 v;
-  v.u = *reinterpret_cast<const uint4*>(p);
-  return v;
-}
-
-__device__ __forceinline__ void st8(bf16* p, const V8& v) {
-  *reinterpret_cast<uint4*>(p) = v.u;
-}
-
+// Pooling and upsampling: thread i takes group i % (C / 8) of output pixel
+// i / (C / 8).
 // 2x2 max pooling, stride 2.
 __global__ void k_maxpool2(const bf16* __restrict__ x, int x_cs, int x_co, bf16* __restrict__ y,
                            int y_cs, int B, int H, int W, int C) {
@@ -666,13 +704,15 @@ int lbfz_nn_conv_wgrad(const lbfz_conv_args* a, float* part, int nsplit, float* 
 
 int lbfz_nn_bias_grad(const void* dz, long P, int cs, int C, float* part, int nblocks, float* db,
                       void* stream) {
-  if (!dz || !part || !db || C <= 0 || C > 256 || nblocks <= 0) return LBFZ_NN_EINVAL;
+  if (!dz || !part || !db || !groups_ok(C, cs, 0) || C > 256 || nblocks <= 0 || P <= 0 ||
+      P >= (1L << 31))
+    return LBFZ_NN_EINVAL;
   const int pper = (int)((P + nblocks - 1) / nblocks);
   hipLaunchKernelGGL(k_bias_grad, dim3(nblocks), dim3(256), 0, (hipStream_t)stream,
                      static_cast<const bf16*>(dz), (int)P, cs, C, pper, part);
   if (hipGetLastError() != hipSuccess) return LBFZ_NN_EHIP;
-  hipLaunchKernelGGL(k_sum_splits, dim3(1), dim3(256), 0, (hipStream_t)stream, part, nblocks,
-                     (long)C, db);
+  hipLaunchKernelGGL(k_sum_splits_small, dim3(C), dim3(256), 0, (hipStream_t)stream, part,
+                     nblocks, C, db);
   HCHK();
 }
 

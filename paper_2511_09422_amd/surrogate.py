@@ -32,7 +32,8 @@ import numpy as np
 from . import lbfz
 
 NF = 6           # predicted fields: phi, f_l, T, C, u_x, u_y
-NIN = 8          # input planes: the six, u_z (zero in 2D) and the pressure p
+NIN = 6          # input planes: phi, f_l, T, C, u_x, u_y (the predicted fields)
+NEXP = 8         # planes exported per grid by the screening: the six, u_z, p
 CIN0 = 16        # padded input channels
 HEAD = 8         # padded head channels
 FIELD_NAMES = ("phi", "fl", "T", "C", "ux", "uy")
@@ -515,7 +516,7 @@ def predict(net: UNet, snaps, norm: Normaliser, pairs, out):
 
 
 # ---------------------------------------------------------------- screening
-SOLUTE_TOL = 5e-4  # screening: largest accepted relative drift of sum C
+SOLUTE_TOL = None  # screening: largest accepted relative drift of sum C (None: not checked)
 
 
 def mass_residual(sum_phi_b, sum_phi_a, sum_fl_b, sum_fl_a, n: int, ratio: float) -> float:
@@ -538,12 +539,15 @@ def solute_drift(sum_c_b, sum_c_a) -> float:
 
 def check(sums_before, sums_after, n: int, ratio: float, mass_tol: float = MASS_TOL,
           solute_tol: float = SOLUTE_TOL):
-    """Accept a prediction (True) or send its grid to the LB (False).
+    """Accept a prediction (True) or send its grid to the LB (False): the
+    phase-field mass residual within mass_tol and, when solute_tol is given,
+    the solute drift within it; a non-finite prediction is never accepted.
     sums_*: per-field sums (phi, f_l, T, C, ...) of the grid before the
     stride and of the prediction.  Returns (accept, mass residual, drift)."""
     r = mass_residual(sums_before[0], sums_after[0], sums_before[1], sums_after[1], n, ratio)
     d = solute_drift(sums_before[3], sums_after[3])
-    ok = bool(np.isfinite(r) and np.isfinite(d) and r <= mass_tol and d <= solute_tol)
+    ok = bool(np.all(np.isfinite(sums_after)) and r <= mass_tol and
+              (solute_tol is None or d <= solute_tol))
     return ok, r, d
 
 
@@ -567,9 +571,9 @@ class Screener:
         self.ratios = [1.0 - c["rho_s"] / c["rho_l"] for c in batch.cfgs]
         self.mass_tol, self.solute_tol = mass_tol, solute_tol
         f = dict(dtype=torch.float32, device=net.dev)
-        self.before = torch.zeros((self.n, NIN, S, S), **f)
+        self.before = torch.zeros((self.n, NEXP, S, S), **f)
         self.pred = torch.zeros((self.n, NF, S, S), **f)
-        self.sums_b = torch.zeros(self.n * NIN, dtype=torch.float64, device=net.dev)
+        self.sums_b = torch.zeros(self.n * NEXP, dtype=torch.float64, device=net.dev)
         self.sums_a = torch.zeros(self.n * NF, dtype=torch.float64, device=net.dev)
         self.time = 0  # LB steps screened so far (the batch's own counter only
         # moves when some grid falls back to the LB)
@@ -580,7 +584,7 @@ class Screener:
         (accept, mass residual, solute drift) of the check."""
         L, net, S, st = nnlib(), self.net, self.S, self.net.st
         for i in range(self.n):
-            self.batch.fields_to_device(i, [self.before[i, f] for f in range(NIN)])
+            self.batch.fields_to_device(i, [self.before[i, f] for f in range(NEXP)])
         for i in range(self.n):
             _ck(L.lbfz_nn_pack_fields(_p(self.before[i]), NIN, S, S, 0, 0, S,
                                       _p(self.norm.in_shift), _p(self.norm.in_scale),
@@ -591,11 +595,11 @@ class Screener:
                                       _p(self.norm.d_shift), _p(self.norm.d_scale),
                                       _p(self.norm.resid), _p(self.pred[i]), i, st),
                 "apply_delta")
-        _ck(L.lbfz_nn_plane_sums(_p(self.before), self.n * NIN, S * S, S * S, _p(self.sums_b),
+        _ck(L.lbfz_nn_plane_sums(_p(self.before), self.n * NEXP, S * S, S * S, _p(self.sums_b),
                                  st), "plane_sums")
         _ck(L.lbfz_nn_plane_sums(_p(self.pred), self.n * NF, S * S, S * S, _p(self.sums_a),
                                  st), "plane_sums")
-        sb = self.sums_b.cpu().numpy().reshape(self.n, NIN)
+        sb = self.sums_b.cpu().numpy().reshape(self.n, NEXP)
         sa = self.sums_a.cpu().numpy().reshape(self.n, NF)
         return [check(sb[i], sa[i], S * S, self.ratios[i], self.mass_tol, self.solute_tol)
                 for i in range(self.n)]
@@ -615,7 +619,7 @@ class Screener:
         for i in range(self.n):
             if acc[i]:
                 self.batch.restart_fields(
-                    i, [self.pred[i, f] for f in range(NF)] + [self.before[i, NIN - 1]])
+                    i, [self.pred[i, f] for f in range(NF)] + [self.before[i, NEXP - 1]])
         self.batch.select([])
         return acc, res
 
