@@ -33,6 +33,20 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;  // LDS rows padded by 16 B
 
+// Buffer descriptor over `bytes` bytes at `base` (raw 32-bit data, no
+// swizzle): loads take a 32-bit lane byte offset, and offsets at or past
+// `bytes` read zero.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr uint32_t kOut = 0x80000000u;  // an offset past every tensor (< 2^31 bytes)
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ uint4 ld16B(rsrc_t r, uint32_t off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+  return __builtin_bit_cast(uint4, v);
+}
+
 __device__ __forceinline__ void tap_offset(int taps, int t, int sign, int& dy, int& dx) {
   if (taps == 1) {
     dy = dx = 0;
@@ -88,14 +102,15 @@ __device__ __forceinline__ int acc_row(int r, int lane) {
 constexpr int KS = 32, LDS_K = KS + 8;      // LDS rows padded by 16 B
 constexpr int CPR = KS / 8, RPP = 256 / CPR;   // 16-byte chunks per row, rows per pass
 
-template <int FM, int FN, int WGM, int WGN>
+template <int FM, int FN, int WGM, int WGN, bool UP>
 __global__ __launch_bounds__(256) void k_conv(lbfz_conv_args a) {
   static_assert(WGM * WGN == 4, "4 waves");
   constexpr int BM_ = 32 * FM * WGM, BN_ = 32 * FN * WGN;
   // 16-byte chunks per thread and slice (B: the last pass may be partial)
   constexpr int AR = BM_ / RPP, BR = (BN_ + RPP - 1) / RPP;
   constexpr int A_EL = BM_ * LDS_K, B_EL = BN_ * LDS_K;
-  constexpr int O_EL = BM_ * (BN_ + 8);  // the bf16 output tile, staged for the stores
+  constexpr int OS = BN_;         // row stride of the bf16 output tile staged for the stores
+  constexpr int O_EL = BM_ * OS;
   constexpr int SM_EL = (A_EL + B_EL) > O_EL ? (A_EL + B_EL) : O_EL;
   __shared__ __align__(16) bf16 smem[SM_EL];
   bf16 (*As)[LDS_K] = reinterpret_cast<bf16 (*)[LDS_K]>(smem);
@@ -107,64 +122,108 @@ __global__ __launch_bounds__(256) void k_conv(lbfz_conv_args a) {
   const int m0 = bx * BM_, n0 = blockIdx.y * BN_;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave % WGM) * 32 * FM, wn = (wave / WGM) * 32 * FN;
-  const bf16* __restrict__ in = static_cast<const bf16*>(a.in);
-  const bf16* __restrict__ wt = static_cast<const bf16*>(a.w);
+  // operands through buffer descriptors: 32-bit byte offsets, and an offset
+  // past the end (kOut) reads zeros -- the halo of the image and the K tail
+  // need no branches (the host keeps both tensors under 2^31 bytes)
+  const uint32_t in_bytes = (uint32_t)((UP ? (size_t)M / 4 : (size_t)M) * a.in_cs * 2);
+  const rsrc_t rin = make_rsrc(a.in, in_bytes);
+  const rsrc_t rw = make_rsrc(a.w, (uint32_t)((size_t)a.N * K * 2));
   const int q = tid % CPR, r0 = tid / CPR;
-  int pp[AR], py[AR], px[AR];
+  // per A row (pixel): the byte offset of its own pixel (UP: of its image in
+  // the half-resolution tensor) and the set of taps whose source lies inside
+  // the image; UP also keeps the half-resolution row / column offsets of the
+  // three source rows and columns
+  const int cs2 = a.in_cs * 2;
+  uint32_t rowb[AR], tapok[AR];
+  int ysh[UP ? AR : 1][3], xsh[UP ? AR : 1][3];
 #pragma unroll
   for (int j = 0; j < AR; ++j) {
     const int p = m0 + r0 + RPP * j;
-    pp[j] = p < M ? p : -1;
-    const int rem = p % (a.H * a.W);
-    py[j] = rem / a.W;
-    px[j] = rem - py[j] * a.W;
-  }
-  uint4 ra[AR], rb[BR];
-  auto gload = [&](int k0) {
-    const int k = k0 + 8 * q;
-    const bool kok = k < K;
-    int t = 0, c = 0;
-    if (kok) {
-      t = k / a.Cin;
-      c = k - t * a.Cin;
-    }
-    int dy, dx;
-    tap_offset(a.taps, t, a.sign, dy, dx);
+    const int img = p / (a.H * a.W), rem = p - img * (a.H * a.W);
+    const int py = rem / a.W, px = rem - py * a.W;
+    uint32_t ok = 0;
+    if (p < M) {
+      if (a.taps == 1) {
+        ok = 1;
+      } else {
 #pragma unroll
-    for (int j = 0; j < AR; ++j) {
-      const int yy = py[j] + dy, xx = px[j] + dx;
-      ra[j] = make_uint4(0, 0, 0, 0);
-      if (kok && pp[j] >= 0 && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
-        // source pixel: the shifted one, or under upsampling its parent in
-        // the half-resolution image (image base pp - py W - px, a multiple of 4)
-        const int src = a.up ? ((pp[j] - py[j] * a.W - px[j]) >> 2) + (yy >> 1) * (a.W >> 1) +
-                                   (xx >> 1)
-                             : pp[j] + dy * a.W + dx;
-        ra[j] = *reinterpret_cast<const uint4*>(in + (size_t)src * a.in_cs + a.in_co + c);
+        for (int t = 0; t < 9; ++t) {
+          const int yy = py + a.sign * (t / 3 - 1), xx = px + a.sign * (t % 3 - 1);
+          if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) ok |= 1u << t;
+        }
       }
     }
+    tapok[j] = ok;
+    if constexpr (UP) {
+      rowb[j] = (uint32_t)(img * (a.H >> 1) * (a.W >> 1)) * cs2;
 #pragma unroll
-    for (int j = 0; j < BR; ++j) {
-      const int rr = r0 + RPP * j, n = n0 + rr;
-      rb[j] = make_uint4(0, 0, 0, 0);
-      if (kok && rr < BN_ && n < a.N) rb[j] = *reinterpret_cast<const uint4*>(wt + (size_t)n * K + k);
+      for (int d = 0; d < 3; ++d) {
+        ysh[j][d] = ((py + d - 1) >> 1) * (a.W >> 1) * cs2;
+        xsh[j][d] = ((px + d - 1) >> 1) * cs2;
+      }
+    } else {
+      rowb[j] = (uint32_t)p * cs2;
     }
+  }
+  // this thread's K position k = k0 + 8 q as (tap t, channel c), advanced by
+  // KS per slice without a division
+  int t = (8 * q) / a.Cin, c = 8 * q - t * a.Cin;
+  // weight rows of this thread (B operand) and their byte offsets at k
+  uint32_t wb[BR];
+  bool wok[BR];
+#pragma unroll
+  for (int j = 0; j < BR; ++j) {
+    const int rr = r0 + RPP * j, n = n0 + rr;
+    wok[j] = rr < BN_ && n < a.N;
+    wb[j] = (uint32_t)(n * K + 8 * q) * 2;
+  }
+  const uint32_t co2 = (uint32_t)a.in_co * 2;
+  auto gload = [&](uint4 (&ra)[AR], uint4 (&rb)[BR]) {
+    const bool kok = t < a.taps;
+    const int ti = a.taps == 1 ? 4 : t;   // the centre tap for 1 x 1
+    const int dyi = ti >= 6 ? 2 : (ti >= 3 ? 1 : 0), dxi = ti - 3 * dyi;
+    const uint32_t cb = co2 + (uint32_t)c * 2;
+    // non-UP: the tap's shift of the pixel index, in bytes
+    const int dsh = (a.sign * (dyi - 1) * a.W + a.sign * (dxi - 1)) * cs2;
+#pragma unroll
+    for (int j = 0; j < AR; ++j) {
+      uint32_t off;
+      if constexpr (UP)
+        off = rowb[j] + ysh[j][dyi] + xsh[j][dxi] + cb;
+      else
+        off = rowb[j] + dsh + cb;
+      const bool ok = kok && ((tapok[j] >> (a.taps == 1 ? 0 : t)) & 1u);
+      ra[j] = ld16B(rin, ok ? off : kOut);
+    }
+#pragma unroll
+    for (int j = 0; j < BR; ++j) rb[j] = ld16B(rw, (kok && wok[j]) ? wb[j] : kOut);
+  };
+  // advance (t, c) and the weight offsets by one slice
+  auto advance = [&]() {
+    c += KS;
+    while (c >= a.Cin) {
+      c -= a.Cin;
+      ++t;
+    }
+#pragma unroll
+    for (int j = 0; j < BR; ++j) wb[j] += KS * 2;
   };
   f32x16 acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
-  gload(0);
-  for (int k0 = 0; k0 < K; k0 += KS) {
-    __syncthreads();  // the previous slice's fragments have been read
+  // one slice: registers -> LDS (after every wave has read the previous one)
+  auto stage = [&](const uint4 (&ra)[AR], const uint4 (&rb)[BR]) {
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < AR; ++j) *reinterpret_cast<uint4*>(&As[r0 + RPP * j][8 * q]) = ra[j];
 #pragma unroll
     for (int j = 0; j < BR; ++j)
       if (r0 + RPP * j < BN_) *reinterpret_cast<uint4*>(&Bs[r0 + RPP * j][8 * q]) = rb[j];
     __syncthreads();
-    if (k0 + KS < K) gload(k0 + KS);
+  };
+  auto compute = [&]() {
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 16) {
       bf16x8 fa[FM], fb[FN];
@@ -181,11 +240,20 @@ __global__ __launch_bounds__(256) void k_conv(lbfz_conv_args a) {
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
+  };
+  uint4 ra[AR], rb[BR];
+  gload(ra, rb);
+  for (int k0 = 0; k0 < K; k0 += KS) {
+    stage(ra, rb);
+    if (k0 + KS < K) {
+      advance();
+      gload(ra, rb);
+    }
+    compute();
   }
   const float* bias = a.bias;
   if (!a.out_f32 && a.N % 8 == 0 && a.out_cs % 8 == 0 && a.out_co % 8 == 0) {
     // stage the bf16 tile in LDS, then write whole 16-byte channel groups
-    constexpr int OS = BN_ + 8;
     bf16* Os = smem;
     __syncthreads();
 #pragma unroll
@@ -233,6 +301,183 @@ __global__ __launch_bounds__(256) void k_conv(lbfz_conv_args a) {
           static_cast<bf16*>(a.out)[o] = (bf16)v;
       }
     }
+  }
+}
+
+// Direct 3 x 3 convolution (forward, data gradient, and the forward through
+// 2x upsampling): a block computes a TH x TW = 4 x 64 tile of output pixels of
+// one image for BN = 32 FN output channels.  Per input-channel chunk of CC =
+// 32 it stages the (TH + 2) x (TW + 2) haloed input tile and the chunk's
+// weights [n][tap][c] in LDS once, then every wave (one output row, 2 x FN
+// accumulators of 32 x 32) runs the nine taps' MFMAs reading its A fragments
+// from the tile at the tap's shift -- each input byte is loaded from memory
+// about 1.6 times instead of nine (the implicit GEMM above re-gathers it per
+// tap).  Tap shifts are compile-time (SIGN), so fragment addresses are one
+// per-lane base plus immediates.  The next chunk's loads are issued before
+// the current chunk's MFMAs.
+constexpr int TW = 64, TH = 4, HWD = TW + 2, HHT = TH + 2, CC = 32, HPS = CC + 8;
+
+template <int FN, bool UP, int SIGN>
+__global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
+  constexpr int BN_ = 32 * FN;
+  constexpr int H_EL = HHT * HWD * HPS;  // haloed input tile [pixel][c]
+  constexpr int W_EL = BN_ * 9 * HPS;    // weights [n][tap][c]
+  constexpr int O_EL = TH * TW * BN_;    // bf16 output tile for the stores
+  constexpr int SM_EL = (H_EL + W_EL) > O_EL ? (H_EL + W_EL) : O_EL;
+  constexpr int HE = HHT * HWD * 4, HJ = (HE + 255) / 256;  // halo 16-byte chunks
+  constexpr int WE = BN_ * 9 * 4, WJ = (WE + 255) / 256;    // weight 16-byte chunks
+  __shared__ __align__(16) bf16 smem[SM_EL];
+  bf16* Hs = smem;
+  bf16* Ws = smem + H_EL;
+  const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + TH - 1) / TH;
+  const int nt = gridDim.x;
+  int bx = blockIdx.x;
+  if ((nt & 7) == 0) bx = (bx & 7) * (nt >> 3) + (bx >> 3);  // neighbouring tiles on one XCD
+  const int b = bx / (tiles_y * tiles_x), rt = bx - b * (tiles_y * tiles_x);
+  const int y0 = (rt / tiles_x) * TH, x0 = (rt % tiles_x) * TW;
+  const int n0 = blockIdx.y * BN_;
+  const int M = a.B * a.H * a.W, K = 9 * a.Cin;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t in_bytes = (uint32_t)((UP ? (size_t)M / 4 : (size_t)M) * a.in_cs * 2);
+  const rsrc_t rin = make_rsrc(a.in, in_bytes);
+  const rsrc_t rw = make_rsrc(a.w, (uint32_t)((size_t)a.N * K * 2));
+  // this thread's halo chunks: byte offset at channel 0 of the layer input
+  // (kOut outside the image) and the chunk's channel offset q * 8
+  uint32_t hoff[HJ];
+  int hq[HJ];
+#pragma unroll
+  for (int j = 0; j < HJ; ++j) {
+    const int e = tid + 256 * j, hp = e >> 2;
+    hq[j] = 8 * (e & 3);
+    const int yy = y0 + hp / HWD - 1, xx = x0 + hp % HWD - 1;
+    hoff[j] = kOut;
+    if (e < HE && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+      const int src = UP ? (b * (a.H >> 1) + (yy >> 1)) * (a.W >> 1) + (xx >> 1)
+                         : (b * a.H + yy) * a.W + xx;
+      hoff[j] = ((uint32_t)src * a.in_cs + a.in_co + hq[j]) * 2;
+    }
+  }
+  uint32_t woff[WJ];
+  int wq[WJ];
+#pragma unroll
+  for (int j = 0; j < WJ; ++j) {
+    const int e = tid + 256 * j, n = e / 36, rem = e - n * 36;
+    wq[j] = 8 * (rem & 3);
+    woff[j] = (e < WE && n0 + n < a.N) ? ((uint32_t)(n0 + n) * K + (rem >> 2) * a.Cin + wq[j]) * 2
+                                      : kOut;
+  }
+  uint4 hv[HJ], wv[WJ];
+  auto gload = [&](int c0) {
+#pragma unroll
+    for (int j = 0; j < HJ; ++j)
+      hv[j] = ld16B(rin, (hoff[j] != kOut && c0 + hq[j] < a.Cin) ? hoff[j] + 2 * c0 : kOut);
+#pragma unroll
+    for (int j = 0; j < WJ; ++j)
+      wv[j] = ld16B(rw, (woff[j] != kOut && c0 + wq[j] < a.Cin) ? woff[j] + 2 * c0 : kOut);
+  };
+  f32x16 acc[2][FN];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+  // fragment bases: A at halo pixel (wave, lane % 32) -- the (-1, -1) shift of
+  // output pixel (wave, lane % 32) -- and B at weight row lane % 32; the k
+  // half 8 (lane / 32)
+  const bf16* abase = Hs + (wave * HWD + (lane & 31)) * HPS + 8 * (lane >> 5);
+  const bf16* bbase = Ws + (lane & 31) * 9 * HPS + 8 * (lane >> 5);
+  gload(0);
+  for (int c0 = 0; c0 < a.Cin; c0 += CC) {
+    __syncthreads();  // the previous chunk's fragments have been read
+#pragma unroll
+    for (int j = 0; j < HJ; ++j) {
+      const int e = tid + 256 * j;
+      if (e < HE) *reinterpret_cast<uint4*>(Hs + (e >> 2) * HPS + 8 * (e & 3)) = hv[j];
+    }
+#pragma unroll
+    for (int j = 0; j < WJ; ++j) {
+      const int e = tid + 256 * j;
+      if (e < WE) {
+        const int n = e / 36, rem = e - n * 36;
+        *reinterpret_cast<uint4*>(Ws + (n * 9 + (rem >> 2)) * HPS + 8 * (rem & 3)) = wv[j];
+      }
+    }
+    __syncthreads();
+    if (c0 + CC < a.Cin) gload(c0 + CC);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      // tap t reads input pixel (y + SIGN (t / 3 - 1), x + SIGN (t % 3 - 1));
+      // relative to the (-1, -1) base that is row 1 + SIGN (t / 3 - 1), column
+      // 1 + SIGN (t % 3 - 1) of the halo tile
+      const int hy = 1 + SIGN * (t / 3 - 1), hx = 1 + SIGN * (t % 3 - 1);
+#pragma unroll
+      for (int kk = 0; kk < CC; kk += 16) {
+        bf16x8 fa[2], fb[FN];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          fa[i] = *reinterpret_cast<const bf16x8*>(abase + (hy * HWD + hx + 32 * i) * HPS + kk);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          fb[j] = *reinterpret_cast<const bf16x8*>(bbase + (32 * j * 9 + t) * HPS + kk);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+  // epilogue: output pixel (y0 + wave, x0 + 32 i + row) and channel
+  // n0 + 32 j + lane % 32 of accumulator element r (row = acc_row(r, lane))
+  const float* bias = a.bias;
+  const int y = y0 + wave;
+  if (!a.out_f32 && a.N % 8 == 0 && a.out_cs % 8 == 0 && a.out_co % 8 == 0) {
+    bf16* Os = smem;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = 32 * j + (lane & 31);
+      const float bv = (bias && n0 + col < a.N) ? bias[n0 + col] : 0.0f;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          float v = acc[i][j][r] + bv;
+          if (a.relu) v = fmaxf(v, 0.0f);
+          Os[(wave * TW + 32 * i + acc_row(r, lane)) * BN_ + col] = (bf16)v;
+        }
+    }
+    __syncthreads();
+    constexpr int GPR = BN_ / 8;
+    for (int g = tid; g < TH * TW * GPR; g += 256) {
+      const int m = g / GPR, cg = g - m * GPR;
+      const int yy = y0 + m / TW, xx = x0 + m % TW, cn = n0 + 8 * cg;
+      if (yy < a.H && xx < a.W && cn < a.N)
+        *reinterpret_cast<uint4*>(static_cast<bf16*>(a.out) +
+                                  ((size_t)(b * a.H + yy) * a.W + xx) * a.out_cs + a.out_co + cn) =
+            *reinterpret_cast<const uint4*>(&Os[m * BN_ + 8 * cg]);
+    }
+    return;
+  }
+  if (y >= a.H) return;
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int cn = n0 + 32 * j + (lane & 31);
+    if (cn >= a.N) continue;
+    const float bv = bias ? bias[cn] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int x = x0 + 32 * i + acc_row(r, lane);
+        if (x >= a.W) continue;
+        float v = acc[i][j][r] + bv;
+        if (a.relu) v = fmaxf(v, 0.0f);
+        const size_t o = ((size_t)(b * a.H + y) * a.W + x) * a.out_cs + a.out_co + cn;
+        if (a.out_f32)
+          static_cast<float*>(a.out)[o] = v;
+        else
+          static_cast<bf16*>(a.out)[o] = (bf16)v;
+      }
   }
 }
 
@@ -666,19 +911,54 @@ int lbfz_nn_conv(const lbfz_conv_args* a, void* stream) {
   if (!conv_ok(a) || !a->out || (a->sign != 1 && a->sign != -1) || (a->up && a->sign != 1))
     return LBFZ_NN_EINVAL;
   const long M = (long)a->B * a->H * a->W;
-  if (M >= (1L << 30)) return LBFZ_NN_EINVAL;
-  // tile shape by output width: 128 x 128 (N a multiple of 128), 256 x 64
-  // (a multiple of 64), else 256 x 32 (column blocks of 32)
+  // operands are addressed with 32-bit byte offsets below 2^31
+  if (M >= (1L << 30) || (a->up ? M / 4 : M) * a->in_cs * 2 >= (1L << 31) ||
+      (long)a->N * a->taps * a->Cin * 2 >= (1L << 31))
+    return LBFZ_NN_EINVAL;
   const hipStream_t st = (hipStream_t)stream;
+  if (a->taps == 9) {
+    // direct convolution over 4 x 64 pixel tiles, 64 output channels per
+    // block when N is a multiple of 64, else 32
+    const long tiles = (long)a->B * ((a->H + TH - 1) / TH) * ((a->W + TW - 1) / TW);
+    if (a->N % 64 == 0) {
+      const dim3 grid((unsigned)tiles, (unsigned)(a->N / 64));
+      if (a->up)
+        hipLaunchKernelGGL((k_conv_direct<2, true, 1>), grid, dim3(256), 0, st, *a);
+      else if (a->sign == 1)
+        hipLaunchKernelGGL((k_conv_direct<2, false, 1>), grid, dim3(256), 0, st, *a);
+      else
+        hipLaunchKernelGGL((k_conv_direct<2, false, -1>), grid, dim3(256), 0, st, *a);
+    } else {
+      const dim3 grid((unsigned)tiles, (unsigned)((a->N + 31) / 32));
+      if (a->up)
+        hipLaunchKernelGGL((k_conv_direct<1, true, 1>), grid, dim3(256), 0, st, *a);
+      else if (a->sign == 1)
+        hipLaunchKernelGGL((k_conv_direct<1, false, 1>), grid, dim3(256), 0, st, *a);
+      else
+        hipLaunchKernelGGL((k_conv_direct<1, false, -1>), grid, dim3(256), 0, st, *a);
+    }
+    HCHK();
+  }
+  // 1 x 1: implicit GEMM, tile shape by output width: 128 x 128 (N a
+  // multiple of 128), 256 x 64 (a multiple of 64), else 256 x 32
   if (a->N % 128 == 0) {
     const dim3 grid((unsigned)((M + 127) / 128), (unsigned)(a->N / 128));
-    hipLaunchKernelGGL((k_conv<2, 2, 2, 2>), grid, dim3(256), 0, st, *a);
+    if (a->up)
+      hipLaunchKernelGGL((k_conv<2, 2, 2, 2, true>), grid, dim3(256), 0, st, *a);
+    else
+      hipLaunchKernelGGL((k_conv<2, 2, 2, 2, false>), grid, dim3(256), 0, st, *a);
   } else if (a->N % 64 == 0) {
     const dim3 grid((unsigned)((M + 255) / 256), (unsigned)(a->N / 64));
-    hipLaunchKernelGGL((k_conv<2, 2, 4, 1>), grid, dim3(256), 0, st, *a);
+    if (a->up)
+      hipLaunchKernelGGL((k_conv<2, 2, 4, 1, true>), grid, dim3(256), 0, st, *a);
+    else
+      hipLaunchKernelGGL((k_conv<2, 2, 4, 1, false>), grid, dim3(256), 0, st, *a);
   } else {
     const dim3 grid((unsigned)((M + 255) / 256), (unsigned)((a->N + 31) / 32));
-    hipLaunchKernelGGL((k_conv<2, 1, 4, 1>), grid, dim3(256), 0, st, *a);
+    if (a->up)
+      hipLaunchKernelGGL((k_conv<2, 1, 4, 1, true>), grid, dim3(256), 0, st, *a);
+    else
+      hipLaunchKernelGGL((k_conv<2, 1, 4, 1, false>), grid, dim3(256), 0, st, *a);
   }
   HCHK();
 }
