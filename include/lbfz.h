@@ -209,6 +209,13 @@ int lbfz_batch_fields(lbfz_batch* b, int32_t i, uint32_t field_mask, float* cons
                       int dst_is_device);
 int lbfz_batch_totals(lbfz_batch* b, int32_t i, lbfz_totals_t* out);
 
+/* The fields of every grid into one device buffer (asynchronous): grid i's
+ * fields of the set bits of field_mask (bit order), one plane of its N
+ * values after the other, from d_dst + i * case_stride (floats; case_stride
+ * >= the number of set bits times the largest N).  LBFZ_EINVAL if a grid is
+ * stale. */
+int lbfz_batch_fields_all(lbfz_batch* b, uint32_t field_mask, float* d_dst, int64_t case_stride);
+
 /* Subset stepping (the LB fallback of a screened sweep): later steps advance
  * only the n grids listed in idx (n = 0: all grids again).  A grid left out
  * while the others step becomes stale -- its state no longer matches the
@@ -222,6 +229,11 @@ int lbfz_batch_select(lbfz_batch* b, int32_t n, const int32_t* idx);
 /* lbfz_restart_fields for grid i at the batch's time level; clears its stale
  * mark.  Asynchronous. */
 int lbfz_batch_restart_fields(lbfz_batch* b, int32_t i, const float* const* d_fields);
+
+/* The same for the n grids idx[0 .. n-1]: field m of grid i at d_fields[m] +
+ * i * case_stride[m] (floats; m < 7, order as lbfz_restart_fields). */
+int lbfz_batch_restart_many(lbfz_batch* b, int32_t n, const int32_t* idx,
+                            const float* const* d_fields, const int64_t* case_stride);
 
 /* Release the grids, graphs and the capture stream (not the workspace). */
 void lbfz_batch_destroy(lbfz_batch* b);

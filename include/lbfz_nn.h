@@ -110,6 +110,21 @@ int lbfz_nn_adam(float* w, const float* g, float* m, float* v, void* wb, long n,
 
 int lbfz_nn_to_bf16(const float* src, void* dst, long n, void* stream);
 
+/* Network input from nimg whole S x S grids at once: image i's nf FP32
+ * planes at planes + i * img_stride (each S * S values), normalised as in
+ * lbfz_nn_pack_fields, into images 0 .. nimg - 1 of dst (cs channels, a
+ * multiple of 8). */
+int lbfz_nn_pack_images(const float* planes, int nimg, long img_stride, int nf, int S,
+                        const float* shift, const float* scale, void* dst, int cs, void* stream);
+
+/* Predictions of nimg whole grids (as lbfz_nn_apply_delta for each image):
+ * before / pred planes of grid i at before + i * before_stride and pred + i *
+ * pred_stride. */
+int lbfz_nn_apply_images(const float* out, int out_cs, const float* before, int nimg,
+                         long before_stride, int nf, int S, const float* shift,
+                         const float* scale, const float* resid, float* pred, long pred_stride,
+                         void* stream);
+
 /* out[k] = sum of the n FP32 values of plane k (at src + k * stride), k <
  * nplanes, accumulated in FP64 in a fixed order (the per-grid sums of the
  * screening check). */

@@ -421,6 +421,27 @@ int lbfz_batch_fields(lbfz_batch* b, int32_t i, uint32_t field_mask, float* cons
   return lbfz_fields(b->h[i], field_mask, dst, dst_is_device);
 }
 
+int lbfz_batch_fields_all(lbfz_batch* b, uint32_t field_mask, float* d_dst, int64_t case_stride) {
+  if (!b || !d_dst || field_mask == 0 || (field_mask >> 9) != 0) return LBFZ_EINVAL;
+  int nf = 0;
+  for (int k = 0; k < 9; ++k) nf += (field_mask >> k) & 1;
+  for (int i = 0; i < b->ncases; ++i) {
+    const int64_t N = (int64_t)b->h[i]->kp.N;
+    if (b->stale[i] || case_stride < nf * N) return LBFZ_EINVAL;
+  }
+  sync_handles(b);
+  for (int i = 0; i < b->ncases; ++i) {
+    const int64_t N = (int64_t)b->h[i]->kp.N;
+    float* dst[9] = {};
+    int r = 0;
+    for (int k = 0; k < 9; ++k)
+      if ((field_mask >> k) & 1) dst[k] = d_dst + i * case_stride + (r++) * N;
+    const int rc = lbfz_fields(b->h[i], field_mask, dst, 1);
+    if (rc != LBFZ_OK) return rc;
+  }
+  return LBFZ_OK;
+}
+
 int lbfz_batch_totals(lbfz_batch* b, int32_t i, lbfz_totals_t* out) {
   if (!b || i < 0 || i >= b->ncases || b->stale[i]) return LBFZ_EINVAL;
   sync_handles(b);
@@ -450,6 +471,22 @@ int lbfz_batch_select(lbfz_batch* b, int32_t n, const int32_t* idx) {
   HIPCHK(hipStreamSynchronize(b->stream));
   // the captured graph (all grids, full work tables) stays valid: subsets
   // are stepped with plain launches
+  return LBFZ_OK;
+}
+
+int lbfz_batch_restart_many(lbfz_batch* b, int32_t n, const int32_t* idx,
+                            const float* const* d_fields, const int64_t* case_stride) {
+  if (!b || n < 0 || (n > 0 && (!idx || !d_fields || !case_stride))) return LBFZ_EINVAL;
+  for (int k = 0; k < n; ++k)
+    if (idx[k] < 0 || idx[k] >= b->ncases) return LBFZ_EINVAL;
+  sync_handles(b);
+  for (int k = 0; k < n; ++k) {
+    const float* f[7];
+    for (int m = 0; m < 7; ++m) f[m] = d_fields[m] + idx[k] * case_stride[m];
+    const int rc = lbfz_restart_fields(b->h[idx[k]], f);
+    if (rc != LBFZ_OK) return rc;
+    b->stale[idx[k]] = 0;
+  }
   return LBFZ_OK;
 }
 

@@ -885,6 +885,50 @@ __global__ void k_apply_delta(const float* __restrict__ out, int out_cs,
                               out[((long)b * n + i) * out_cs + f] / scale[f] + shift[f];
 }
 
+// Whole S x S grids as network input, nimg at once: image i's nf FP32 planes
+// at planes + i * img_stride (plane stride S * S), normalised, into image i
+// of the bf16 NHWC tensor dst (cs channels, nf .. cs - 1 zero); one thread
+// per pixel writes its cs channels as 16-byte groups.
+__global__ void k_pack_images(const float* __restrict__ planes, int nimg, long img_stride, int nf,
+                              int S, const float* __restrict__ shift,
+                              const float* __restrict__ scale, bf16* __restrict__ dst, int cs) {
+  const long npx = (long)S * S, n = npx * nimg;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    const long img = i / npx, px = i - img * npx;
+    const float* src = planes + img * img_stride + px;
+    bf16* d = dst + i * cs;
+    for (int g = 0; g < cs; g += 8) {
+      V8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int f = g + e;
+        v.h[e] = f < nf ? (bf16)((src[(long)f * npx] - shift[f]) * scale[f]) : (bf16)0.0f;
+      }
+      st8(d + g, v);
+    }
+  }
+}
+
+// Predictions of nimg whole grids from the network output: pred_i[f] =
+// resid[f] before_i[f] + out_i[f] / scale[f] + shift[f] (planes of S * S at
+// before + i * before_stride, pred + i * pred_stride).
+__global__ void k_apply_images(const float* __restrict__ out, int out_cs,
+                               const float* __restrict__ before, int nimg, long before_stride,
+                               int nf, int S, const float* __restrict__ shift,
+                               const float* __restrict__ scale, const float* __restrict__ resid,
+                               float* __restrict__ pred, long pred_stride) {
+  const long npx = (long)S * S, n = npx * nimg;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    const long img = i / npx, px = i - img * npx;
+    const float* o = out + i * out_cs;
+    const float* bsrc = before + img * before_stride + px;
+    float* p = pred + img * pred_stride + px;
+    for (int f = 0; f < nf; ++f) p[(long)f * npx] = resid[f] * bsrc[(long)f * npx] + o[f] / scale[f] + shift[f];
+  }
+}
+
 int grid_for(long n) { return (int)std::min<long>((n + 255) / 256, 16384); }
 
 // 8-channel groups: C, the channel stride and the offset multiples of 8
@@ -1065,6 +1109,31 @@ int lbfz_nn_mse(const float* out, int out_cs, const float* tgt, long P, int C, c
                      C, wch, static_cast<bf16*>(dout), part);
   if (hipGetLastError() != hipSuccess) return LBFZ_NN_EHIP;
   hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, (hipStream_t)stream, part, nblocks, loss);
+  HCHK();
+}
+
+int lbfz_nn_pack_images(const float* planes, int nimg, long img_stride, int nf, int S,
+                        const float* shift, const float* scale, void* dst, int cs, void* stream) {
+  if (!planes || !shift || !scale || !dst || nimg <= 0 || S <= 0 || nf <= 0 || nf > cs ||
+      cs % 8 != 0 || img_stride < (long)nf * S * S)
+    return LBFZ_NN_EINVAL;
+  hipLaunchKernelGGL(k_pack_images, dim3(grid_for((long)nimg * S * S)), dim3(256), 0,
+                     (hipStream_t)stream, planes, nimg, img_stride, nf, S, shift, scale,
+                     static_cast<bf16*>(dst), cs);
+  HCHK();
+}
+
+int lbfz_nn_apply_images(const float* out, int out_cs, const float* before, int nimg,
+                         long before_stride, int nf, int S, const float* shift,
+                         const float* scale, const float* resid, float* pred, long pred_stride,
+                         void* stream) {
+  if (!out || !before || !shift || !scale || !resid || !pred || nimg <= 0 || S <= 0 ||
+      nf <= 0 || nf > out_cs || before_stride < (long)nf * S * S ||
+      pred_stride < (long)nf * S * S)
+    return LBFZ_NN_EINVAL;
+  hipLaunchKernelGGL(k_apply_images, dim3(grid_for((long)nimg * S * S)), dim3(256), 0,
+                     (hipStream_t)stream, out, out_cs, before, nimg, before_stride, nf, S, shift,
+                     scale, resid, pred, pred_stride);
   HCHK();
 }
 

@@ -95,13 +95,17 @@ def lib() -> ctypes.CDLL:
         L.lbfz_restart_fields.argtypes = [vp, vpp]
         L.lbfz_batch_select.argtypes = [vp, ctypes.c_int32, ip]
         L.lbfz_batch_restart_fields.argtypes = [vp, ctypes.c_int32, vpp]
+        L.lbfz_batch_fields_all.argtypes = [vp, ctypes.c_uint32, vp, ctypes.c_int64]
+        L.lbfz_batch_restart_many.argtypes = [vp, ctypes.c_int32, ip, vpp,
+                                              ctypes.POINTER(ctypes.c_int64)]
         for nm in ("lbfz_workspace_bytes", "lbfz_create", "lbfz_step", "lbfz_fields",
                    "lbfz_totals", "lbfz_sync", "lbfz_state_floats", "lbfz_get_state",
                    "lbfz_set_state", "lbfz_batch_workspace_bytes", "lbfz_batch_create",
                    "lbfz_batch_tune", "lbfz_batch_step", "lbfz_batch_step_sequential",
                    "lbfz_batch_groups", "lbfz_batch_group_config", "lbfz_batch_fields",
                    "lbfz_batch_totals", "lbfz_restart_fields", "lbfz_batch_select",
-                   "lbfz_batch_restart_fields"):
+                   "lbfz_batch_restart_fields", "lbfz_batch_fields_all",
+                   "lbfz_batch_restart_many"):
             getattr(L, nm).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -433,6 +437,25 @@ class Batch:
 
     def totals(self, i: int) -> dict:
         return lbfz_batch_totals(self._b, i)
+
+    def restart_many(self, idx, planes, strides) -> None:
+        """Equilibrium restart of the grids idx: field m (RESTART_FIELDS) of
+        grid i at planes[m] (a device tensor) + i * strides[m] floats."""
+        idx = [int(i) for i in idx]
+        if not idx:
+            return
+        arr = (ctypes.c_int32 * len(idx))(*idx)
+        ptrs = (ctypes.c_void_p * 7)(*[t.data_ptr() for t in planes])
+        st = (ctypes.c_int64 * 7)(*[int(v) for v in strides])
+        _check(lib().lbfz_batch_restart_many(self._b, len(idx), arr, ptrs, st),
+               "lbfz_batch_restart_many")
+
+    def fields_all_to_device(self, nfields: int, dst) -> None:
+        """The first nfields fields (order FIELDS) of every grid into the
+        device tensor dst [grids][nfields][...] (asynchronous)."""
+        per = dst.numel() // dst.shape[0]
+        _check(lib().lbfz_batch_fields_all(self._b, (1 << nfields) - 1, dst.data_ptr(), per),
+               "lbfz_batch_fields_all")
 
     def select(self, idx=()) -> None:
         """Later steps advance only the grids in idx (empty: all)."""

@@ -74,6 +74,8 @@ def nnlib():
             "lbfz_nn_fill_u32": [vp, lg, u32, vp],
             "lbfz_nn_mse": [vp, i32, vp, lg, i32, vp, vp, vp, i32, vp, vp],
             "lbfz_nn_plane_sums": [vp, i32, lg, lg, vp, vp],
+            "lbfz_nn_pack_images": [vp, i32, lg, i32, i32, vp, vp, vp, i32, vp],
+            "lbfz_nn_apply_images": [vp, i32, vp, i32, lg, i32, i32, vp, vp, vp, vp, lg, vp],
             "lbfz_nn_adam": [vp, vp, vp, vp, vp, lg, f32, f32, f32, f32, i32, vp],
             "lbfz_nn_to_bf16": [vp, vp, lg, vp],
             "lbfz_nn_transpose_w": [vp, i32, i32, i32, vp, vp],
@@ -583,18 +585,15 @@ class Screener:
         self.pred holds the fields STRIDE steps ahead.  Returns the per-grid
         (accept, mass residual, solute drift) of the check."""
         L, net, S, st = nnlib(), self.net, self.S, self.net.st
-        for i in range(self.n):
-            self.batch.fields_to_device(i, [self.before[i, f] for f in range(NEXP)])
-        for i in range(self.n):
-            _ck(L.lbfz_nn_pack_fields(_p(self.before[i]), NIN, S, S, 0, 0, S,
-                                      _p(self.norm.in_shift), _p(self.norm.in_scale),
-                                      _p(net.t["X0"]), CIN0, i, st), "pack_fields")
+        self.batch.fields_all_to_device(NEXP, self.before)
+        _ck(L.lbfz_nn_pack_images(_p(self.before), self.n, NEXP * S * S, NIN, S,
+                                  _p(self.norm.in_shift), _p(self.norm.in_scale),
+                                  _p(net.t["X0"]), CIN0, st), "pack_images")
         net.forward()
-        for i in range(self.n):
-            _ck(L.lbfz_nn_apply_delta(_p(net.t["OUT"]), HEAD, _p(self.before[i]), NF, S, S,
-                                      _p(self.norm.d_shift), _p(self.norm.d_scale),
-                                      _p(self.norm.resid), _p(self.pred[i]), i, st),
-                "apply_delta")
+        _ck(L.lbfz_nn_apply_images(_p(net.t["OUT"]), HEAD, _p(self.before), self.n, NEXP * S * S,
+                                   NF, S, _p(self.norm.d_shift), _p(self.norm.d_scale),
+                                   _p(self.norm.resid), _p(self.pred), NF * S * S, st),
+            "apply_images")
         _ck(L.lbfz_nn_plane_sums(_p(self.before), self.n * NEXP, S * S, S * S, _p(self.sums_b),
                                  st), "plane_sums")
         _ck(L.lbfz_nn_plane_sums(_p(self.pred), self.n * NF, S * S, S * S, _p(self.sums_a),
@@ -616,10 +615,10 @@ class Screener:
             self.batch.select(rej)
             self.batch.step(STRIDE)
         self.time += STRIDE
-        for i in range(self.n):
-            if acc[i]:
-                self.batch.restart_fields(
-                    i, [self.pred[i, f] for f in range(NF)] + [self.before[i, NEXP - 1]])
+        SS = self.S * self.S
+        self.batch.restart_many([i for i in range(self.n) if acc[i]],
+                                [self.pred[0, f] for f in range(NF)] + [self.before[0, NEXP - 1]],
+                                [NF * SS] * NF + [NEXP * SS])
         self.batch.select([])
         return acc, res
 

@@ -91,11 +91,18 @@ def test_batch_subset_step_and_restart(storage):
     part.select([1])
     with pytest.raises(LbfzError):
         part.step(1)
-    # restart them from the full batch's fields at this time level
-    for i in (1, 3):
-        planes = [torch.empty((64, 64), dtype=torch.float32, device="cuda") for _ in range(8)]
-        full.fields_to_device(i, planes)
-        part.restart_fields(i, planes[:6] + [planes[7]])
+    # restart them from the full batch's fields at this time level: grid 1
+    # alone, grid 3 through the many-grid call (fields of every grid in one
+    # buffer, which must equal the per-grid reads)
+    allf = torch.empty((4, 8, 64, 64), dtype=torch.float32, device="cuda")
+    full.fields_all_to_device(8, allf)
+    torch.cuda.synchronize()
+    for i in range(4):
+        fi = full.fields(i)
+        for k, nm in enumerate(("phi", "fl", "T", "C", "ux", "uy", "uz", "p")):
+            assert np.array_equal(allf[i, k].cpu().numpy(), fi[nm]), (i, nm)
+    part.restart_fields(1, [allf[1, k] for k in range(6)] + [allf[1, 7]])
+    part.restart_many([3], [allf[0, k] for k in range(6)] + [allf[0, 7]], [8 * 64 * 64] * 7)
     part.select([])
     part.step(24)
     full.step(24)
