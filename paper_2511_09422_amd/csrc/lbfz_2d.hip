@@ -85,28 +85,32 @@ __device__ __forceinline__ Bufs make_bufs(const KParams& P, const StepArgs& A) {
   const long PS = P.ps;
   B.pb = (uint32_t)PS * 4u;
   B.hb = (uint32_t)PS * 2u;
+  // population sets: descriptors from kSetPad bytes before the first plane
+  auto set = [](const void* first, uint32_t bytes) {
+    return rsrc(static_cast<const char*>(first) - kSetPad, bytes + kSetPad);
+  };
   if constexpr (ST == LBFZ_STORE_F32) {
-    B.f = rsrc(A.src + PF * PS, 5 * B.pb);
-    B.g = rsrc(A.src + PG * PS, 9 * B.pb);
-    B.h = rsrc(A.src + PH * PS, 5 * B.pb);
-    B.l = rsrc(A.src + PL * PS, 5 * B.pb);
-    B.df = rsrc(A.dst + PF * PS, 5 * B.pb);
-    B.dg = rsrc(A.dst + PG * PS, 9 * B.pb);
-    B.dh = rsrc(A.dst + PH * PS, 5 * B.pb);
-    B.dl = rsrc(A.dst + PL * PS, 5 * B.pb);
+    B.f = set(A.src + PF * PS, 5 * B.pb);
+    B.g = set(A.src + PG * PS, 9 * B.pb);
+    B.h = set(A.src + PH * PS, 5 * B.pb);
+    B.l = set(A.src + PL * PS, 5 * B.pb);
+    B.df = set(A.dst + PF * PS, 5 * B.pb);
+    B.dg = set(A.dst + PG * PS, 9 * B.pb);
+    B.dh = set(A.dst + PH * PS, 5 * B.pb);
+    B.dl = set(A.dst + PL * PS, 5 * B.pb);
   } else {
     const uint16_t* s16 = reinterpret_cast<const uint16_t*>(A.src + 4 * PS);
     const uint16_t* d16 = reinterpret_cast<const uint16_t*>(A.dst + 4 * PS);
     B.rest = rsrc(A.src, 4 * B.pb);
-    B.f = rsrc(s16, 4 * B.hb);
-    B.g = rsrc(s16 + 4 * PS, 8 * B.hb);
-    B.h = rsrc(s16 + 12 * PS, 4 * B.hb);
-    B.l = rsrc(s16 + 16 * PS, 4 * B.hb);
+    B.f = set(s16, 4 * B.hb);
+    B.g = set(s16 + 4 * PS, 8 * B.hb);
+    B.h = set(s16 + 12 * PS, 4 * B.hb);
+    B.l = set(s16 + 16 * PS, 4 * B.hb);
     B.drest = rsrc(A.dst, 4 * B.pb);
-    B.df = rsrc(d16, 4 * B.hb);
-    B.dg = rsrc(d16 + 4 * PS, 8 * B.hb);
-    B.dh = rsrc(d16 + 12 * PS, 4 * B.hb);
-    B.dl = rsrc(d16 + 16 * PS, 4 * B.hb);
+    B.df = set(d16, 4 * B.hb);
+    B.dg = set(d16 + 4 * PS, 8 * B.hb);
+    B.dh = set(d16 + 12 * PS, 4 * B.hb);
+    B.dl = set(d16 + 16 * PS, 4 * B.hb);
     B.phiO = rsrc(A.phiP_old, B.pb);
     B.CO = rsrc(A.CP_old, B.pb);
     B.TO = rsrc(A.T_old, B.pb);
@@ -115,6 +119,16 @@ __device__ __forceinline__ Bufs make_bufs(const KParams& P, const StepArgs& A) {
   B.p_old = rsrc(A.p_old, B.pb);
   B.u_old = rsrc(A.u_old, 2 * B.pb);
   return B;
+}
+
+// Plane byte offsets within a population set's descriptor for direction i:
+// FP32 sets hold directions 0.., 16-bit sets 1.. (the rest populations are
+// FP32 planes of their own); both shifted by -c_x (kXS).
+__device__ __forceinline__ uint32_t off32(const Bufs& B, int i) {
+  return kSetPad + (uint32_t)i * B.pb - kXS * CX[i] * 4;
+}
+__device__ __forceinline__ uint32_t off16(const Bufs& B, int i) {
+  return kSetPad + (uint32_t)(i - 1) * B.hb - kXS * CX[i] * 2;
 }
 
 // Wall-normal (y) coordinate -> stored row.  side: 0 inside, -1 ghost below
@@ -143,9 +157,9 @@ __device__ __forceinline__ void load_fhl(const KParams& P, const Bufs& B, uint32
   if constexpr (ST == LBFZ_STORE_F32) {
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-      f[i] = ld(B.f, o, i * B.pb);
-      h[i] = ld(B.h, o, i * B.pb);
-      l[i] = ld(B.l, o, i * B.pb);
+      f[i] = ld(B.f, o, off32(B, i));
+      h[i] = ld(B.h, o, off32(B, i));
+      l[i] = ld(B.l, o, off32(B, i));
     }
   } else {
     const uint32_t o2 = o >> 1;
@@ -156,9 +170,9 @@ __device__ __forceinline__ void load_fhl(const KParams& P, const Bufs& B, uint32
     l[0] = ld(B.rest, o, SL * B.pb);
 #pragma unroll
     for (int i = 1; i < 5; ++i) {
-      f[i] = fmaf(dec16<ST>(ld16(B.f, o2, (i - 1) * B.hb)), 1.0f / SC_F, rf);
-      h[i] = fmaf(dec16<ST>(ld16(B.h, o2, (i - 1) * B.hb)), 1.0f / SC_H, rh);
-      l[i] = fmaf(dec16<ST>(ld16(B.l, o2, (i - 1) * B.hb)), 1.0f / SC_L, rl);
+      f[i] = fmaf(dec16<ST>(ld16(B.f, o2, off16(B, i))), 1.0f / SC_F, rf);
+      h[i] = fmaf(dec16<ST>(ld16(B.h, o2, off16(B, i))), 1.0f / SC_H, rh);
+      l[i] = fmaf(dec16<ST>(ld16(B.l, o2, off16(B, i))), 1.0f / SC_L, rl);
     }
   }
 }
@@ -167,14 +181,14 @@ template <int ST>
 __device__ __forceinline__ void load_g(const Bufs& B, uint32_t o, float* g) {
   if constexpr (ST == LBFZ_STORE_F32) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) g[i] = ld(B.g, o, i * B.pb);
+    for (int i = 0; i < 9; ++i) g[i] = ld(B.g, o, off32(B, i));
   } else {
     const uint32_t o2 = o >> 1;
     const float p3 = 3.0f * ld(B.pR, o);
     g[0] = ld(B.rest, o, SG * B.pb);
 #pragma unroll
     for (int i = 1; i < 9; ++i)
-      g[i] = fmaf(dec16<ST>(ld16(B.g, o2, (i - 1) * B.hb)), 1.0f / SC_G, W9[i] * p3);
+      g[i] = fmaf(dec16<ST>(ld16(B.g, o2, off16(B, i))), 1.0f / SC_G, W9[i] * p3);
   }
 }
 
@@ -494,14 +508,14 @@ __device__ __forceinline__ void step2d_tile(const KParams& P, const StepArgs& A,
   auto push = [&](rsrc_t set, int i, float v, float scale, auto ref) {
     if constexpr (ST == LBFZ_STORE_F32) {
       if (walled(i))
-        st(set, on, OPP[i] * PB, v);  // half-way bounce-back
+        st(set, on, off32(B, OPP[i]), v);  // half-way bounce-back
       else
-        st(set, rowb[CY[i] + 1] + colb[CX[i] + 1], i * PB, v);
+        st(set, rowb[CY[i] + 1] + colb[CX[i] + 1], off32(B, i), v);
     } else {
       if (walled(i)) {
-        st16(set, on >> 1, (OPP[i] - 1) * HB, enc16<ST>((v - ref(0, 0)) * scale));
+        st16(set, on >> 1, off16(B, OPP[i]), enc16<ST>((v - ref(0, 0)) * scale));
       } else {
-        st16(set, (rowb[CY[i] + 1] + colb[CX[i] + 1]) >> 1, (i - 1) * HB,
+        st16(set, (rowb[CY[i] + 1] + colb[CX[i] + 1]) >> 1, off16(B, i),
              enc16<ST>((v - ref(CY[i], CX[i])) * scale));
       }
     }
@@ -509,7 +523,7 @@ __device__ __forceinline__ void step2d_tile(const KParams& P, const StepArgs& A,
   // rest population of set k at the own node
   auto put_rest = [&](rsrc_t set, int k, float v) {
     if constexpr (ST == LBFZ_STORE_F32)
-      st(set, on, 0, v);
+      st(set, on, kSetPad, v);
     else
       st(B.drest, on, k * PB, v);
   };
@@ -572,9 +586,9 @@ __device__ __forceinline__ void step2d_tile(const KParams& P, const StepArgs& A,
         const float Tw = CY[i] < 0 ? P.T_lo + P.T_lo_amp * cosf(P.kwall * (float)gx) : P.T_hi;
         const float hv = -v + 2.0f * W5[o] * P.rhoc_ref * Tw;  // anti-bounce-back
         if constexpr (ST == LBFZ_STORE_F32)
-          st(B.dh, on, o * PB, hv);
+          st(B.dh, on, off32(B, o), hv);
         else
-          st16(B.dh, on >> 1, (o - 1) * HB, enc16<ST>((hv - href_w * T) * SC_H));
+          st16(B.dh, on >> 1, off16(B, o), enc16<ST>((hv - href_w * T) * SC_H));
       } else {
         push(B.dh, i, v, SC_H, [&](int dy, int dx) { return href_w * s_T[cy + dy][cx + dx]; });
       }
@@ -668,15 +682,16 @@ __global__ __launch_bounds__(256) void k_init2d(KParams P, const double* __restr
     if constexpr (ST == LBFZ_STORE_F32) {
 #pragma unroll
       for (int i = 1; i < 5; ++i) {
-        pop[(PH + i) * PS + n] = W5[i] * P.rhoc_ref * T;
-        pop[(PF + i) * PS + n] = W5[i] * phi;
-        pop[(PL + i) * PS + n] = W5[i] * C;
+        const long m = n - kXS * CX[i];  // shifted plane position of node n
+        pop[(PH + i) * PS + m] = W5[i] * P.rhoc_ref * T;
+        pop[(PF + i) * PS + m] = W5[i] * phi;
+        pop[(PL + i) * PS + m] = W5[i] * C;
       }
       pop[(PH + 0) * PS + n] = h0;
       pop[(PF + 0) * PS + n] = f0;
       pop[(PL + 0) * PS + n] = l0;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) pop[(PG + i) * PS + n] = 0.0f;
+      for (int i = 0; i < 9; ++i) pop[(PG + i) * PS + n - kXS * CX[i]] = 0.0f;
       S.phiA[n] = 0.f;
       S.CA[n] = 0.f;
     } else {
@@ -686,7 +701,10 @@ __global__ __launch_bounds__(256) void k_init2d(KParams P, const double* __restr
       pop[SL * PS + n] = l0;
       uint16_t* m16 = reinterpret_cast<uint16_t*>(pop + 4 * PS);
 #pragma unroll
-      for (int j = 0; j < 20; ++j) m16[j * PS + n] = enc16<ST>(0.0f);
+      for (int j = 0; j < 20; ++j) {
+        const int i = j < 4 ? j + 1 : (j < 12 ? j - 3 : (j < 16 ? j - 11 : j - 15));
+        m16[j * PS + n - kXS * CX[i]] = enc16<ST>(0.0f);
+      }
       // decode references of the step that reads these populations
       S.phiA[n] = phi;
       S.CA[n] = C;
@@ -758,12 +776,14 @@ __global__ __launch_bounds__(256) void k_import2d(KParams P, StepArgs A,
     uint16_t* m16 = reinterpret_cast<uint16_t*>(A.dst + 4 * PS);
 #pragma unroll
     for (int i = 1; i < 5; ++i) {
-      m16[(i - 1) * PS + n] = enc16<ST>((f[i] - rf) * SC_F);
-      m16[(12 + i - 1) * PS + n] = enc16<ST>((h[i] - rh) * SC_H);
-      m16[(16 + i - 1) * PS + n] = enc16<ST>((l[i] - rl) * SC_L);
+      const long m = n - kXS * CX[i];
+      m16[(i - 1) * PS + m] = enc16<ST>((f[i] - rf) * SC_F);
+      m16[(12 + i - 1) * PS + m] = enc16<ST>((h[i] - rh) * SC_H);
+      m16[(16 + i - 1) * PS + m] = enc16<ST>((l[i] - rl) * SC_L);
     }
 #pragma unroll
-    for (int i = 1; i < 9; ++i) m16[(4 + i - 1) * PS + n] = enc16<ST>((g[i] - W9[i] * p3) * SC_G);
+    for (int i = 1; i < 9; ++i)
+      m16[(4 + i - 1) * PS + n - kXS * CX[i]] = enc16<ST>((g[i] - W9[i] * p3) * SC_G);
   }
 }
 

@@ -424,7 +424,16 @@ int state_planes(lbfz_handle* h, std::vector<float*>& planes) {
     for (int q = 0; q < h->npop; ++q) planes.push_back(h->stage + q * N);
   } else {
     float* pop = h->pop[h->cur];
-    for (int q = 0; q < h->npop; ++q) planes.push_back(pop + q * ps);
+    // 2D planes of a direction with an x component are stored shifted by -c_x
+    static const int kCx9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    for (int q = 0; q < h->npop; ++q) {
+      int cx = 0;
+      if (h->prm.dim == 2) {
+        const int i = q < 5 ? q : (q < 14 ? q - 5 : (q < 19 ? q - 14 : q - 19));
+        cx = kXS * kCx9[i];
+      }
+      planes.push_back(pop + q * ps - cx);
+    }
   }
   float* cf = h->cf[h->cur];
   planes.push_back(h->prm.dim == 3 ? cf + 3 * ps : h->fs);

@@ -110,6 +110,22 @@ __device__ __forceinline__ double block_sum(double v, double* sred) {
   return s;  // valid on thread 0
 }
 
+// 2D population planes of a direction with an x component are stored shifted
+// by -c_x nodes: node m's population i sits at element m - c_x,i of its
+// plane.  A push-streamed write from node x to x + c_i then lands at flat
+// element x + c_y,i nx -- a wave's 64 writes fill aligned cache lines -- and
+// the misalignment moves to the reads of the next step, which the caches
+// absorb.  The planes' padding holds the one element a plane reaches past
+// either end.  LBFZ_XSHIFT 0 stores them unshifted (for comparison).
+#ifndef LBFZ_XSHIFT
+#define LBFZ_XSHIFT 1
+#endif
+constexpr int kXS = LBFZ_XSHIFT;
+// A population set's buffer descriptor starts this many bytes before its
+// first plane, so that the (unsigned) plane offsets stay positive for a
+// first plane shifted by -1 element.
+constexpr uint32_t kSetPad = 256;
+
 // Word 3 of a CDNA buffer descriptor: 32-bit data format, no swizzle.
 constexpr int kBufWord3 = 0x00020000;
 
