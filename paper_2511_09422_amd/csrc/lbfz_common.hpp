@@ -115,12 +115,16 @@ __device__ __forceinline__ double block_sum(double v, double* sred) {
 // plane.  A push-streamed write from node x to x + c_i then lands at flat
 // element x + c_y,i nx -- a wave's 64 writes fill aligned cache lines -- and
 // the misalignment moves to the reads of the next step, which the caches
-// absorb.  The planes' padding holds the one element a plane reaches past
-// either end.  LBFZ_XSHIFT 0 stores them unshifted (for comparison).
+// absorb (FP32 step 217 -> 209 us at 2048^2).  The planes' padding holds the
+// one element a plane reaches past either end.  The 3D step keeps its planes
+// unshifted (kXS3 = 0): shifted, its FP32 step was no faster and its 16-bit
+// step slower (1.42 -> 1.52 ms at 256^3), its reads being the critical
+// path.  LBFZ_XSHIFT 0 builds 2D unshifted too (for comparison).
 #ifndef LBFZ_XSHIFT
 #define LBFZ_XSHIFT 1
 #endif
 constexpr int kXS = LBFZ_XSHIFT;
+constexpr int kXS3 = 0;
 // A population set's buffer descriptor starts this many bytes before its
 // first plane, so that the (unsigned) plane offsets stay positive for a
 // first plane shifted by -1 element.

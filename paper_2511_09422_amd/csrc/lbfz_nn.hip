@@ -306,8 +306,8 @@ __global__ __launch_bounds__(256) void k_conv(lbfz_conv_args a) {
 
 // Direct 3 x 3 convolution (forward, data gradient, and the forward through
 // 2x upsampling): a block computes a TH x TW = 4 x 64 tile of output pixels of
-// one image for BN = 32 FN output channels.  Per input-channel chunk of CC =
-// 32 it stages the (TH + 2) x (TW + 2) haloed input tile and the chunk's
+// one image for BN = 32 FN output channels.  Per input-channel chunk of CC
+// (32, or 16) it stages the (TH + 2) x (TW + 2) haloed input tile and the chunk's
 // weights [n][tap][c] in LDS once, then every wave (one output row, 2 x FN
 // accumulators of 32 x 32) runs the nine taps' MFMAs reading its A fragments
 // from the tile at the tap's shift -- each input byte is loaded from memory
@@ -315,17 +315,21 @@ __global__ __launch_bounds__(256) void k_conv(lbfz_conv_args a) {
 // tap).  Tap shifts are compile-time (SIGN), so fragment addresses are one
 // per-lane base plus immediates.  The next chunk's loads are issued before
 // the current chunk's MFMAs.
-constexpr int TW = 64, TH = 4, HWD = TW + 2, HHT = TH + 2, CC = 32, HPS = CC + 8;
+constexpr int TW = 64, TH = 4, HWD = TW + 2, HHT = TH + 2;
 
-template <int FN, bool UP, int SIGN>
+// CC: input channels per chunk (32, or 16 for layers whose channel count is
+// not a multiple of 32, e.g. the 16-channel input layer)
+template <int FN, bool UP, int SIGN, int CC = 32>
 __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
   constexpr int BN_ = 32 * FN;
+  constexpr int HPS = CC + 8;            // LDS pixel stride (bf16), padded by 16 B
+  constexpr int CPX = CC / 8;            // 16-byte chunks per pixel and chunk
   constexpr int H_EL = HHT * HWD * HPS;  // haloed input tile [pixel][c]
   constexpr int W_EL = BN_ * 9 * HPS;    // weights [n][tap][c]
   constexpr int O_EL = TH * TW * BN_;    // bf16 output tile for the stores
   constexpr int SM_EL = (H_EL + W_EL) > O_EL ? (H_EL + W_EL) : O_EL;
-  constexpr int HE = HHT * HWD * 4, HJ = (HE + 255) / 256;  // halo 16-byte chunks
-  constexpr int WE = BN_ * 9 * 4, WJ = (WE + 255) / 256;    // weight 16-byte chunks
+  constexpr int HE = HHT * HWD * CPX, HJ = (HE + 255) / 256;  // halo 16-byte chunks
+  constexpr int WE = BN_ * 9 * CPX, WJ = (WE + 255) / 256;    // weight 16-byte chunks
   __shared__ __align__(16) bf16 smem[SM_EL];
   bf16* Hs = smem;
   bf16* Ws = smem + H_EL;
@@ -347,8 +351,8 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
   int hq[HJ];
 #pragma unroll
   for (int j = 0; j < HJ; ++j) {
-    const int e = tid + 256 * j, hp = e >> 2;
-    hq[j] = 8 * (e & 3);
+    const int e = tid + 256 * j, hp = e / CPX;
+    hq[j] = 8 * (e % CPX);
     const int yy = y0 + hp / HWD - 1, xx = x0 + hp % HWD - 1;
     hoff[j] = kOut;
     if (e < HE && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
@@ -361,9 +365,9 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
   int wq[WJ];
 #pragma unroll
   for (int j = 0; j < WJ; ++j) {
-    const int e = tid + 256 * j, n = e / 36, rem = e - n * 36;
-    wq[j] = 8 * (rem & 3);
-    woff[j] = (e < WE && n0 + n < a.N) ? ((uint32_t)(n0 + n) * K + (rem >> 2) * a.Cin + wq[j]) * 2
+    const int e = tid + 256 * j, n = e / (9 * CPX), rem = e - n * (9 * CPX);
+    wq[j] = 8 * (rem % CPX);
+    woff[j] = (e < WE && n0 + n < a.N) ? ((uint32_t)(n0 + n) * K + (rem / CPX) * a.Cin + wq[j]) * 2
                                       : kOut;
   }
   uint4 hv[HJ], wv[WJ];
@@ -391,14 +395,14 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
 #pragma unroll
     for (int j = 0; j < HJ; ++j) {
       const int e = tid + 256 * j;
-      if (e < HE) *reinterpret_cast<uint4*>(Hs + (e >> 2) * HPS + 8 * (e & 3)) = hv[j];
+      if (e < HE) *reinterpret_cast<uint4*>(Hs + (e / CPX) * HPS + 8 * (e % CPX)) = hv[j];
     }
 #pragma unroll
     for (int j = 0; j < WJ; ++j) {
       const int e = tid + 256 * j;
       if (e < WE) {
-        const int n = e / 36, rem = e - n * 36;
-        *reinterpret_cast<uint4*>(Ws + (n * 9 + (rem >> 2)) * HPS + 8 * (rem & 3)) = wv[j];
+        const int n = e / (9 * CPX), rem = e - n * (9 * CPX);
+        *reinterpret_cast<uint4*>(Ws + (n * 9 + rem / CPX) * HPS + 8 * (rem % CPX)) = wv[j];
       }
     }
     __syncthreads();
@@ -964,7 +968,15 @@ int lbfz_nn_conv(const lbfz_conv_args* a, void* stream) {
     // direct convolution over 4 x 64 pixel tiles, 64 output channels per
     // block when N is a multiple of 64, else 32
     const long tiles = (long)a->B * ((a->H + TH - 1) / TH) * ((a->W + TW - 1) / TW);
-    if (a->N % 64 == 0) {
+    if (a->Cin % 32 != 0 && !a->up && a->sign == 1) {
+      // 16-channel chunks: no half-empty chunk for e.g. a 16-channel input
+      if (a->N % 64 == 0)
+        hipLaunchKernelGGL((k_conv_direct<2, false, 1, 16>), dim3((unsigned)tiles, a->N / 64),
+                           dim3(256), 0, st, *a);
+      else
+        hipLaunchKernelGGL((k_conv_direct<1, false, 1, 16>),
+                           dim3((unsigned)tiles, (a->N + 31) / 32), dim3(256), 0, st, *a);
+    } else if (a->N % 64 == 0) {
       const dim3 grid((unsigned)tiles, (unsigned)(a->N / 64));
       if (a->up)
         hipLaunchKernelGGL((k_conv_direct<2, true, 1>), grid, dim3(256), 0, st, *a);

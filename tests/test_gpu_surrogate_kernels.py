@@ -31,15 +31,17 @@ def _rel(got, ref):
     return float(np.abs(np.asarray(got, np.float64) - ref).max() / max(np.abs(ref).max(), 1e-30))
 
 
-# the forward runs a 256 x 32, 256 x 64 or 128 x 128 tile by N (and the data
-# gradient by Cin): the cases cover each shape with pixel counts that leave a
-# ragged last tile, K slices that cross taps (Cin 16, 32, 96) and a K tail
-# (K = 9 * 96 is not a multiple of the 64-deep slice)
+# 3 x 3 layers run the direct kernel (4 x 64 pixel tiles, 32 or 64 output
+# channels per block, 32- or 16-channel input chunks), 1 x 1 the implicit
+# GEMM: the cases cover both widths, ragged tiles in x and y (widths below
+# and above 64), partial and multiple input chunks (Cin 16, 48, 96, 192) and
+# several column blocks (N 72, 128, 256)
 @pytest.mark.parametrize("B,H,W,Cin,N,taps", [(2, 16, 16, 16, 32, 9), (1, 12, 20, 32, 40, 9),
                                               (2, 8, 8, 64, 72, 9), (2, 16, 16, 32, 8, 1),
                                               (1, 20, 24, 32, 64, 9), (1, 10, 30, 64, 128, 9),
                                               (1, 9, 14, 96, 32, 9), (2, 6, 11, 192, 64, 9),
-                                              (1, 16, 24, 128, 256, 9)])
+                                              (1, 16, 24, 128, 256, 9), (1, 9, 20, 16, 64, 9),
+                                              (1, 7, 12, 48, 32, 9)])
 def test_conv_forward_and_gradients(B, H, W, Cin, N, taps):
     import torch
     import torch.nn.functional as F
