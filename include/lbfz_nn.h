@@ -64,8 +64,10 @@ typedef struct lbfz_conv_args {
 int lbfz_nn_conv(const lbfz_conv_args* a, void* stream);
 
 /* Weight gradient dw[n][t][c] = sum_p dz[p][n] x[p + o(t)][c], FP32.  The
- * pixel sum is split over nsplit block rows into part (nsplit * N * taps *
- * Cin floats), then summed in a fixed order (deterministic). */
+ * pixel sum is split into at most nsplit partial rows in part (nsplit * N *
+ * taps * Cin floats; 3 x 3: up to about 512 / (ceil(N/32) ceil(Cin/32))
+ * rows are used, 1 x 1: nsplit), then summed in a fixed order
+ * (deterministic). */
 int lbfz_nn_conv_wgrad(const lbfz_conv_args* a, float* part, int nsplit, float* dw, void* stream);
 
 /* Bias gradient db[c] = sum_p dz[p][c] (C <= 256 channels at stride cs, both

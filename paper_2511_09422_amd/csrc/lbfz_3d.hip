@@ -98,33 +98,28 @@ __device__ __forceinline__ Bufs3 make_bufs3(const KParams& P, const StepArgs& A)
   const long PS = P.ps;
   B.pb = (uint32_t)PS * 4u;
   B.hb = (uint32_t)PS * 2u;
-  // population sets: descriptors from kSetPad bytes before the first plane
-  // (planes of directions with an x component shifted by -c_x when kXS3)
-  auto set = [](const void* first, uint32_t bytes) {
-    return rsrc(static_cast<const char*>(first) - kSetPad, bytes + kSetPad);
-  };
   if constexpr (ST == LBFZ_STORE_F32) {
-    B.f = set(A.src + PF * PS, 7 * B.pb);
-    B.g = set(A.src + PG * PS, 19 * B.pb);
-    B.h = set(A.src + PH * PS, 7 * B.pb);
-    B.l = set(A.src + PL * PS, 7 * B.pb);
-    B.df = set(A.dst + PF * PS, 7 * B.pb);
-    B.dg = set(A.dst + PG * PS, 19 * B.pb);
-    B.dh = set(A.dst + PH * PS, 7 * B.pb);
-    B.dl = set(A.dst + PL * PS, 7 * B.pb);
+    B.f = rsrc(A.src + PF * PS, 7 * B.pb);
+    B.g = rsrc(A.src + PG * PS, 19 * B.pb);
+    B.h = rsrc(A.src + PH * PS, 7 * B.pb);
+    B.l = rsrc(A.src + PL * PS, 7 * B.pb);
+    B.df = rsrc(A.dst + PF * PS, 7 * B.pb);
+    B.dg = rsrc(A.dst + PG * PS, 19 * B.pb);
+    B.dh = rsrc(A.dst + PH * PS, 7 * B.pb);
+    B.dl = rsrc(A.dst + PL * PS, 7 * B.pb);
   } else {
     const uint16_t* s16 = reinterpret_cast<const uint16_t*>(A.src + 2 * PS);
     const uint16_t* d16 = reinterpret_cast<const uint16_t*>(A.dst + 2 * PS);
     B.rest = rsrc(A.src, 2 * B.pb);
     B.drest = rsrc(A.dst, 2 * B.pb);
-    B.f = set(s16 + M_F * PS, 6 * B.hb);
-    B.g = set(s16 + M_G * PS, 18 * B.hb);
-    B.h = set(s16 + M_H * PS, 6 * B.hb);
-    B.l = set(s16 + M_L * PS, 6 * B.hb);
-    B.df = set(d16 + M_F * PS, 6 * B.hb);
-    B.dg = set(d16 + M_G * PS, 18 * B.hb);
-    B.dh = set(d16 + M_H * PS, 6 * B.hb);
-    B.dl = set(d16 + M_L * PS, 6 * B.hb);
+    B.f = rsrc(s16 + M_F * PS, 6 * B.hb);
+    B.g = rsrc(s16 + M_G * PS, 18 * B.hb);
+    B.h = rsrc(s16 + M_H * PS, 6 * B.hb);
+    B.l = rsrc(s16 + M_L * PS, 6 * B.hb);
+    B.df = rsrc(d16 + M_F * PS, 6 * B.hb);
+    B.dg = rsrc(d16 + M_G * PS, 18 * B.hb);
+    B.dh = rsrc(d16 + M_H * PS, 6 * B.hb);
+    B.dl = rsrc(d16 + M_L * PS, 6 * B.hb);
     B.p_ref = rsrc(A.p_ref, B.pb);
   }
   B.cfo = rsrc(A.cf_old, CF_N * B.pb);
@@ -133,15 +128,6 @@ __device__ __forceinline__ Bufs3 make_bufs3(const KParams& P, const StepArgs& A)
   B.u_old = rsrc(A.u_old, 3 * B.pb);
   B.mask = rsrc(A.mask, A.mask ? (uint32_t)P.N : 0u);
   return B;
-}
-
-// Plane byte offsets within a population set's descriptor for direction i
-// (FP32 sets from direction 0, 16-bit sets from 1), shifted by -c_x (kXS3).
-__device__ __forceinline__ uint32_t off32(const Bufs3& B, int i) {
-  return kSetPad + (uint32_t)i * B.pb - kXS3 * CX[i] * 4;
-}
-__device__ __forceinline__ uint32_t off16(const Bufs3& B, int i) {
-  return kSetPad + (uint32_t)(i - 1) * B.hb - kXS3 * CX[i] * 2;
 }
 
 // f (links 1..6), h (0..6), l (1..6) of the node at byte offset o; f[0] = l[0]
@@ -154,9 +140,9 @@ __device__ __forceinline__ void load_fhl3(const KParams& P, const Bufs3& B, uint
   if constexpr (ST == LBFZ_STORE_F32) {
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
-      if (i) f[i] = ld(B.f, o, off32(B, i));
-      h[i] = ld(B.h, o, off32(B, i));
-      if (i) l[i] = ld(B.l, o, off32(B, i));
+      if (i) f[i] = ld(B.f, o, i * B.pb);
+      h[i] = ld(B.h, o, i * B.pb);
+      if (i) l[i] = ld(B.l, o, i * B.pb);
     }
   } else {
     const uint32_t o2 = o >> 1;
@@ -166,9 +152,9 @@ __device__ __forceinline__ void load_fhl3(const KParams& P, const Bufs3& B, uint
     h[0] = ld(B.rest, o, R_H0 * B.pb);
 #pragma unroll
     for (int i = 1; i < 7; ++i) {
-      f[i] = fmaf(dec16<ST>(ld16(B.f, o2, off16(B, i))), 1.0f / SC_F, rf);
-      h[i] = fmaf(dec16<ST>(ld16(B.h, o2, off16(B, i))), 1.0f / SC_H, rh);
-      l[i] = fmaf(dec16<ST>(ld16(B.l, o2, off16(B, i))), 1.0f / SC_L, rl);
+      f[i] = fmaf(dec16<ST>(ld16(B.f, o2, (i - 1) * B.hb)), 1.0f / SC_F, rf);
+      h[i] = fmaf(dec16<ST>(ld16(B.h, o2, (i - 1) * B.hb)), 1.0f / SC_H, rh);
+      l[i] = fmaf(dec16<ST>(ld16(B.l, o2, (i - 1) * B.hb)), 1.0f / SC_L, rl);
     }
   }
 }
@@ -177,14 +163,14 @@ template <int ST>
 __device__ __forceinline__ void load_g3(const Bufs3& B, uint32_t o, float* g) {
   if constexpr (ST == LBFZ_STORE_F32) {
 #pragma unroll
-    for (int i = 0; i < 19; ++i) g[i] = ld(B.g, o, off32(B, i));
+    for (int i = 0; i < 19; ++i) g[i] = ld(B.g, o, i * B.pb);
   } else {
     const uint32_t o2 = o >> 1;
     const float p3 = 3.0f * ld(B.p_ref, o);
     g[0] = ld(B.rest, o, R_G0 * B.pb);
 #pragma unroll
     for (int i = 1; i < 19; ++i)
-      g[i] = fmaf(dec16<ST>(ld16(B.g, o2, off16(B, i))), 1.0f / SC_G, W19[i] * p3);
+      g[i] = fmaf(dec16<ST>(ld16(B.g, o2, (i - 1) * B.hb)), 1.0f / SC_G, W19[i] * p3);
   }
 }
 
@@ -400,13 +386,13 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
   // against the reference refw = w_i r of the node it is stored at
   auto put = [&](rsrc_t set, uint32_t off, int slot, float v, float refw, float scale) {
     if constexpr (ST == LBFZ_STORE_F32)
-      st(set, off, off32(B, slot), v);
+      st(set, off, slot * PB, v);
     else
-      st16(set, off >> 1, off16(B, slot), enc16<ST>((v - refw) * scale));
+      st16(set, off >> 1, (slot - 1) * HB, enc16<ST>((v - refw) * scale));
   };
   auto put_rest = [&](rsrc_t set, int slot32, int slot16, float v) {
     if constexpr (ST == LBFZ_STORE_F32)
-      st(set, on, off32(B, slot32), v);
+      st(set, on, slot32 * PB, v);
     else
       st(B.drest, on, slot16 * PB, v);
   };
@@ -721,21 +707,17 @@ __global__ __launch_bounds__(256) void k_init3d(KParams P, const double* __restr
     if constexpr (ST == LBFZ_STORE_F32) {
 #pragma unroll
       for (int i = 1; i < 7; ++i) {
-        const long m = n - kXS3 * CX[i];  // shifted plane position of node n
-        popA[(PH + i) * PS + m] = W7 * P.rhoc_ref * T;
-        popA[(PF + i) * PS + m] = ob ? 0.0f : W7 * phi;
-        popA[(PL + i) * PS + m] = ob ? 0.0f : W7 * C;
+        popA[(PH + i) * PS + n] = W7 * P.rhoc_ref * T;
+        popA[(PF + i) * PS + n] = ob ? 0.0f : W7 * phi;
+        popA[(PL + i) * PS + n] = ob ? 0.0f : W7 * C;
       }
       popA[(PH + 0) * PS + n] = h0;
       popA[(PF + 0) * PS + n] = 0.0f;
       popA[(PL + 0) * PS + n] = 0.0f;
 #pragma unroll
-      for (int i = 0; i < 19; ++i) popA[(PG + i) * PS + n - kXS3 * CX[i]] = 0.0f;
+      for (int i = 0; i < 19; ++i) popA[(PG + i) * PS + n] = 0.0f;
 #pragma unroll
-      for (int q = 0; q < 40; ++q) {
-        const int i = q < 7 ? q : (q < 26 ? q - 7 : (q < 33 ? q - 26 : q - 33));
-        popB[q * PS + n - kXS3 * CX[i]] = 0.0f;
-      }
+      for (int q = 0; q < 40; ++q) popB[q * PS + n] = 0.0f;
     } else {
       // every moving population at its reference (offset 0); obstacle f and l
       // slots are never read for the step
@@ -747,9 +729,8 @@ __global__ __launch_bounds__(256) void k_init3d(KParams P, const double* __restr
       uint16_t* b16 = reinterpret_cast<uint16_t*>(popB + 2 * PS);
 #pragma unroll
       for (int j = 0; j < M_N; ++j) {
-        const int i = j < M_G ? j + 1 : (j < M_H ? j - M_G + 1 : (j < M_L ? j - M_H + 1 : j - M_L + 1));
-        a16[j * PS + n - kXS3 * CX[i]] = enc16<ST>(0.0f);
-        b16[j * PS + n - kXS3 * CX[i]] = enc16<ST>(0.0f);
+        a16[j * PS + n] = enc16<ST>(0.0f);
+        b16[j * PS + n] = enc16<ST>(0.0f);
       }
       S.pC[n] = 0.f;
     }
@@ -819,15 +800,13 @@ __global__ __launch_bounds__(256) void k_import3d(KParams P, StepArgs A,
     uint16_t* m16 = reinterpret_cast<uint16_t*>(A.dst + 2 * PS);
 #pragma unroll
     for (int i = 1; i < 7; ++i) {
-      const long m = n - kXS3 * CX[i];
-      m16[(M_F + i - 1) * PS + m] = enc16<ST>((src[(PF + i) * N + n] - rf) * SC_F);
-      m16[(M_H + i - 1) * PS + m] = enc16<ST>((src[(PH + i) * N + n] - rh) * SC_H);
-      m16[(M_L + i - 1) * PS + m] = enc16<ST>((src[(PL + i) * N + n] - rl) * SC_L);
+      m16[(M_F + i - 1) * PS + n] = enc16<ST>((src[(PF + i) * N + n] - rf) * SC_F);
+      m16[(M_H + i - 1) * PS + n] = enc16<ST>((src[(PH + i) * N + n] - rh) * SC_H);
+      m16[(M_L + i - 1) * PS + n] = enc16<ST>((src[(PL + i) * N + n] - rl) * SC_L);
     }
 #pragma unroll
     for (int i = 1; i < 19; ++i)
-      m16[(M_G + i - 1) * PS + n - kXS3 * CX[i]] =
-          enc16<ST>((src[(PG + i) * N + n] - W19[i] * p3) * SC_G);
+      m16[(M_G + i - 1) * PS + n] = enc16<ST>((src[(PG + i) * N + n] - W19[i] * p3) * SC_G);
   }
 }
 

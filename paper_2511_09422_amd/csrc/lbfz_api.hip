@@ -424,20 +424,16 @@ int state_planes(lbfz_handle* h, std::vector<float*>& planes) {
     for (int q = 0; q < h->npop; ++q) planes.push_back(h->stage + q * N);
   } else {
     float* pop = h->pop[h->cur];
-    // planes of a direction with an x component are stored shifted by -c_x
-    // (direction orders as documented for the state layout)
+    // 2D planes of a direction with an x component are stored shifted by
+    // -c_x (direction order as documented for the state layout)
     static const int kCx9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-    static const int kCx19[19] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0};
     for (int q = 0; q < h->npop; ++q) {
-      int cx;
+      int cx = 0;
       if (h->prm.dim == 2) {
         const int i = q < 5 ? q : (q < 14 ? q - 5 : (q < 19 ? q - 14 : q - 19));
-        cx = kCx9[i];
-      } else {
-        const int i = q < 7 ? q : (q < 26 ? q - 7 : (q < 33 ? q - 26 : q - 33));
-        cx = kCx19[i];
+        cx = kXS * kCx9[i];
       }
-      planes.push_back(pop + q * ps - (h->prm.dim == 2 ? kXS : kXS3) * cx);
+      planes.push_back(pop + q * ps - cx);
     }
   }
   float* cf = h->cf[h->cur];

@@ -117,15 +117,14 @@ __device__ __forceinline__ double block_sum(double v, double* sred) {
 // the misalignment moves to the reads of the next step, which the caches
 // absorb (FP32 step 217 -> 209 us at 2048^2).  The planes' padding holds the
 // one element a plane reaches past either end.  The 3D step keeps its planes
-// unshifted (kXS3 = 0): shifted, its FP32 step was no faster and its 16-bit
-// step slower (1.42 -> 1.52 ms at 256^3), its reads being the critical
-// path.  LBFZ_XSHIFT 0 builds 2D unshifted too (for comparison).
+// unshifted: shifted, its FP32 step was no faster and its 16-bit step slower
+// (its reads are the critical path).  LBFZ_XSHIFT 0 builds 2D unshifted too
+// (for comparison).
 #ifndef LBFZ_XSHIFT
 #define LBFZ_XSHIFT 1
 #endif
 constexpr int kXS = LBFZ_XSHIFT;
-constexpr int kXS3 = 0;
-// A population set's buffer descriptor starts this many bytes before its
+// A 2D population set's buffer descriptor starts this many bytes before its
 // first plane, so that the (unsigned) plane offsets stay positive for a
 // first plane shifted by -1 element.
 constexpr uint32_t kSetPad = 256;

@@ -47,6 +47,24 @@ __device__ __forceinline__ uint4 ld16B(rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(uint4, v);
 }
 
+// 8-channel (16-byte) groups of bf16 activations: pooling, upsampling and the
+// bias gradient move whole groups (channel counts, strides and offsets are
+// multiples of 8, checked by the callers).
+union V8 {
+  uint4 u;
+  bf16 h[8];
+};
+
+__device__ __forceinline__ V8 ld8(const bf16* p) {
+  V8 v;
+  v.u = *reinterpret_cast<const uint4*>(p);
+  return v;
+}
+
+__device__ __forceinline__ void st8(bf16* p, const V8& v) {
+  *reinterpret_cast<uint4*>(p) = v.u;
+}
+
 __device__ __forceinline__ void tap_offset(int taps, int t, int sign, int& dy, int& dx) {
   if (taps == 1) {
     dy = dx = 0;
@@ -485,6 +503,133 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
   }
 }
 
+// Weight gradient of a 3 x 3 convolution, direct form: dW[n][t][c] = sum_p
+// dz[p][n] x[p + o(t)][c].  A block owns 32 output channels n0.. and 32 input
+// channels c0.. and walks the 4 x 64 pixel tiles split, split + gridDim.x, ...
+// For each tile it stages dz transposed, dzT[n][pixel], and the haloed input
+// transposed in three copies shifted by the tap column, X[s][c][row][col] =
+// x(row - 1, col + s - 1), so that the MFMA fragments -- 8 consecutive
+// pixels of one channel per lane -- are aligned 16-byte LDS reads for every
+// tap.  Wave w reduces over output row w of the tile and keeps the nine
+// taps' 32 x 32 accumulators; the block adds its four waves' sums (fixed
+// order) into partial row `split`, and the partial rows are summed in a
+// fixed order (deterministic).
+constexpr int DZS = TH * TW + 8;  // dzT row stride (bf16)
+constexpr int XRS = TW + 8;       // X row stride (bf16)
+
+template <bool UP>
+__global__ __launch_bounds__(256) void k_conv_wgrad_direct(lbfz_conv_args a,
+                                                           float* __restrict__ part) {
+  constexpr int DZ_EL = 32 * DZS, X_EL = 3 * 32 * HHT * XRS;
+  constexpr int DJ = TH * TW * 4 / 256;                  // dz 16-byte chunks per thread
+  constexpr int XE = HHT * HWD * 4, XJ = (XE + 255) / 256;  // halo chunks
+  __shared__ __align__(16) bf16 smem[DZ_EL + X_EL];
+  bf16* dzT = smem;
+  bf16* Xs = smem + DZ_EL;
+  const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + TH - 1) / TH;
+  const int ntiles = a.B * tiles_y * tiles_x;
+  const int n0 = blockIdx.y * 32, c0 = blockIdx.z * 32;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int M = a.B * a.H * a.W;
+  const rsrc_t rin = make_rsrc(a.in, (uint32_t)((UP ? (size_t)M / 4 : (size_t)M) * a.in_cs * 2));
+  const rsrc_t rdz = make_rsrc(a.w, (uint32_t)((size_t)M * a.dz_cs * 2));
+  uint4 dv[DJ], xv[XJ];
+  // loads of tile `tile` into registers: dz chunk j of this thread is pixel
+  // (tid + 256 j) % 256 of the tile, channel group (tid + 256 j) / 256; halo
+  // chunk j is halo pixel e % (HHT HWD), channel group e / (HHT HWD)
+  auto gload = [&](int tile) {
+    const int b = tile / (tiles_y * tiles_x), rt = tile - b * (tiles_y * tiles_x);
+    const int y0 = (rt / tiles_x) * TH, x0 = (rt % tiles_x) * TW;
+#pragma unroll
+    for (int j = 0; j < DJ; ++j) {
+      const int e = tid + 256 * j, px = e % (TH * TW), g = e / (TH * TW);
+      const int y = y0 + px / TW, x = x0 + px % TW;
+      const bool ok = y < a.H && x < a.W && n0 + 8 * g < a.N;
+      dv[j] = ld16B(rdz, ok ? ((uint32_t)((b * a.H + y) * a.W + x) * a.dz_cs + n0 + 8 * g) * 2
+                            : kOut);
+    }
+#pragma unroll
+    for (int j = 0; j < XJ; ++j) {
+      const int e = tid + 256 * j, hp = e % (HHT * HWD), g = e / (HHT * HWD);
+      const int yy = y0 + hp / HWD - 1, xx = x0 + hp % HWD - 1;
+      uint32_t off = kOut;
+      if (e < XE && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W && c0 + 8 * g < a.Cin) {
+        const int src = UP ? (b * (a.H >> 1) + (yy >> 1)) * (a.W >> 1) + (xx >> 1)
+                           : (b * a.H + yy) * a.W + xx;
+        off = ((uint32_t)src * a.in_cs + a.in_co + c0 + 8 * g) * 2;
+      }
+      xv[j] = ld16B(rin, off);
+    }
+  };
+  f32x16 acc[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t] = f32x16{};
+  const int split = blockIdx.x;
+  if (split < ntiles) gload(split);
+  for (int tile = split; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();  // the previous tile's fragments have been read
+#pragma unroll
+    for (int j = 0; j < DJ; ++j) {
+      const int e = tid + 256 * j, px = e % (TH * TW), g = e / (TH * TW);
+      V8 v;
+      v.u = dv[j];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) dzT[(8 * g + k) * DZS + px] = v.h[k];
+    }
+#pragma unroll
+    for (int j = 0; j < XJ; ++j) {
+      const int e = tid + 256 * j;
+      if (e >= XE) continue;
+      const int hp = e % (HHT * HWD), g = e / (HHT * HWD);
+      const int hy = hp / HWD, hx = hp % HWD;
+      V8 v;
+      v.u = xv[j];
+#pragma unroll
+      for (int sft = 0; sft < 3; ++sft) {
+        const int tx = hx - sft;
+        if (tx >= 0 && tx < TW) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) Xs[((sft * 32 + 8 * g + k) * HHT + hy) * XRS + tx] = v.h[k];
+        }
+      }
+    }
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) gload(tile + gridDim.x);
+    // wave w: output row w of the tile, 4 k-steps of 16 pixels per tap
+    const bf16* abase = dzT + (lane & 31) * DZS + wave * TW + 8 * (lane >> 5);
+    const bf16* bbase = Xs + (lane & 31) * HHT * XRS + 8 * (lane >> 5);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int sft = t % 3, hy = wave + t / 3;  // copy dx + 1, halo row y + dy + 1
+#pragma unroll
+      for (int kk = 0; kk < TW; kk += 16) {
+        const bf16x8 fa = *reinterpret_cast<const bf16x8*>(abase + kk);
+        const bf16x8 fb =
+            *reinterpret_cast<const bf16x8*>(bbase + (sft * 32 * HHT + hy) * XRS + kk);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  // the four waves' sums, added in LDS in a fixed order, one tap at a time,
+  // into partial row `split`: element r of tap t is dW[n0 + acc_row][t][c0 +
+  // lane % 32]
+  const size_t NW = (size_t)9 * a.Cin;
+  float* prow = part + (size_t)split * a.N * NW;
+  float* red = reinterpret_cast<float*>(smem);  // 4 x 32 x 32 floats
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[wave * 1024 + acc_row(r, lane) * 32 + (lane & 31)] = acc[t][r];
+    __syncthreads();
+    for (int i = tid; i < 1024; i += 256) {
+      const float v = ((red[i] + red[1024 + i]) + red[2048 + i]) + red[3072 + i];
+      const int n = n0 + i / 32, c = c0 + i % 32;
+      if (n < a.N && c < a.Cin) prow[(size_t)n * NW + t * a.Cin + c] = v;
+    }
+  }
+}
+
 // Weight gradient: partial[s][n][t * Cin + c] over the pixel range of split s
 // (M = out channels a.N, N = taps * a.Cin, K = pixels).  a.in: the layer's
 // input, a.w: dz (gradient at the layer's pre-activation, a.N channels at
@@ -535,23 +680,6 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(lbfz_conv_args a, float* __r
   }
 }
 
-// 8-channel (16-byte) groups of bf16 activations: pooling, upsampling and the
-// bias gradient move whole groups (channel counts, strides and offsets are
-// multiples of 8, checked by the callers).
-union V8 {
-  uint4 u;
-  bf16 h[8];
-};
-
-__device__ __forceinline__ V8 ld8(const bf16* p) {
-  V8 v;
-  v.u = *reinterpret_cast<const uint4*>(p);
-  return v;
-}
-
-__device__ __forceinline__ void st8(bf16* p, const V8& v) {
-  *reinterpret_cast<uint4*>(p) = v.u;
-}
 
 // dst[i] = sum over s of part[s][i] (fixed order).
 __global__ void k_sum_splits(const float* __restrict__ part, int nsplit, long n,
@@ -789,9 +917,22 @@ __global__ __launch_bounds__(256) void k_plane_sums(const float* __restrict__ sr
                                                     long stride, double* __restrict__ out) {
   __shared__ double red[256];
   const float* p = src + blockIdx.x * stride;
-  double acc = 0.0;
-  for (long i = threadIdx.x; i < n; i += 256) acc += (double)p[i];
-  red[threadIdx.x] = acc;
+  // four independent accumulators over 16-byte loads (the plane start is
+  // 16-byte aligned when stride is a multiple of 4), then the scalar tail
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const bool vec = ((uintptr_t)p & 15) == 0;
+  const long n4 = vec ? n / 4 : 0;
+  const float4* p4 = reinterpret_cast<const float4*>(p);
+#pragma unroll 4
+  for (long i = threadIdx.x; i < n4; i += 256) {
+    const float4 v = p4[i];
+    a0 += (double)v.x;
+    a1 += (double)v.y;
+    a2 += (double)v.z;
+    a3 += (double)v.w;
+  }
+  for (long i = 4 * n4 + threadIdx.x; i < n; i += 256) a0 += (double)p[i];
+  red[threadIdx.x] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -1025,6 +1166,35 @@ int lbfz_nn_conv_wgrad(const lbfz_conv_args* a, float* part, int nsplit, float* 
     return LBFZ_NN_EINVAL;
   const long P = (long)a->B * a->H * a->W;
   const int NW = a->taps * a->Cin;
+  if (a->taps == 9) {
+    if ((a->up ? P / 4 : P) * a->in_cs * 2 >= (1L << 31) || P * a->dz_cs * 2 >= (1L << 31))
+      return LBFZ_NN_EINVAL;
+    // direct form: blocks of 32 output x 32 input channels, each walking a
+    // share of the pixel tiles (about 512 blocks in all, at most nsplit
+    // shares: one partial row per share)
+    const long tiles = (long)a->B * ((a->H + TH - 1) / TH) * ((a->W + TW - 1) / TW);
+    const long cblk = (long)((a->N + 31) / 32) * ((a->Cin + 31) / 32);
+    const int splits = (int)std::max<long>(
+        1, std::min<long>(std::min<long>(nsplit, tiles), (512 + cblk - 1) / cblk));
+    const dim3 grid((unsigned)splits, (unsigned)((a->N + 31) / 32),
+                    (unsigned)((a->Cin + 31) / 32));
+    if (a->up)
+      hipLaunchKernelGGL((k_conv_wgrad_direct<true>), grid, dim3(256), 0, (hipStream_t)stream,
+                         *a, part);
+    else
+      hipLaunchKernelGGL((k_conv_wgrad_direct<false>), grid, dim3(256), 0, (hipStream_t)stream,
+                         *a, part);
+    if (hipGetLastError() != hipSuccess) return LBFZ_NN_EHIP;
+    const long n = (long)a->N * NW;
+    const int rows = splits;
+    if (n <= 16384)
+      hipLaunchKernelGGL(k_sum_splits_small, dim3((unsigned)n), dim3(256), 0,
+                         (hipStream_t)stream, part, rows, (int)n, dw);
+    else
+      hipLaunchKernelGGL(k_sum_splits, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
+                         part, rows, n, dw);
+    HCHK();
+  }
   long kper = (P + nsplit - 1) / nsplit;
   kper = (kper + BK - 1) / BK * BK;
   const int ns = (int)((P + kper - 1) / kper);

@@ -315,7 +315,10 @@ class UNet:
         a.in_, a.in_cs, a.in_co, a.Cin = x.data_ptr(), x_cs, x_co, Ly.cin
         a.w, a.dz_cs, a.N = dz_p.data_ptr(), dz_cs, N
         a.B, a.H, a.W, a.taps, a.sign, a.up = B, H, W, Ly.taps, 1, int(up)
-        _ck(L.lbfz_nn_conv_wgrad(ctypes.byref(a), _p(self.part), self.nsplit,
+        # partial rows: the 3 x 3 kernel takes what the buffer holds for this
+        # layer, the 1 x 1 one a fixed split
+        rows = self.part.numel() // nw if Ly.taps == 9 else self.nsplit
+        _ck(L.lbfz_nn_conv_wgrad(ctypes.byref(a), _p(self.part), rows,
                                  ctypes.c_void_p(self.gf.data_ptr() + 4 * o), st),
             "wgrad " + name)
         _ck(L.lbfz_nn_bias_grad(_p(dz_p), P, dz_cs, N, _p(self.bpart), 256,
