@@ -1203,8 +1203,12 @@ int lbfz_nn_conv_wgrad(const lbfz_conv_args* a, float* part, int nsplit, float* 
   hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(256), 0, (hipStream_t)stream, *a, part, (int)kper);
   if (hipGetLastError() != hipSuccess) return LBFZ_NN_EHIP;
   const long n = (long)a->N * NW;
-  hipLaunchKernelGGL(k_sum_splits, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, part,
-                     ns, n, dw);
+  if (n <= 16384)
+    hipLaunchKernelGGL(k_sum_splits_small, dim3((unsigned)n), dim3(256), 0, (hipStream_t)stream,
+                       part, ns, (int)n, dw);
+  else
+    hipLaunchKernelGGL(k_sum_splits, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, part,
+                       ns, n, dw);
   HCHK();
 }
 

@@ -316,8 +316,8 @@ class UNet:
         a.w, a.dz_cs, a.N = dz_p.data_ptr(), dz_cs, N
         a.B, a.H, a.W, a.taps, a.sign, a.up = B, H, W, Ly.taps, 1, int(up)
         # partial rows: the 3 x 3 kernel takes what the buffer holds for this
-        # layer, the 1 x 1 one a fixed split
-        rows = self.part.numel() // nw if Ly.taps == 9 else self.nsplit
+        # layer (it uses about 512 blocks), the 1 x 1 one up to 1024 pixel splits
+        rows = self.part.numel() // nw if Ly.taps == 9 else min(self.part.numel() // nw, 1024)
         _ck(L.lbfz_nn_conv_wgrad(ctypes.byref(a), _p(self.part), rows,
                                  ctypes.c_void_p(self.gf.data_ptr() + 4 * o), st),
             "wgrad " + name)
