@@ -270,11 +270,11 @@ __global__ __launch_bounds__(NT) void k_close3d(KParams P, StepArgs A) {
     T = cl.T;
     fs = cl.fs;
   }
-  st(B.cfn, on, CF_PHI * PB, phi);
-  st(B.cfn, on, CF_T * PB, T);
-  st(B.cfn, on, CF_C * PB, C);
-  st(B.cfn, on, CF_FS * PB, fs);
-  st(B.cfn, on, CF_D * PB, D);
+  st_keep(B.cfn, on, CF_PHI * PB, phi);
+  st_keep(B.cfn, on, CF_T * PB, T);
+  st_keep(B.cfn, on, CF_C * PB, C);
+  st_keep(B.cfn, on, CF_FS * PB, fs);
+  st_keep(B.cfn, on, CF_D * PB, D);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,15 +386,15 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
   // against the reference refw = w_i r of the node it is stored at
   auto put = [&](rsrc_t set, uint32_t off, int slot, float v, float refw, float scale) {
     if constexpr (ST == LBFZ_STORE_F32)
-      st(set, off, slot * PB, v);
+      st_keep(set, off, slot * PB, v);
     else
-      st16(set, off >> 1, (slot - 1) * HB, enc16<ST>((v - refw) * scale));
+      st16_keep(set, off >> 1, (slot - 1) * HB, enc16<ST>((v - refw) * scale));
   };
   auto put_rest = [&](rsrc_t set, int slot32, int slot16, float v) {
     if constexpr (ST == LBFZ_STORE_F32)
-      st(set, on, slot32 * PB, v);
+      st_keep(set, on, slot32 * PB, v);
     else
-      st(B.drest, on, slot16 * PB, v);
+      st_keep(B.drest, on, slot16 * PB, v);
   };
   const float href_w = W7 * P.rhoc_ref;
 
@@ -409,15 +409,15 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
     }
     if (DRY) {
       float* const* o = A.out;
-      if (o[0]) st(rsrc(o[0], NB), on, 0, -1.0f);
-      if (o[1]) st(rsrc(o[1], NB), on, 0, 1.0f);
-      if (o[2]) st(rsrc(o[2], NB), on, 0, T);
-      if (o[3]) st(rsrc(o[3], NB), on, 0, 0.0f);
-      if (o[4]) st(rsrc(o[4], NB), on, 0, 0.0f);
-      if (o[5]) st(rsrc(o[5], NB), on, 0, 0.0f);
-      if (o[6]) st(rsrc(o[6], NB), on, 0, 0.0f);
-      if (o[7]) st(rsrc(o[7], NB), on, 0, 0.0f);
-      if (o[8]) st(rsrc(o[8], NB), on, 0, P.rho_g);
+      if (o[0]) st_keep(rsrc(o[0], NB), on, 0, -1.0f);
+      if (o[1]) st_keep(rsrc(o[1], NB), on, 0, 1.0f);
+      if (o[2]) st_keep(rsrc(o[2], NB), on, 0, T);
+      if (o[3]) st_keep(rsrc(o[3], NB), on, 0, 0.0f);
+      if (o[4]) st_keep(rsrc(o[4], NB), on, 0, 0.0f);
+      if (o[5]) st_keep(rsrc(o[5], NB), on, 0, 0.0f);
+      if (o[6]) st_keep(rsrc(o[6], NB), on, 0, 0.0f);
+      if (o[7]) st_keep(rsrc(o[7], NB), on, 0, 0.0f);
+      if (o[8]) st_keep(rsrc(o[8], NB), on, 0, P.rho_g);
       double dh = 0.0;
       float sh = 0.f;
 #pragma unroll
@@ -447,11 +447,11 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
           put(B.dh, target(i), i, hp, href_w * tref(1, i), SC_H);
         }
       }
-      st(rsrc(A.p_new, PB), on, 0, 0.0f);
+      st_keep(rsrc(A.p_new, PB), on, 0, 0.0f);
       const rsrc_t r_un = rsrc(A.u_new, 3 * PB);
-      st(r_un, on, 0, 0.0f);
-      st(r_un, on, PB, 0.0f);
-      st(r_un, on, 2 * PB, 0.0f);
+      st_keep(r_un, on, 0, 0.0f);
+      st_keep(r_un, on, PB, 0.0f);
+      st_keep(r_un, on, 2 * PB, 0.0f);
     }
   } else if (valid) {
     // stencils (isotropic D3Q19 gradient / Laplacian), one field per pass
@@ -542,15 +542,15 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
         (kCs2 / (1.0f - W19[0])) * (sum_nz + 0.5f * S_ + P.tau_g * G0 + rho * srest);
     if (DRY) {
       float* const* o = A.out;
-      if (o[0]) st(rsrc(o[0], NB), on, 0, phi);
-      if (o[1]) st(rsrc(o[1], NB), on, 0, 1.0f - fs);
-      if (o[2]) st(rsrc(o[2], NB), on, 0, T);
-      if (o[3]) st(rsrc(o[3], NB), on, 0, C);
-      if (o[4]) st(rsrc(o[4], NB), on, 0, u[0]);
-      if (o[5]) st(rsrc(o[5], NB), on, 0, u[1]);
-      if (o[6]) st(rsrc(o[6], NB), on, 0, u[2]);
-      if (o[7]) st(rsrc(o[7], NB), on, 0, pn);
-      if (o[8]) st(rsrc(o[8], NB), on, 0, rho);
+      if (o[0]) st_keep(rsrc(o[0], NB), on, 0, phi);
+      if (o[1]) st_keep(rsrc(o[1], NB), on, 0, 1.0f - fs);
+      if (o[2]) st_keep(rsrc(o[2], NB), on, 0, T);
+      if (o[3]) st_keep(rsrc(o[3], NB), on, 0, C);
+      if (o[4]) st_keep(rsrc(o[4], NB), on, 0, u[0]);
+      if (o[5]) st_keep(rsrc(o[5], NB), on, 0, u[1]);
+      if (o[6]) st_keep(rsrc(o[6], NB), on, 0, u[2]);
+      if (o[7]) st_keep(rsrc(o[7], NB), on, 0, pn);
+      if (o[8]) st_keep(rsrc(o[8], NB), on, 0, rho);
       double df = 0, dh = 0, dl = 0;
       bool bad = !isfinite(phi) || !isfinite(T) || !isfinite(pn) || !isfinite(uu);
 #pragma unroll
@@ -659,11 +659,11 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
             put(B.dl, target(i), i, post, W7 * tref(2, i), SC_L);
         }
       }
-      st(rsrc(A.p_new, PB), on, 0, pn);
+      st_keep(rsrc(A.p_new, PB), on, 0, pn);
       const rsrc_t r_un = rsrc(A.u_new, 3 * PB);
-      st(r_un, on, 0, u[0]);
-      st(r_un, on, PB, u[1]);
-      st(r_un, on, 2 * PB, u[2]);
+      st_keep(r_un, on, 0, u[0]);
+      st_keep(r_un, on, PB, u[1]);
+      st_keep(r_un, on, 2 * PB, u[2]);
     }
   }
   // per-tile FP64 reductions

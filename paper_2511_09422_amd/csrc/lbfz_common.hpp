@@ -141,20 +141,42 @@ __device__ __forceinline__ rsrc_t rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
                                            kBufWord3);
 }
+// Cache policy of the loads and stores: stores carry the non-temporal hint
+// (every plane a step writes is read only by the next step, after the whole
+// grid has streamed through the caches; 2048^2 FP32 step 208 -> 200 us),
+// loads the default policy (non-temporal loads lose the reuse of the halo
+// rows between neighbouring tiles: 254 us).
+#ifndef LBFZ_LD_AUX
+#define LBFZ_LD_AUX 0
+#endif
+#ifndef LBFZ_ST_AUX
+#define LBFZ_ST_AUX 2
+#endif
 __device__ __forceinline__ float ld(rsrc_t r, uint32_t off, uint32_t soff = 0) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff,
+                                                                          LBFZ_LD_AUX));
 }
 __device__ __forceinline__ void st(rsrc_t r, uint32_t off, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, (int)soff,
+                                        LBFZ_ST_AUX);
+}
+// Stores with the default cache policy: the 3D step's (its two launches read
+// the closure fields back at once, and its population writes measured
+// slower with the hint: 1.80 -> 1.89 ms at 256^3).
+__device__ __forceinline__ void st_keep(rsrc_t r, uint32_t off, uint32_t soff, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, (int)soff, 0);
 }
+__device__ __forceinline__ void st16_keep(rsrc_t r, uint32_t off, uint32_t soff, uint16_t v) {
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, (int)soff, 0);
+}
 __device__ __forceinline__ uint16_t ld16(rsrc_t r, uint32_t off, uint32_t soff) {
-  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0);
+  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, LBFZ_LD_AUX);
 }
 __device__ __forceinline__ uint8_t ld8(rsrc_t r, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
 }
 __device__ __forceinline__ void st16(rsrc_t r, uint32_t off, uint32_t soff, uint16_t v) {
-  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, (int)soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, (int)soff, LBFZ_ST_AUX);
 }
 
 // 16-bit storage: offsets from the reference are scaled by these powers of two
