@@ -56,6 +56,12 @@ typedef struct lbfz_conv_args {
                               image read through nearest 2x upsampling (pixel (y, x) takes
                               (y/2, x/2); H, W even), 0 = `in` is B x H x W.  Must be 0 for
                               the data gradient                                             */
+  void* pool;              /* 3 x 3 forward / data gradient with bf16 output: if not NULL,
+                              also write the 2x2 max pooling (stride 2) of the stored output
+                              here, a B x (H/2) x (W/2) image of N channels at channel
+                              stride pool_cs, offset pool_co (H, W even; as lbfz_nn_maxpool2
+                              of `out`, bit for bit)                                          */
+  int32_t pool_cs, pool_co;
 } lbfz_conv_args;
 
 /* Forward: out[p][n] = act(sum_{t,c} in[p + o(t)][c] W[n][t][c] + bias[n]);

@@ -323,40 +323,42 @@ __global__ __launch_bounds__(256) void k_conv(lbfz_conv_args a) {
 }
 
 // Direct 3 x 3 convolution (forward, data gradient, and the forward through
-// 2x upsampling): a block computes a TH x TW = 4 x 64 tile of output pixels of
+// 2x upsampling): a block computes a (4 RPW) x 64 tile of output pixels of
 // one image for BN = 32 FN output channels.  Per input-channel chunk of CC
-// (32, or 16) it stages the (TH + 2) x (TW + 2) haloed input tile and the chunk's
-// weights [n][tap][c] in LDS once, then every wave (one output row, 2 x FN
-// accumulators of 32 x 32) runs the nine taps' MFMAs reading its A fragments
-// from the tile at the tap's shift -- each input byte is loaded from memory
-// about 1.6 times instead of nine (the implicit GEMM above re-gathers it per
-// tap).  Tap shifts are compile-time (SIGN), so fragment addresses are one
+// (32, or 16) it stages the (4 RPW + 2) x 66 haloed input tile and the chunk's
+// weights [n][tap][c] in LDS once, then every wave (RPW output rows, 2 RPW x
+// FN accumulators of 32 x 32) runs the nine taps' MFMAs reading its A
+// fragments from the tile at the tap's shift -- each input byte is loaded
+// from memory 1.3 - 1.6 times instead of nine (the implicit GEMM above
+// re-gathers it per tap).  Tap shifts are compile-time (SIGN), so fragment addresses are one
 // per-lane base plus immediates.  The next chunk's loads are issued before
 // the current chunk's MFMAs.
 constexpr int TW = 64, TH = 4, HWD = TW + 2, HHT = TH + 2;
 
 // CC: input channels per chunk (32, or 16 for layers whose channel count is
 // not a multiple of 32, e.g. the 16-channel input layer)
-template <int FN, bool UP, int SIGN, int CC = 32>
+template <int FN, bool UP, int SIGN, int CC = 32, int RPW = 1>
 __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
   constexpr int BN_ = 32 * FN;
+  constexpr int TH_ = 4 * RPW, HH_ = TH_ + 2;  // tile rows (RPW per wave), halo rows
+  constexpr int FM = 2 * RPW;                  // A fragments per wave (32 pixels each)
   constexpr int HPS = CC + 8;            // LDS pixel stride (bf16), padded by 16 B
   constexpr int CPX = CC / 8;            // 16-byte chunks per pixel and chunk
-  constexpr int H_EL = HHT * HWD * HPS;  // haloed input tile [pixel][c]
+  constexpr int H_EL = HH_ * HWD * HPS;  // haloed input tile [pixel][c]
   constexpr int W_EL = BN_ * 9 * HPS;    // weights [n][tap][c]
-  constexpr int O_EL = TH * TW * BN_;    // bf16 output tile for the stores
+  constexpr int O_EL = TH_ * TW * BN_;   // bf16 output tile for the stores
   constexpr int SM_EL = (H_EL + W_EL) > O_EL ? (H_EL + W_EL) : O_EL;
-  constexpr int HE = HHT * HWD * CPX, HJ = (HE + 255) / 256;  // halo 16-byte chunks
+  constexpr int HE = HH_ * HWD * CPX, HJ = (HE + 255) / 256;  // halo 16-byte chunks
   constexpr int WE = BN_ * 9 * CPX, WJ = (WE + 255) / 256;    // weight 16-byte chunks
   __shared__ __align__(16) bf16 smem[SM_EL];
   bf16* Hs = smem;
   bf16* Ws = smem + H_EL;
-  const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + TH - 1) / TH;
+  const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + TH_ - 1) / TH_;
   const int nt = gridDim.x;
   int bx = blockIdx.x;
   if ((nt & 7) == 0) bx = (bx & 7) * (nt >> 3) + (bx >> 3);  // neighbouring tiles on one XCD
   const int b = bx / (tiles_y * tiles_x), rt = bx - b * (tiles_y * tiles_x);
-  const int y0 = (rt / tiles_x) * TH, x0 = (rt % tiles_x) * TW;
+  const int y0 = (rt / tiles_x) * TH_, x0 = (rt % tiles_x) * TW;
   const int n0 = blockIdx.y * BN_;
   const int M = a.B * a.H * a.W, K = 9 * a.Cin;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -397,15 +399,16 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
     for (int j = 0; j < WJ; ++j)
       wv[j] = ld16B(rw, (woff[j] != kOut && c0 + wq[j] < a.Cin) ? woff[j] + 2 * c0 : kOut);
   };
-  f32x16 acc[2][FN];
+  f32x16 acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
-  // fragment bases: A at halo pixel (wave, lane % 32) -- the (-1, -1) shift of
-  // output pixel (wave, lane % 32) -- and B at weight row lane % 32; the k
-  // half 8 (lane / 32)
-  const bf16* abase = Hs + (wave * HWD + (lane & 31)) * HPS + 8 * (lane >> 5);
+  // fragment bases: A at halo pixel (RPW wave, lane % 32) -- the (-1, -1)
+  // shift of output pixel (RPW wave, lane % 32) -- and B at weight row
+  // lane % 32; the k half 8 (lane / 32).  A fragment i covers output row
+  // RPW wave + i / 2, columns 32 (i % 2) ...
+  const bf16* abase = Hs + (RPW * wave * HWD + (lane & 31)) * HPS + 8 * (lane >> 5);
   const bf16* bbase = Ws + (lane & 31) * 9 * HPS + 8 * (lane >> 5);
   gload(0);
   for (int c0 = 0; c0 < a.Cin; c0 += CC) {
@@ -433,25 +436,26 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
       const int hy = 1 + SIGN * (t / 3 - 1), hx = 1 + SIGN * (t % 3 - 1);
 #pragma unroll
       for (int kk = 0; kk < CC; kk += 16) {
-        bf16x8 fa[2], fb[FN];
+        bf16x8 fa[FM], fb[FN];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-          fa[i] = *reinterpret_cast<const bf16x8*>(abase + (hy * HWD + hx + 32 * i) * HPS + kk);
+        for (int i = 0; i < FM; ++i)
+          fa[i] = *reinterpret_cast<const bf16x8*>(
+              abase + ((hy + i / 2) * HWD + hx + 32 * (i % 2)) * HPS + kk);
 #pragma unroll
         for (int j = 0; j < FN; ++j)
           fb[j] = *reinterpret_cast<const bf16x8*>(bbase + (32 * j * 9 + t) * HPS + kk);
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
       }
     }
   }
-  // epilogue: output pixel (y0 + wave, x0 + 32 i + row) and channel
-  // n0 + 32 j + lane % 32 of accumulator element r (row = acc_row(r, lane))
+  // epilogue: output pixel (y0 + RPW wave + i / 2, x0 + 32 (i % 2) + row)
+  // and channel n0 + 32 j + lane % 32 of accumulator element r (row =
+  // acc_row(r, lane))
   const float* bias = a.bias;
-  const int y = y0 + wave;
   if (!a.out_f32 && a.N % 8 == 0 && a.out_cs % 8 == 0 && a.out_co % 8 == 0) {
     bf16* Os = smem;
     __syncthreads();
@@ -460,17 +464,17 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
       const int col = 32 * j + (lane & 31);
       const float bv = (bias && n0 + col < a.N) ? bias[n0 + col] : 0.0f;
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           float v = acc[i][j][r] + bv;
           if (a.relu) v = fmaxf(v, 0.0f);
-          Os[(wave * TW + 32 * i + acc_row(r, lane)) * BN_ + col] = (bf16)v;
+          Os[((RPW * wave + i / 2) * TW + 32 * (i % 2) + acc_row(r, lane)) * BN_ + col] = (bf16)v;
         }
     }
     __syncthreads();
     constexpr int GPR = BN_ / 8;
-    for (int g = tid; g < TH * TW * GPR; g += 256) {
+    for (int g = tid; g < TH_ * TW * GPR; g += 256) {
       const int m = g / GPR, cg = g - m * GPR;
       const int yy = y0 + m / TW, xx = x0 + m % TW, cn = n0 + 8 * cg;
       if (yy < a.H && xx < a.W && cn < a.N)
@@ -478,19 +482,43 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
                                   ((size_t)(b * a.H + yy) * a.W + xx) * a.out_cs + a.out_co + cn) =
             *reinterpret_cast<const uint4*>(&Os[m * BN_ + 8 * cg]);
     }
+    if (a.pool) {
+      // fused 2 x 2 max pooling of the stored (bf16) output: the tile's rows
+      // and columns start even, so every window lies inside it
+      const int Ho = a.H >> 1, Wo = a.W >> 1;
+      for (int g = tid; g < (TH_ / 2) * (TW / 2) * GPR; g += 256) {
+        const int m = g / GPR, cg = g - m * GPR;
+        const int py = m / (TW / 2), px = m % (TW / 2);
+        const int yo = (y0 >> 1) + py, xo = (x0 >> 1) + px, cn = n0 + 8 * cg;
+        if (yo >= Ho || xo >= Wo || cn >= a.N) continue;
+        const int m00 = (2 * py) * TW + 2 * px;
+        V8 v0, v1, v2, v3, r;
+        v0.u = *reinterpret_cast<const uint4*>(&Os[m00 * BN_ + 8 * cg]);
+        v1.u = *reinterpret_cast<const uint4*>(&Os[(m00 + 1) * BN_ + 8 * cg]);
+        v2.u = *reinterpret_cast<const uint4*>(&Os[(m00 + TW) * BN_ + 8 * cg]);
+        v3.u = *reinterpret_cast<const uint4*>(&Os[(m00 + TW + 1) * BN_ + 8 * cg]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          r.h[e] = (bf16)fmaxf(fmaxf((float)v0.h[e], (float)v1.h[e]),
+                               fmaxf((float)v2.h[e], (float)v3.h[e]));
+        *reinterpret_cast<uint4*>(static_cast<bf16*>(a.pool) +
+                                  ((size_t)(b * Ho + yo) * Wo + xo) * a.pool_cs + a.pool_co + cn) = r.u;
+      }
+    }
     return;
   }
-  if (y >= a.H) return;
 #pragma unroll
   for (int j = 0; j < FN; ++j) {
     const int cn = n0 + 32 * j + (lane & 31);
     if (cn >= a.N) continue;
     const float bv = bias ? bias[cn] : 0.0f;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FM; ++i) {
+      const int y = y0 + RPW * wave + i / 2;
+      if (y >= a.H) continue;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int x = x0 + 32 * i + acc_row(r, lane);
+        const int x = x0 + 32 * (i % 2) + acc_row(r, lane);
         if (x >= a.W) continue;
         float v = acc[i][j][r] + bv;
         if (a.relu) v = fmaxf(v, 0.0f);
@@ -500,6 +528,7 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
         else
           static_cast<bf16*>(a.out)[o] = (bf16)v;
       }
+    }
   }
 }
 
@@ -1099,6 +1128,11 @@ static bool conv_ok(const lbfz_conv_args* a) {
 int lbfz_nn_conv(const lbfz_conv_args* a, void* stream) {
   if (!conv_ok(a) || !a->out || (a->sign != 1 && a->sign != -1) || (a->up && a->sign != 1))
     return LBFZ_NN_EINVAL;
+  // fused pooling: 3 x 3, bf16 output written whole 16-byte groups, even sizes
+  if (a->pool && (a->taps != 9 || a->out_f32 || a->N % 8 || a->out_cs % 8 || a->out_co % 8 ||
+                  a->pool_cs % 8 || a->pool_co % 8 || a->pool_co + a->N > a->pool_cs ||
+                  a->H % 2 || a->W % 2))
+    return LBFZ_NN_EINVAL;
   const long M = (long)a->B * a->H * a->W;
   // operands are addressed with 32-bit byte offsets below 2^31
   if (M >= (1L << 30) || (a->up ? M / 4 : M) * a->in_cs * 2 >= (1L << 31) ||
@@ -1106,33 +1140,34 @@ int lbfz_nn_conv(const lbfz_conv_args* a, void* stream) {
     return LBFZ_NN_EINVAL;
   const hipStream_t st = (hipStream_t)stream;
   if (a->taps == 9) {
-    // direct convolution over 4 x 64 pixel tiles, 64 output channels per
-    // block when N is a multiple of 64, else 32
-    const long tiles = (long)a->B * ((a->H + TH - 1) / TH) * ((a->W + TW - 1) / TW);
+    // direct convolution: 64 output channels per block over 4 x 64 pixel
+    // tiles when N is a multiple of 64; else 32 channels over 8 x 64 tiles
+    // (two output rows per wave: one weight fragment serves four pixel
+    // fragments)
+    const long nb = a->B, ty4 = (a->H + 3) / 4, ty8 = (a->H + 7) / 8, tx = (a->W + TW - 1) / TW;
+    const dim3 g64((unsigned)(nb * ty4 * tx), (unsigned)(a->N / 64));
+    const dim3 g32((unsigned)(nb * ty8 * tx), (unsigned)((a->N + 31) / 32));
+    const dim3 g32r1((unsigned)(nb * ty4 * tx), (unsigned)((a->N + 31) / 32));
     if (a->Cin % 32 != 0 && !a->up && a->sign == 1) {
       // 16-channel chunks: no half-empty chunk for e.g. a 16-channel input
       if (a->N % 64 == 0)
-        hipLaunchKernelGGL((k_conv_direct<2, false, 1, 16>), dim3((unsigned)tiles, a->N / 64),
-                           dim3(256), 0, st, *a);
+        hipLaunchKernelGGL((k_conv_direct<2, false, 1, 16>), g64, dim3(256), 0, st, *a);
       else
-        hipLaunchKernelGGL((k_conv_direct<1, false, 1, 16>),
-                           dim3((unsigned)tiles, (a->N + 31) / 32), dim3(256), 0, st, *a);
+        hipLaunchKernelGGL((k_conv_direct<1, false, 1, 16>), g32r1, dim3(256), 0, st, *a);
     } else if (a->N % 64 == 0) {
-      const dim3 grid((unsigned)tiles, (unsigned)(a->N / 64));
       if (a->up)
-        hipLaunchKernelGGL((k_conv_direct<2, true, 1>), grid, dim3(256), 0, st, *a);
+        hipLaunchKernelGGL((k_conv_direct<2, true, 1>), g64, dim3(256), 0, st, *a);
       else if (a->sign == 1)
-        hipLaunchKernelGGL((k_conv_direct<2, false, 1>), grid, dim3(256), 0, st, *a);
+        hipLaunchKernelGGL((k_conv_direct<2, false, 1>), g64, dim3(256), 0, st, *a);
       else
-        hipLaunchKernelGGL((k_conv_direct<2, false, -1>), grid, dim3(256), 0, st, *a);
+        hipLaunchKernelGGL((k_conv_direct<2, false, -1>), g64, dim3(256), 0, st, *a);
     } else {
-      const dim3 grid((unsigned)tiles, (unsigned)((a->N + 31) / 32));
       if (a->up)
-        hipLaunchKernelGGL((k_conv_direct<1, true, 1>), grid, dim3(256), 0, st, *a);
+        hipLaunchKernelGGL((k_conv_direct<1, true, 1, 32, 2>), g32, dim3(256), 0, st, *a);
       else if (a->sign == 1)
-        hipLaunchKernelGGL((k_conv_direct<1, false, 1>), grid, dim3(256), 0, st, *a);
+        hipLaunchKernelGGL((k_conv_direct<1, false, 1, 32, 2>), g32, dim3(256), 0, st, *a);
       else
-        hipLaunchKernelGGL((k_conv_direct<1, false, -1>), grid, dim3(256), 0, st, *a);
+        hipLaunchKernelGGL((k_conv_direct<1, false, -1, 32, 2>), g32, dim3(256), 0, st, *a);
     }
     HCHK();
   }

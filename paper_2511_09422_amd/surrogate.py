@@ -48,7 +48,8 @@ class lbfz_conv_args(ctypes.Structure):
                 ("out_cs", ctypes.c_int32), ("out_co", ctypes.c_int32),
                 ("out_f32", ctypes.c_int32), ("relu", ctypes.c_int32), ("sign", ctypes.c_int32),
                 ("B", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
-                ("taps", ctypes.c_int32), ("up", ctypes.c_int32)]
+                ("taps", ctypes.c_int32), ("up", ctypes.c_int32), ("pool", ctypes.c_void_p),
+                ("pool_cs", ctypes.c_int32), ("pool_co", ctypes.c_int32)]
 
 
 _nn = None
@@ -102,7 +103,7 @@ def _p(t):
 
 
 def conv_args(x, x_cs, x_co, cin, w, n, out, out_cs, out_co, B, H, W, taps, bias=None,
-              relu=False, sign=1, out_f32=False, dz_cs=0, up=False):
+              relu=False, sign=1, out_f32=False, dz_cs=0, up=False, pool=None, pool_cs=0):
     a = lbfz_conv_args()
     a.in_ = x.data_ptr()
     a.in_cs, a.in_co, a.Cin = x_cs, x_co, cin
@@ -115,6 +116,8 @@ def conv_args(x, x_cs, x_co, cin, w, n, out, out_cs, out_co, B, H, W, taps, bias
     a.relu, a.sign = int(relu), sign
     a.B, a.H, a.W, a.taps = B, H, W, taps
     a.up = int(up)
+    if pool is not None:
+        a.pool, a.pool_cs, a.pool_co = pool.data_ptr(), pool_cs, 0
     return a
 
 
@@ -252,7 +255,8 @@ class UNet:
         return self.B, s, s
 
     # ---------------------------------------------------------------- forward
-    def _conv(self, name, x, x_cs, x_co, out, out_cs, out_co, out_f32=False, up=False):
+    def _conv(self, name, x, x_cs, x_co, out, out_cs, out_co, out_f32=False, up=False,
+              pool=None, pool_cs=0):
         Ly = self.L[name]
         B, H, W = self._dims(Ly.level)
         wb, bias = self._w(name)
@@ -263,6 +267,8 @@ class UNet:
         a.out_cs, a.out_co, a.out_f32 = out_cs, out_co, int(out_f32)
         a.relu, a.sign = int(Ly.relu), 1
         a.B, a.H, a.W, a.taps, a.up = B, H, W, Ly.taps, int(up)
+        if pool is not None:
+            a.pool, a.pool_cs, a.pool_co = pool.data_ptr(), pool_cs, 0
         _ck(nnlib().lbfz_nn_conv(ctypes.byref(a), self.st), "conv " + name)
 
     def forward(self):
@@ -270,13 +276,10 @@ class UNet:
         L, t = nnlib(), self.t
         B, S = self.B, self.S
         self._conv("L1a", t["X0"], CIN0, 0, t["A1"], 32, 0)
-        self._conv("L1b", t["A1"], 32, 0, t["CAT1"], 64, 32)
-        _ck(L.lbfz_nn_maxpool2(_p(t["CAT1"]), 64, 32, _p(t["P1"]), 32, B, S, S, 32, self.st),
-            "pool1")
+        # the encoder's second convolutions also write the pooled tensors
+        self._conv("L1b", t["A1"], 32, 0, t["CAT1"], 64, 32, pool=t["P1"], pool_cs=32)
         self._conv("L2a", t["P1"], 32, 0, t["A2"], 64, 0)
-        self._conv("L2b", t["A2"], 64, 0, t["CAT2"], 128, 64)
-        _ck(L.lbfz_nn_maxpool2(_p(t["CAT2"]), 128, 64, _p(t["P2"]), 64, B, S // 2, S // 2, 64,
-                               self.st), "pool2")
+        self._conv("L2b", t["A2"], 64, 0, t["CAT2"], 128, 64, pool=t["P2"], pool_cs=64)
         self._conv("L3a", t["P2"], 64, 0, t["A3"], 128, 0)
         self._conv("L3b", t["A3"], 128, 0, t["A3b"], 128, 0)
         # the up-convolutions read the half-resolution tensor through nearest 2x

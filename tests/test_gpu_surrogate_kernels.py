@@ -133,6 +133,37 @@ def test_conv_reading_through_upsampling(B, h, w, Cin, N):
     assert L.lbfz_nn_conv(ctypes.byref(a), st) == sg.LBFZ_NN_EINVAL
 
 
+@pytest.mark.parametrize("B,H,W,Cin,N", [(2, 18, 22, 32, 32), (1, 10, 70, 32, 64)])
+def test_conv_with_fused_pooling(B, H, W, Cin, N):
+    """pool != NULL: the convolution also writes the 2 x 2 max pooling of its
+    stored output; bit for bit lbfz_nn_maxpool2 of that output (ragged tiles
+    in both directions; 32-wide and 64-wide tile shapes)."""
+    import torch
+    import ctypes
+    from paper_2511_09422_amd import surrogate as sg
+    rng = np.random.default_rng(H * W + N)
+    x = _bf16(rng.standard_normal((B, H, W, Cin)))
+    w9 = _bf16(rng.standard_normal((N, 9, Cin)) / np.sqrt(9 * Cin))
+    bias = rng.standard_normal(N).astype(np.float32)
+    L = sg.nnlib()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    dx_, dw_, db = _dev(x, torch.bfloat16), _dev(w9, torch.bfloat16), torch.tensor(bias).cuda()
+    cs = N + 8   # output at a channel offset inside a wider tensor, as in the network
+    y = torch.zeros(B * H * W * cs, dtype=torch.bfloat16).cuda()
+    pooled = torch.full((B * (H // 2) * (W // 2) * N,), 7.0, dtype=torch.bfloat16).cuda()
+    a = sg.conv_args(dx_, Cin, 0, Cin, dw_, N, y, cs, 8, B, H, W, 9, bias=db, relu=True,
+                     pool=pooled, pool_cs=N)
+    assert L.lbfz_nn_conv(ctypes.byref(a), st) == 0
+    ref = torch.zeros_like(pooled)
+    assert L.lbfz_nn_maxpool2(sg._p(y), cs, 8, sg._p(ref), N, B, H, W, N, st) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(pooled, ref)
+    # odd sizes are refused
+    a = sg.conv_args(dx_, Cin, 0, Cin, dw_, N, y, cs, 8, B, H - 1, W, 9, bias=db,
+                     pool=pooled, pool_cs=N)
+    assert L.lbfz_nn_conv(ctypes.byref(a), st) == sg.LBFZ_NN_EINVAL
+
+
 def test_pool_and_upsample():
     import torch
     import torch.nn.functional as F
