@@ -85,11 +85,33 @@ def cpu_baseline(cfg, phi, T, C, budget_s: float = 12.0) -> dict:
         if time.perf_counter() - t0 > budget_s or n >= 20:
             break
     dt = time.perf_counter() - t0
+    del o
     N = cfg["nx"] * cfg["ny"]
+    # the same oracle on one thread, two whole steps
+    o1 = Oracle(cfg, phi, T, C, threads=1)
+    o1.step(1)
+    t1 = time.perf_counter()
+    o1.step(2)
+    dt1 = time.perf_counter() - t1
+    del o1
     return {"value": round(N * n / dt / 1e6, 4), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{n} full steps of the {cfg['nx']}x{cfg['ny']} workload after one "
-                      f"untimed step, FP64, OpenMP over nodes"}
+                      f"untimed step, FP64, OpenMP over nodes",
+            "single_thread": {"value": round(N * 2 / dt1 / 1e6, 4), "unit": "MLUPS",
+                              "sample": "2 full steps after one untimed step"},
+            "cpu": cpu_model(), "nproc": os.cpu_count()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def load_traffic(kernel_tag: str):
@@ -137,6 +159,30 @@ def time_form(cfg, phi, T, C, storage: str, warmup: int, steps: int, mask=None) 
     achieved = bpn * N / (ms_per_step * 1e-3) / 1e9
     return {"ms_per_step": ms_per_step, "mlups": N / (ms_per_step * 1e-3) / 1e6,
             "bytes_per_node": bpn, "achieved": achieved, "wall": wall}
+
+
+def time_copy(nbytes: int, reps: int = 20) -> dict:
+    """A plain device-to-device copy that reads and writes nbytes in total
+    (nbytes / 2 each way), timed with HIP events: the bandwidth this memory
+    system gives a pure streaming kernel of the same volume as one step."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes": 8 * n, "us": ms * 1e3, "GBs": 8 * n / (ms * 1e-3) / 1e9}
 
 
 def time_sweep(ncases: int, steps: int, case_steps: int, storage: str) -> dict:
@@ -344,6 +390,9 @@ def main():
     main_r = time_form(cfg, phi, T, C, args.storage, args.warmup, args.steps)
     print(f"bench: {args.storage} {main_r['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr,
           flush=True)
+    copy_r = time_copy(main_r["bytes_per_node"] * n * n)
+    print(f"bench: copy of the same {copy_r['bytes'] / 1e6:.0f} MB {copy_r['us']:.2f} us "
+          f"({copy_r['GBs']:.0f} GB/s)", file=sys.stderr, flush=True)
     other = {}
     for f in forms:
         r = time_form(cfg, phi, T, C, f, args.warmup, args.steps)
@@ -417,6 +466,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(main_r["achieved"] / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic(f"k_step2d_{args.storage}_{n}")},
+        "copy_ceiling": {"bytes": copy_r["bytes"], "us": round(copy_r["us"], 2),
+                         "GB/s": round(copy_r["GBs"], 1),
+                         "frac_of_peak": round(copy_r["GBs"] / HBM_PEAK_GBS, 4),
+                         "step_vs_copy": round(main_r["achieved"] / copy_r["GBs"], 4)},
     }
     if other:
         out["storage_forms"] = other

@@ -636,7 +636,9 @@ __device__ __forceinline__ void step2d_tile(const KParams& P, const StepArgs& A,
 
 template <bool DRY, int ST, int TY>
 __global__ __launch_bounds__(Geo<TY>::NT) LBFZ_OCC void k_step2d(KParams P, StepArgs A) {
-  step2d_tile<DRY, ST, TY>(P, A, xcd_tile(blockIdx.x, P.nblk));
+  // consecutive steps walk the tiles in opposite directions
+  step2d_tile<DRY, ST, TY>(
+      P, A, A.rev ? xcd_tile_rev(blockIdx.x, P.nblk) : xcd_tile(blockIdx.x, P.nblk));
 }
 
 // Batched sweep: every (case, tile) of one step of many grids in one launch.

@@ -174,14 +174,15 @@ __device__ __forceinline__ void load_g3(const Bufs3& B, uint32_t o, float* g) {
   }
 }
 
-// Tile of a block: (x0, y0, z) in XCD-aware order; one row per wave.
+// Tile of a block: (x0, y0, z) in XCD-aware order (rev: each band walked
+// backwards); one row per wave.
 struct Tile3 {
   int tile, x0, y0, z, tx, ty, gx, gy;
   bool valid;
 };
-__device__ __forceinline__ Tile3 tile3(const KParams& P) {
+__device__ __forceinline__ Tile3 tile3(const KParams& P, bool rev) {
   Tile3 t;
-  t.tile = xcd_tile(blockIdx.x, P.nblk);
+  t.tile = rev ? xcd_tile_rev(blockIdx.x, P.nblk) : xcd_tile(blockIdx.x, P.nblk);
   const int txy = P.nblk_x * P.nblk_y;
   t.z = t.tile / txy;
   const int r = t.tile - t.z * txy;
@@ -201,7 +202,7 @@ template <int ST>
 __global__ __launch_bounds__(NT) void k_close3d(KParams P, StepArgs A) {
   __shared__ float s_u[3][RS];  // previous velocity on the 1-ring, 3 planes
   __shared__ uint8_t s_m[RS];   // obstacle mask on the ring (ghost planes: 0)
-  const Tile3 t = tile3(P);
+  const Tile3 t = tile3(P, false);
   const Bufs3 B = make_bufs3<ST>(P, A);
   const uint32_t PB = B.pb;
   const int omx = wrap_near(t.gx, P.nx), omy = wrap_near(t.gy, P.ny);
@@ -284,7 +285,9 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
   __shared__ float s_c[5][RS];  // phi, T, C, f_s, p^{n-1} on the 1-ring, 3 planes
   __shared__ uint8_t s_m[RS];
   __shared__ double s_red[NT / 64];
-  const Tile3 t = tile3(P);
+  // the tiles in reverse: the collision starts where the closure launch
+  // ended, and the next closure where this launch ends
+  const Tile3 t = tile3(P, true);
   const Bufs3 B = make_bufs3<ST>(P, A);
   const uint32_t PB = B.pb, HB = B.hb, NB = (uint32_t)P.N * 4u;
   const int nx = P.nx, ny = P.ny, nz = P.nz;

@@ -226,6 +226,7 @@ StepArgs base_args(lbfz_handle* h) {
   }
   a.mask = h->mask;
   a.mpc_part = h->mpc_part;
+  a.rev = (int)(h->step & 1);
   return a;
 }
 

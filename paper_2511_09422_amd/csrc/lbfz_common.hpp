@@ -213,5 +213,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
   if (per == 0 || (nblk & 7)) return b;
   return (b & 7) * per + (b >> 3);
 }
+// The same bands, each walked from its last tile to its first.  A launch that
+// follows one walked forward starts on the tiles whose data the previous
+// launch touched last, while part of it is still in the memory-side cache
+// (bit-identical results: tiles are independent and per-tile partial sums are
+// indexed by tile).
+__device__ __forceinline__ int xcd_tile_rev(int b, int nblk) {
+  const int per = nblk >> 3;
+  if (per == 0 || (nblk & 7)) return nblk - 1 - b;
+  return (b & 7) * per + (per - 1 - (b >> 3));
+}
 
 }  // namespace lbfz

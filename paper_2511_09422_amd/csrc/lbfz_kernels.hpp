@@ -38,6 +38,7 @@ struct StepArgs {
   double* mpc_part;     // [ntiles]
   float* out[9];
   double* tot_part;     // [ntiles][8]
+  int rev;              // 2D: walk the tiles in reverse (odd steps)
 };
 
 // Buffers the initial state is written to (pop: the buffer the first step
