@@ -151,3 +151,78 @@ def test_3d_64_copy_conservation_and_one_step():
     got, ref = s.fields(), o.fields()
     for k in FIELDS:
         assert rel_linf(got[k], ref[k], mask) <= 2e-5, k
+
+
+def _window(a, x0, y0, w):
+    """Columns x0 .. x0 + w - 1, rows y0 .. y0 + w - 1 (periodic) of every z
+    plane of a [..., z, y, x] array."""
+    nx, ny = a.shape[-1], a.shape[-2]
+    xs = np.arange(x0, x0 + w) % nx
+    ys = np.arange(y0, y0 + w) % ny
+    return np.take(np.take(a, ys, axis=-2), xs, axis=-1)
+
+
+def test_full_size_256_3d_windows():
+    """The 256^3 droplet with its obstacle (the benchmark's workload and
+    launch configuration): conservation over 200 steps, then one more step
+    checked on 24 x 24 x 256 column windows.  The oracle steps each window of
+    the GPU's state on its own (periodic in x and y: only the 16 x 16 core,
+    four nodes from the window's edge, outside the one-step dependency radius
+    of three nodes, is compared), within 2e-5 on every population, previous-
+    level field and macroscopic field.  As in the whole-grid tests the error
+    is relative to the quantity's maximum over the grid: for each state plane
+    and for the fields the state carries (phi, C, u, p) that maximum is taken
+    from the common input state, else (f_l, T: order-one fields) from the
+    window.  Windows: through the obstacle, across the contact line, and
+    through the droplet's top."""
+    cfg, phi, T, C, mask = droplet_3d(256, R=64.0, imp_R=12.0, seed=1)
+    assert cfg.get("T_lo_amp", 0.0) == 0.0  # the wall rule must not depend on x
+    n, W, M = 256, 24, 4
+    s = _solver(cfg, phi, T, C, mask)
+    t0 = s.totals()
+    s.step(200)
+    t1 = s.totals()
+    assert t1["nonfinite"] == 0
+    norm = np.abs(phi[mask == 0]).sum()
+    assert abs(t1["sum_f"] - t0["sum_f"] - t1["mpc"]) <= 1e-5 * norm
+    assert abs(t1["sum_l"] - t0["sum_l"]) <= 1e-5 * t0["sum_l"]
+    st0 = s.get_state()
+    # grid-wide maxima of the input state's planes (f_s, p, u, phi, C of the
+    # previous level at 40 .. 46)
+    plane_max = np.abs(st0).reshape(st0.shape[0], -1).max(axis=1).astype(np.float64)
+    field_plane = {"p": 41, "ux": 42, "uy": 43, "uz": 44, "phi": 45, "C": 46}
+    s.step(1)
+    st1 = s.get_state()
+    got_all = s.fields()
+    zi, yi, xi = np.nonzero(mask)
+    ox, oy = int(round(xi.mean())), int(round(yi.mean()))
+    windows = {"obstacle": (ox - W // 2, oy - W // 2),
+               "contact_line": (n // 2 + 64 - W // 2, n // 2 - W // 2),
+               "top": (n // 2 - W // 2, n // 2 + 40 - W // 2)}
+    del phi, T, C
+    for name, (x0, y0) in windows.items():
+        wcfg = dict(cfg, nx=W, ny=W)
+        wmask = np.ascontiguousarray(_window(mask, x0, y0, W))
+        o = _oracle_from_state(wcfg, _window(st0, x0, y0, W), (n, W, W), wmask)
+        o.step(1)
+        core = (slice(None), slice(M, W - M), slice(M, W - M))
+        ref, keep = o.fields(), wmask[core] == 0
+        worst = {}
+        for k in FIELDS:
+            g = _window(got_all[k], x0, y0, W)[core][keep]
+            r = ref[k][core][keep]
+            scale = max(np.abs(r).max(), plane_max[field_plane[k]] if k in field_plane else 0.0)
+            e = float(np.abs(g - r).max() / max(scale, 1e-30))
+            worst[k] = e
+            assert e <= 2e-5, (name, k, e)
+        gw = _window(st1, x0, y0, W).astype(np.float64)
+        ow = np.concatenate([o.get_pops(0), o.get_pops(1), o.get_pops(2), o.get_pops(3)] +
+                            [o.get_state(w)[None] for w in range(7)])
+        for q in range(ow.shape[0]):
+            g, r = gw[q][core][keep], ow[q][core][keep]
+            e = float(np.abs(g - r).max() / max(np.abs(r).max(), plane_max[q], 1e-30))
+            assert e <= 2e-5, (name, "plane", q, e)
+        print(f"[window3d] {name} at ({x0}, {y0}): " +
+              " ".join(f"{k}={v:.1e}" for k, v in worst.items()) +
+              f"; {ow.shape[0]} planes within 2e-5", flush=True)
+        del o
