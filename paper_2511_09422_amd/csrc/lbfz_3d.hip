@@ -3,13 +3,13 @@
 // h (TRT) and solute l; walls on z, periodic x and y; optional obstacle mask
 // (bounce-back for f, g, l; h conducts through it).
 //
-// Two launches per step, each one node per thread on 64 x 4 xy tiles of one
-// z plane (one tile row per wave):
+// Two launches per step, each one node per thread on tiles of 64 x TY x TZ
+// nodes (FP32 storage 64 x 1 x 4, 16-bit 64 x 2 x 2; one x row per wave):
 //   k_close3d    the pointwise closure of every node -- phi, T, C, f_s from
 //                its f, h, l populations and div u^{n-1} from a velocity ring
 //                staged in LDS -- into the closure-field buffer of the level;
-//   k_collide3d  stencils of phi, T, C, f_s and p^{n-1} from a 1-ring staged
-//                in LDS (3 planes), forces, velocity, pressure, the four
+//   k_collide3d  stencils of phi, T, C, f_s and p^{n-1} from the tile and
+//                its 1-ring staged in LDS, forces, velocity, pressure, the four
 //                collisions and push streaming into the other population
 //                buffer.
 // The closure-field buffers (phi, T, C, f_s, div u) are double-buffered: the
@@ -35,10 +35,22 @@ namespace lbfz {
 
 namespace {
 
-constexpr int TX = 64, TY = 4, NT = TX * TY;
-constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY;  // 1-ring, per plane
-constexpr int RS = 3 * HP;                             // ring slots, 3 planes
-constexpr int RIT = (RS + NT - 1) / NT;                // ring slots per thread
+// Tile of one block: 64 x TY x TZ nodes, one x row per wave, 256 threads.
+// A tile that spans several z planes re-reads fewer ring planes per node
+// (2 / TZ) from beyond the L2; at 256^3 FP32 storage runs fastest with
+// 64 x 1 x 4 tiles (1.776 -> 1.734 ms per step against 64 x 4 x 1), 16-bit
+// storage with 64 x 2 x 2 (1.393 -> 1.379 ms; 64 x 1 x 4: 1.424 ms).
+constexpr int TX = 64, NT = 256, HX = TX + 2;
+template <int ST>
+struct G3 {
+  static constexpr int TY = ST == LBFZ_STORE_F32 ? 1 : 2;
+  static constexpr int TZ = NT / (TX * TY);
+  static constexpr int HY = TY + 2, HZ = TZ + 2;  // tile + 1-ring
+  static constexpr int HP = HX * HY;              // ring slots per plane
+  static constexpr int RS = HZ * HP;              // ring slots
+  static constexpr int RIT = (RS + NT - 1) / NT;  // ring slots per thread
+  static_assert(TX * TY * TZ == NT, "tile shape");
+};
 
 constexpr int PF = 0, PG = 7, PH = 26, PL = 33;  // FP32 layout
 // 16-bit layout: FP32 rest planes, then the first 16-bit plane of each set
@@ -76,7 +88,8 @@ __device__ __forceinline__ uint32_t node3(const KParams& P, int x, int y, int z)
   return (((uint32_t)z * (uint32_t)P.ny + (uint32_t)y) * (uint32_t)P.nx + (uint32_t)x) * 4u;
 }
 
-// Ring slot s (0 <= s < RS) -> (plane 0..2, row 0..HY-1, column 0..HX-1).
+// Ring slot s (0 <= s < RS) -> (plane 0..HZ-1, row 0..HY-1, column 0..HX-1).
+template <int HP>
 __device__ __forceinline__ void ring_pos(int s, int& pz, int& ly, int& lx) {
   pz = s / HP;
   const int r = s - pz * HP;
@@ -177,22 +190,27 @@ __device__ __forceinline__ void load_g3(const Bufs3& B, uint32_t o, float* g) {
 // Tile of a block: (x0, y0, z) in XCD-aware order (rev: each band walked
 // backwards); one row per wave.
 struct Tile3 {
-  int tile, x0, y0, z, tx, ty, gx, gy;
+  int tile, x0, y0, z0, tx, ty, tz, gx, gy, z;  // z: own plane, clamped into the grid
   bool valid;
 };
+template <int TY, int TZ>
 __device__ __forceinline__ Tile3 tile3(const KParams& P, bool rev) {
   Tile3 t;
   t.tile = rev ? xcd_tile_rev(blockIdx.x, P.nblk) : xcd_tile(blockIdx.x, P.nblk);
   const int txy = P.nblk_x * P.nblk_y;
-  t.z = t.tile / txy;
-  const int r = t.tile - t.z * txy;
+  const int bz = t.tile / txy;
+  const int r = t.tile - bz * txy;
   t.x0 = (r % P.nblk_x) * TX;
   t.y0 = (r / P.nblk_x) * TY;
+  t.z0 = bz * TZ;
   t.tx = threadIdx.x & (TX - 1);
-  t.ty = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // wave = x row
+  t.ty = w % TY;
+  t.tz = w / TY;
   t.gx = t.x0 + t.tx;
   t.gy = t.y0 + t.ty;
-  t.valid = t.gx < P.nx && t.gy < P.ny;
+  t.valid = t.gx < P.nx && t.gy < P.ny && t.z0 + t.tz < P.nz;
+  t.z = min(t.z0 + t.tz, P.nz - 1);
   return t;
 }
 
@@ -200,9 +218,11 @@ __device__ __forceinline__ Tile3 tile3(const KParams& P, bool rev) {
 // Closure: phi, T, C, f_s and div u^{n-1} of every node (Sec. 3.1, 3.3, Eq. NS1).
 template <int ST>
 __global__ __launch_bounds__(NT) void k_close3d(KParams P, StepArgs A) {
-  __shared__ float s_u[3][RS];  // previous velocity on the 1-ring, 3 planes
+  using G = G3<ST>;
+  constexpr int HP = G::HP, RS = G::RS, RIT = G::RIT;
+  __shared__ float s_u[3][RS];  // previous velocity on the tile + 1-ring
   __shared__ uint8_t s_m[RS];   // obstacle mask on the ring (ghost planes: 0)
-  const Tile3 t = tile3(P, false);
+  const Tile3 t = tile3<G::TY, G::TZ>(P, false);
   const Bufs3 B = make_bufs3<ST>(P, A);
   const uint32_t PB = B.pb;
   const int omx = wrap_near(t.gx, P.nx), omy = wrap_near(t.gy, P.ny);
@@ -217,8 +237,8 @@ __global__ __launch_bounds__(NT) void k_close3d(KParams P, StepArgs A) {
   for (int j = 0; j < RIT; ++j) {
     const int s = min((int)threadIdx.x + j * NT, RS - 1);
     int pz, ly, lx, ghost;
-    ring_pos(s, pz, ly, lx);
-    const int kz = map_z(P, t.z - 1 + pz, ghost);
+    ring_pos<HP>(s, pz, ly, lx);
+    const int kz = map_z(P, t.z0 - 1 + pz, ghost);
     const uint32_t o =
         node3(P, wrap_near(t.x0 + lx - 1, P.nx), wrap_near(t.y0 + ly - 1, P.ny), kz);
     sg[j] = ghost ? -1.0f : 1.0f;  // no-slip walls: negated mirror
@@ -253,7 +273,7 @@ __global__ __launch_bounds__(NT) void k_close3d(KParams P, StepArgs A) {
     D = 0.0f;
   } else {
     // div u^{n-1}: D3Q19 isotropic gradient; obstacle neighbours give -u(centre)
-    const int c = HP + (t.ty + 1) * HX + (t.tx + 1);
+    const int c = (t.tz + 1) * HP + (t.ty + 1) * HX + (t.tx + 1);
     float acc = 0.0f;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
@@ -282,12 +302,14 @@ __global__ __launch_bounds__(NT) void k_close3d(KParams P, StepArgs A) {
 // Collision and streaming (Sec. 3.1-3.4, walls Sec. 4.5).
 template <bool DRY, int ST>
 __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
-  __shared__ float s_c[5][RS];  // phi, T, C, f_s, p^{n-1} on the 1-ring, 3 planes
+  using G = G3<ST>;
+  constexpr int HP = G::HP, RS = G::RS, RIT = G::RIT;
+  __shared__ float s_c[5][RS];  // phi, T, C, f_s, p^{n-1} on the tile + 1-ring
   __shared__ uint8_t s_m[RS];
   __shared__ double s_red[NT / 64];
   // the tiles in reverse: the collision starts where the closure launch
   // ended, and the next closure where this launch ends
-  const Tile3 t = tile3(P, true);
+  const Tile3 t = tile3<G::TY, G::TZ>(P, true);
   const Bufs3 B = make_bufs3<ST>(P, A);
   const uint32_t PB = B.pb, HB = B.hb, NB = (uint32_t)P.N * 4u;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
@@ -308,8 +330,8 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
   for (int j = 0; j < RIT; ++j) {
     const int s = min((int)threadIdx.x + j * NT, RS - 1);
     int pz, ly, lx, ghost;
-    ring_pos(s, pz, ly, lx);
-    const int kz = map_z(P, t.z - 1 + pz, ghost);
+    ring_pos<HP>(s, pz, ly, lx);
+    const int kz = map_z(P, t.z0 - 1 + pz, ghost);
     const int mx = wrap_near(t.x0 + lx - 1, nx);
     const uint32_t o = node3(P, mx, wrap_near(t.y0 + ly - 1, ny), kz);
 #pragma unroll
@@ -338,7 +360,7 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
   }
   __syncthreads();
 
-  const int c = HP + (t.ty + 1) * HX + (t.tx + 1);  // own ring slot
+  const int c = (t.tz + 1) * HP + (t.ty + 1) * HX + (t.tx + 1);  // own ring slot
   const bool valid = t.valid;
   const bool ob = s_m[c] != 0;
   double mpc_acc = 0.0;
@@ -826,10 +848,12 @@ void launch_step3d_st(const KParams& P, const StepArgs& A, bool dry, hipStream_t
 
 }  // namespace
 
-int tiles3d(int nx, int ny, int nz, int* nbx, int* nby, int* nbz) {
+int tiles3d(int nx, int ny, int nz, int storage, int* nbx, int* nby, int* nbz) {
+  const int ty = storage == LBFZ_STORE_F32 ? G3<LBFZ_STORE_F32>::TY : G3<LBFZ_STORE_F16>::TY;
+  const int tz = storage == LBFZ_STORE_F32 ? G3<LBFZ_STORE_F32>::TZ : G3<LBFZ_STORE_F16>::TZ;
   *nbx = (nx + TX - 1) / TX;
-  *nby = (ny + TY - 1) / TY;
-  *nbz = nz;
+  *nby = (ny + ty - 1) / ty;
+  *nbz = (nz + tz - 1) / tz;
   return (*nbx) * (*nby) * (*nbz);
 }
 

@@ -61,7 +61,7 @@ int check_support(const lbfz_params* p) {
 int npop_of(const lbfz_params* p) { return p->dim == 3 ? 40 : 24; }
 
 int tiles_of(const lbfz_params* p, int* nbx, int* nby, int* nbz) {
-  if (p->dim == 3) return tiles3d(p->nx, p->ny, p->nz, nbx, nby, nbz);
+  if (p->dim == 3) return tiles3d(p->nx, p->ny, p->nz, p->storage, nbx, nby, nbz);
   *nbz = 1;
   return tiles2d(p->nx, p->ny, nbx, nby);
 }

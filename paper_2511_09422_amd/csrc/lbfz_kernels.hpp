@@ -79,7 +79,7 @@ struct StatePlanes {
 hipError_t launch_equil2d(const KParams& P, const EquilFields& F, const StatePlanes& S,
                           hipStream_t st);
 
-int tiles3d(int nx, int ny, int nz, int* nbx, int* nby, int* nbz);
+int tiles3d(int nx, int ny, int nz, int storage, int* nbx, int* nby, int* nbz);
 size_t pop_bytes3d(int storage, size_t ps);
 hipError_t launch_init3d(const KParams& P, int storage, const double* phi, const double* T,
                          const double* C, const uint8_t* mask, float* popA, float* popB,
