@@ -212,8 +212,10 @@ int lbfz_batch_totals(lbfz_batch* b, int32_t i, lbfz_totals_t* out);
 /* The fields of every grid into one device buffer (asynchronous): grid i's
  * fields of the set bits of field_mask (bit order), one plane of its N
  * values after the other, from d_dst + i * case_stride (floats; case_stride
- * >= the number of set bits times the largest N).  LBFZ_EINVAL if a grid is
- * stale. */
+ * >= the number of set bits times the largest N).  One launch per group of
+ * equal-sized grids; the values agree with lbfz_batch_fields up to FP32
+ * rounding (the batched kernel forms its fused multiply-adds differently).
+ * LBFZ_EINVAL if a grid is stale, LBFZ_EHIP if a launch fails. */
 int lbfz_batch_fields_all(lbfz_batch* b, uint32_t field_mask, float* d_dst, int64_t case_stride);
 
 /* Subset stepping (the LB fallback of a screened sweep): later steps advance

@@ -659,6 +659,34 @@ __global__ __launch_bounds__(Geo<TY>::NT) void k_step2d_batch(
   }
 }
 
+// Fields of many grids in one launch: the dry pass (the step's closure, forces
+// and velocity, no collision) over the same (case, tile) items, the fields
+// selected by `mask` (bit k: field k of lbfz_fields) written to grid c's
+// slice dst + c * case_stride, one plane of N_c values per selected field in
+// the order of the bits.
+template <int ST, int TY>
+__global__ __launch_bounds__(Geo<TY>::NT) void k_fields2d_batch(
+    const BatchCase* __restrict__ cases, const int2* __restrict__ work, int nwork, int slot,
+    float* __restrict__ dst, long case_stride, uint32_t mask) {
+  for (int e = blockIdx.x; e < nwork; e += gridDim.x) {
+    const int2 w = work[e];
+    const int c = __builtin_amdgcn_readfirstlane(w.x);
+    const int tile = __builtin_amdgcn_readfirstlane(w.y);
+    StepArgs A = cases[c].A[slot];
+    const long N = cases[c].P.N;
+    float* base = dst + (long)c * case_stride;
+    int r = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      A.out[k] = ((mask >> k) & 1u) ? base + (long)r * N : nullptr;
+      r += (mask >> k) & 1u;
+    }
+    A.tot_part = nullptr;
+    step2d_tile<true, ST, TY>(cases[c].P, A, tile);
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
 // Equilibrium populations of the initial fields (u = 0, p = 0) and the zero
 // previous-level state.  16-bit: every moving population sits exactly at its
 // reference (offset 0), and the references phi, C, T are stored.
@@ -929,6 +957,29 @@ hipError_t launch_step2d_batch(int storage, int ty, const BatchCase* cases, cons
     case LBFZ_STORE_F16 * 16 + 8: launch_batch_st<LBFZ_STORE_F16, 8>(cases, work, nwork, grid, slot, st); break;
     case LBFZ_STORE_BF16 * 16 + 4: launch_batch_st<LBFZ_STORE_BF16, 4>(cases, work, nwork, grid, slot, st); break;
     case LBFZ_STORE_BF16 * 16 + 8: launch_batch_st<LBFZ_STORE_BF16, 8>(cases, work, nwork, grid, slot, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int ST, int TY>
+static void launch_fields_batch_st(const BatchCase* cases, const int2* work, int nwork, int slot,
+                                   float* dst, long case_stride, uint32_t mask, hipStream_t st) {
+  hipLaunchKernelGGL((k_fields2d_batch<ST, TY>), dim3(nwork), dim3(Geo<TY>::NT), 0, st, cases,
+                     work, nwork, slot, dst, case_stride, mask);
+}
+
+hipError_t launch_fields2d_batch(int storage, int ty, const BatchCase* cases, const int2* work,
+                                 int nwork, int slot, float* dst, long case_stride,
+                                 uint32_t mask, hipStream_t st) {
+  if (nwork <= 0) return hipSuccess;
+  switch (storage * 16 + ty) {
+    case LBFZ_STORE_F32 * 16 + 4: launch_fields_batch_st<LBFZ_STORE_F32, 4>(cases, work, nwork, slot, dst, case_stride, mask, st); break;
+    case LBFZ_STORE_F32 * 16 + 8: launch_fields_batch_st<LBFZ_STORE_F32, 8>(cases, work, nwork, slot, dst, case_stride, mask, st); break;
+    case LBFZ_STORE_F16 * 16 + 4: launch_fields_batch_st<LBFZ_STORE_F16, 4>(cases, work, nwork, slot, dst, case_stride, mask, st); break;
+    case LBFZ_STORE_F16 * 16 + 8: launch_fields_batch_st<LBFZ_STORE_F16, 8>(cases, work, nwork, slot, dst, case_stride, mask, st); break;
+    case LBFZ_STORE_BF16 * 16 + 4: launch_fields_batch_st<LBFZ_STORE_BF16, 4>(cases, work, nwork, slot, dst, case_stride, mask, st); break;
+    case LBFZ_STORE_BF16 * 16 + 8: launch_fields_batch_st<LBFZ_STORE_BF16, 8>(cases, work, nwork, slot, dst, case_stride, mask, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

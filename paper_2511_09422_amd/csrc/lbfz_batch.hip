@@ -430,14 +430,12 @@ int lbfz_batch_fields_all(lbfz_batch* b, uint32_t field_mask, float* d_dst, int6
     if (b->stale[i] || case_stride < nf * N) return LBFZ_EINVAL;
   }
   sync_handles(b);
-  for (int i = 0; i < b->ncases; ++i) {
-    const int64_t N = (int64_t)b->h[i]->kp.N;
-    float* dst[9] = {};
-    int r = 0;
-    for (int k = 0; k < 9; ++k)
-      if ((field_mask >> k) & 1) dst[k] = d_dst + i * case_stride + (r++) * N;
-    const int rc = lbfz_fields(b->h[i], field_mask, dst, 1);
-    if (rc != LBFZ_OK) return rc;
+  // one dry-pass launch per group over all of its (grid, tile) items
+  const int slot = (int)(b->step % b->L);
+  for (const auto& g : b->groups) {
+    const int v = g.ty_index;
+    HIPCHK(launch_fields2d_batch(b->storage, kTY[v], b->d_cases, g.work[v], g.nwork[v], slot,
+                                 d_dst, (long)case_stride, field_mask, b->stream));
   }
   return LBFZ_OK;
 }

@@ -63,6 +63,9 @@ hipError_t launch_step2d(const KParams& P, int storage, const StepArgs& A, bool 
                          hipStream_t st);
 hipError_t launch_step2d_batch(int storage, int ty, const BatchCase* cases, const int2* work,
                                int nwork, int grid, int slot, hipStream_t st);
+hipError_t launch_fields2d_batch(int storage, int ty, const BatchCase* cases, const int2* work,
+                                 int nwork, int slot, float* dst, long case_stride,
+                                 uint32_t mask, hipStream_t st);
 hipError_t launch_export2d(const KParams& P, int storage, const StepArgs& A, float* dst,
                            hipStream_t st);
 hipError_t launch_import2d(const KParams& P, int storage, const StepArgs& A, const float* src,

@@ -118,3 +118,42 @@ def test_batch_grid_against_oracle():
     for k in FIELDS:
         err = np.abs(got[k] - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-30)
         assert err <= 1e-4, (k, err)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_fields_all_equals_per_grid_fields(storage):
+    """lbfz_batch_fields_all (one dry-pass launch per group of equal-sized
+    grids, writing every grid's fields into one buffer) against the per-grid
+    lbfz_batch_fields: uneven and equal sizes, the tile heights the tuner
+    picked, a padded case stride, all fields and a subset mask.  The batched
+    and single-grid kernels differ only in FP32 rounding (fused multiply-adds
+    formed differently, as for the step): within 2e-6 of each field's
+    maximum, and nothing written outside each grid's planes."""
+    import torch
+    from paper_2511_09422_amd.lbfz import FIELDS as ALL, Batch, lib
+    cases = _cases() + [sweep_case(k, side=512) for k in (2, 3)]
+    b = Batch(cases, storage=storage)
+    b.tune(2)
+    b.step(7)
+    print(f"[fields_all {storage}] groups {b.groups()}", flush=True)
+    max_n = max(c[0]["nx"] * c[0]["ny"] for c in cases)
+    for mask in ((1 << 9) - 1, 0b010000101):
+        bits = [k for k in range(9) if mask >> k & 1]
+        stride = len(bits) * max_n + 37
+        dst = torch.full((len(cases) * stride,), float("nan"), dtype=torch.float32,
+                         device="cuda")
+        assert lib().lbfz_batch_fields_all(b._b, mask, dst.data_ptr(), stride) == 0
+        torch.cuda.synchronize()
+        host = dst.cpu().numpy()
+        for i, c in enumerate(cases):
+            n = c[0]["nx"] * c[0]["ny"]
+            ref = b.fields(i, names=[ALL[k] for k in bits])
+            for r, k in enumerate(bits):
+                got = host[i * stride + r * n:i * stride + (r + 1) * n].reshape(b.shapes[i])
+                r_ = ref[ALL[k]]
+                e = float(np.abs(got - r_).max() / max(np.abs(r_).max(), 1e-30))
+                assert e <= 2e-6, (storage, mask, i, ALL[k], e)
+            # nothing past the grid's planes is written
+            tail = host[i * stride + len(bits) * n:(i + 1) * stride]
+            assert np.isnan(tail).all(), (storage, mask, i)
+    b.close()
