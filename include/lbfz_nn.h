@@ -69,6 +69,33 @@ typedef struct lbfz_conv_args {
  * W[n][t][c'].  Implicit GEMM, M = pixels, N = a->N, K = taps * Cin. */
 int lbfz_nn_conv(const lbfz_conv_args* a, void* stream);
 
+/* The network's tail at inference, fused into one launch: the last 3 x 3
+ * convolution `a` (forward, bias, ReLU, bf16 activations, a->N == 32 output
+ * channels, a->Cin a multiple of 32, no upsampling, no pooling), the 1 x 1
+ * head over its 32 outputs, and the prediction of whole grids as
+ * lbfz_nn_apply_images computes it, without writing the head's input or
+ * output to memory (a->out may be NULL; if not, the convolution's output is
+ * stored as lbfz_nn_conv stores it).  The head's input is the convolution's
+ * output rounded to bf16, as the unfused network stores it; the head's dot
+ * products are FP32 in channel order (the unfused head's matrix-core sums
+ * round differently, by about 1e-7 of the largest term).  Image i of the
+ * convolution is grid i: its nf FP32 planes at before + i * before_stride,
+ * its prediction at pred + i * pred_stride (a->H x a->W values per plane). */
+typedef struct lbfz_tail_args {
+  const void* head_w;      /* bf16 [nh][32]: the head's weights over the 32 channels */
+  const float* head_b;     /* [nh] or NULL */
+  int32_t nh;              /* head outputs (nf <= nh <= 32); outputs nf .. nh - 1 unused */
+  int32_t nf;              /* fields predicted                                           */
+  const float* before;     /* fields of the grids before the stride                      */
+  int64_t before_stride;
+  const float* shift;      /* device arrays of nf floats: pred[f] = resid[f] before[f] +  */
+  const float* scale;      /*   head[f] / scale[f] + shift[f]                             */
+  const float* resid;
+  float* pred;
+  int64_t pred_stride;
+} lbfz_tail_args;
+int lbfz_nn_conv_tail(const lbfz_conv_args* a, const lbfz_tail_args* t, void* stream);
+
 /* Weight gradient dw[n][t][c] = sum_p dz[p][n] x[p + o(t)][c], FP32.  The
  * pixel sum is split into at most nsplit partial rows in part (nsplit * N *
  * taps * Cin floats; 3 x 3: up to about 512 / (ceil(N/32) ceil(Cin/32))

@@ -337,8 +337,12 @@ constexpr int TW = 64, TH = 4, HWD = TW + 2, HHT = TH + 2;
 
 // CC: input channels per chunk (32, or 16 for layers whose channel count is
 // not a multiple of 32, e.g. the 16-channel input layer)
-template <int FN, bool UP, int SIGN, int CC = 32, int RPW = 1>
-__global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
+//
+// TAIL (inference, lbfz_nn_conv_tail): after the block's output tile is staged
+// in LDS, the 1 x 1 head and the prediction of the tile's pixels follow in
+// the same block (the 32 channels of every pixel are in the tile).
+template <int FN, bool UP, int SIGN, int CC, int RPW, bool TAIL>
+__device__ __forceinline__ void conv_direct(const lbfz_conv_args& a, const lbfz_tail_args& tl) {
   constexpr int BN_ = 32 * FN;
   constexpr int TH_ = 4 * RPW, HH_ = TH_ + 2;  // tile rows (RPW per wave), halo rows
   constexpr int FM = 2 * RPW;                  // A fragments per wave (32 pixels each)
@@ -456,7 +460,7 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
   // and channel n0 + 32 j + lane % 32 of accumulator element r (row =
   // acc_row(r, lane))
   const float* bias = a.bias;
-  if (!a.out_f32 && a.N % 8 == 0 && a.out_cs % 8 == 0 && a.out_co % 8 == 0) {
+  if (TAIL || (!a.out_f32 && a.N % 8 == 0 && a.out_cs % 8 == 0 && a.out_co % 8 == 0)) {
     bf16* Os = smem;
     __syncthreads();
 #pragma unroll
@@ -472,15 +476,52 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
           Os[((RPW * wave + i / 2) * TW + 32 * (i % 2) + acc_row(r, lane)) * BN_ + col] = (bf16)v;
         }
     }
+    // tail: the head's weights and bias as FP32 behind the output tile
+    float* hw = reinterpret_cast<float*>(smem + O_EL);
+    if constexpr (TAIL) {
+      static_assert(FN == 1 && 2 * O_EL + 4 * 32 * 33 <= 2 * SM_EL, "tail LDS");
+      for (int e = tid; e < tl.nh * 32; e += 256)
+        hw[e] = (float)static_cast<const bf16*>(tl.head_w)[e];
+      if (tid < tl.nh) hw[32 * 32 + tid] = tl.head_b ? tl.head_b[tid] : 0.0f;
+    }
     __syncthreads();
     constexpr int GPR = BN_ / 8;
-    for (int g = tid; g < TH_ * TW * GPR; g += 256) {
-      const int m = g / GPR, cg = g - m * GPR;
-      const int yy = y0 + m / TW, xx = x0 + m % TW, cn = n0 + 8 * cg;
-      if (yy < a.H && xx < a.W && cn < a.N)
-        *reinterpret_cast<uint4*>(static_cast<bf16*>(a.out) +
-                                  ((size_t)(b * a.H + yy) * a.W + xx) * a.out_cs + a.out_co + cn) =
-            *reinterpret_cast<const uint4*>(&Os[m * BN_ + 8 * cg]);
+    if (!TAIL || a.out) {
+      for (int g = tid; g < TH_ * TW * GPR; g += 256) {
+        const int m = g / GPR, cg = g - m * GPR;
+        const int yy = y0 + m / TW, xx = x0 + m % TW, cn = n0 + 8 * cg;
+        if (yy < a.H && xx < a.W && cn < a.N)
+          *reinterpret_cast<uint4*>(static_cast<bf16*>(a.out) +
+                                    ((size_t)(b * a.H + yy) * a.W + xx) * a.out_cs + a.out_co +
+                                    cn) = *reinterpret_cast<const uint4*>(&Os[m * BN_ + 8 * cg]);
+      }
+    }
+    if constexpr (TAIL) {
+      // head and prediction, one pixel per thread and pass (consecutive
+      // threads take consecutive columns of a row: coalesced plane accesses)
+      const long npx = (long)a.H * a.W;
+      for (int m = tid; m < TH_ * TW; m += 256) {
+        const int yy = y0 + m / TW, xx = x0 + m % TW;
+        if (yy >= a.H || xx >= a.W) continue;
+        float v[32];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          V8 c8;
+          c8.u = *reinterpret_cast<const uint4*>(&Os[m * BN_ + 8 * q]);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[8 * q + e] = (float)c8.h[e];
+        }
+        const long px = (long)yy * a.W + xx;
+        const float* bsrc = tl.before + b * tl.before_stride + px;
+        float* pdst = tl.pred + b * tl.pred_stride + px;
+        for (int f = 0; f < tl.nf; ++f) {
+          float o = hw[32 * 32 + f];
+#pragma unroll
+          for (int c = 0; c < 32; ++c) o = fmaf(hw[32 * f + c], v[c], o);
+          pdst[f * npx] = tl.resid[f] * bsrc[f * npx] + o / tl.scale[f] + tl.shift[f];
+        }
+      }
+      return;
     }
     if (a.pool) {
       // fused 2 x 2 max pooling of the stored (bf16) output: the tile's rows
@@ -530,6 +571,15 @@ __global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
       }
     }
   }
+}
+
+template <int FN, bool UP, int SIGN, int CC = 32, int RPW = 1>
+__global__ __launch_bounds__(256) void k_conv_direct(lbfz_conv_args a) {
+  conv_direct<FN, UP, SIGN, CC, RPW, false>(a, lbfz_tail_args{});
+}
+
+__global__ __launch_bounds__(256) void k_conv_tail(lbfz_conv_args a, lbfz_tail_args t) {
+  conv_direct<1, false, 1, 32, 2, true>(a, t);
 }
 
 // Weight gradient of a 3 x 3 convolution, direct form: dW[n][t][c] = sum_p
@@ -1123,6 +1173,25 @@ static bool conv_ok(const lbfz_conv_args* a) {
   return a && a->in && a->w && a->B > 0 && a->H > 0 && a->W > 0 && (a->taps == 1 || a->taps == 9) &&
          a->Cin > 0 && a->Cin % 8 == 0 && a->N > 0 && a->in_cs % 8 == 0 && a->in_co % 8 == 0 &&
          (a->up == 0 || (a->up == 1 && a->H % 2 == 0 && a->W % 2 == 0));
+}
+
+int lbfz_nn_conv_tail(const lbfz_conv_args* a, const lbfz_tail_args* t, void* stream) {
+  if (!conv_ok(a) || !t || a->taps != 9 || a->sign != 1 || a->up || a->pool || a->out_f32 ||
+      a->N != 32 || a->Cin % 32 != 0)
+    return LBFZ_NN_EINVAL;
+  if (a->out && (a->out_cs % 8 || a->out_co % 8 || a->out_co + a->N > a->out_cs))
+    return LBFZ_NN_EINVAL;
+  if (!t->head_w || !t->before || !t->shift || !t->scale || !t->resid || !t->pred ||
+      t->nf < 1 || t->nf > t->nh || t->nh > 32)
+    return LBFZ_NN_EINVAL;
+  const long M = (long)a->B * a->H * a->W, npx = (long)a->H * a->W;
+  if (M >= (1L << 30) || M * a->in_cs * 2 >= (1L << 31) || (long)a->N * 9 * a->Cin * 2 >= (1L << 31) ||
+      t->before_stride < t->nf * npx || t->pred_stride < t->nf * npx)
+    return LBFZ_NN_EINVAL;
+  const long ty8 = (a->H + 7) / 8, tx = (a->W + TW - 1) / TW;
+  hipLaunchKernelGGL(k_conv_tail, dim3((unsigned)(a->B * ty8 * tx)), dim3(256), 0,
+                     (hipStream_t)stream, *a, *t);
+  HCHK();
 }
 
 int lbfz_nn_conv(const lbfz_conv_args* a, void* stream) {

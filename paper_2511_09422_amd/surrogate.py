@@ -52,6 +52,14 @@ class lbfz_conv_args(ctypes.Structure):
                 ("pool_cs", ctypes.c_int32), ("pool_co", ctypes.c_int32)]
 
 
+class lbfz_tail_args(ctypes.Structure):
+    _fields_ = [("head_w", ctypes.c_void_p), ("head_b", ctypes.c_void_p), ("nh", ctypes.c_int32),
+                ("nf", ctypes.c_int32), ("before", ctypes.c_void_p),
+                ("before_stride", ctypes.c_int64), ("shift", ctypes.c_void_p),
+                ("scale", ctypes.c_void_p), ("resid", ctypes.c_void_p), ("pred", ctypes.c_void_p),
+                ("pred_stride", ctypes.c_int64)]
+
+
 _nn = None
 
 
@@ -64,6 +72,7 @@ def nnlib():
         cp = ctypes.POINTER(lbfz_conv_args)
         sig = {
             "lbfz_nn_conv": [cp, vp],
+            "lbfz_nn_conv_tail": [cp, ctypes.POINTER(lbfz_tail_args), vp],
             "lbfz_nn_conv_wgrad": [cp, vp, i32, vp, vp],
             "lbfz_nn_bias_grad": [vp, lg, i32, i32, vp, i32, vp, vp],
             "lbfz_nn_relu_bwd": [vp, i32, i32, vp, i32, i32, vp, i32, lg, i32, vp],
@@ -273,6 +282,41 @@ class UNet:
 
     def forward(self):
         """X0 -> OUT (FP32, HEAD channels)."""
+        t = self.t
+        self._forward_body()
+        self._conv("L5b", t["A5"], 32, 0, t["A5b"], 32, 0)
+        self._conv("head", t["A5b"], 32, 0, t["OUT"], HEAD, 0, out_f32=True)
+
+    def predict_fields(self, nimg, before, before_stride, pred, pred_stride, nf, shift, scale,
+                       resid):
+        """Inference: the prediction of the grids of images 0 .. nimg - 1 (as
+        lbfz_nn_apply_images of forward()'s output), with the last convolution,
+        the head and the prediction fused into one launch (lbfz_nn_conv_tail:
+        neither A5b nor OUT is written)."""
+        if not 0 < nimg <= self.B:
+            raise ValueError("nimg out of range")
+        t = self.t
+        self._forward_body()
+        Ly = self.L["L5b"]
+        B, H, W = self._dims(Ly.level)
+        wb, bias = self._w("L5b")
+        a = lbfz_conv_args()
+        a.in_, a.in_cs, a.in_co, a.Cin = t["A5"].data_ptr(), 32, 0, Ly.cin
+        a.w, a.dz_cs, a.N = wb.value, 0, Ly.cout
+        a.bias, a.out = bias.value, None
+        a.out_cs, a.out_co, a.out_f32 = 32, 0, 0
+        a.relu, a.sign = int(Ly.relu), 1
+        a.B, a.H, a.W, a.taps, a.up = nimg, H, W, 9, 0
+        hw, hb = self._w("head")
+        ta = lbfz_tail_args()
+        ta.head_w, ta.head_b, ta.nh, ta.nf = hw.value, hb.value, HEAD, nf
+        ta.before, ta.before_stride = before.data_ptr(), before_stride
+        ta.shift, ta.scale, ta.resid = shift.data_ptr(), scale.data_ptr(), resid.data_ptr()
+        ta.pred, ta.pred_stride = pred.data_ptr(), pred_stride
+        _ck(nnlib().lbfz_nn_conv_tail(ctypes.byref(a), ctypes.byref(ta), self.st), "conv_tail")
+
+    def _forward_body(self):
+        """X0 -> A5 (every layer before the last convolution)."""
         L, t = nnlib(), self.t
         B, S = self.B, self.S
         self._conv("L1a", t["X0"], CIN0, 0, t["A1"], 32, 0)
@@ -289,8 +333,6 @@ class UNet:
         self._conv("L4b", t["A4"], 64, 0, t["A4b"], 64, 0)
         self._conv("U1", t["A4b"], 64, 0, t["CAT1"], 64, 0, up=True)
         self._conv("L5a", t["CAT1"], 64, 0, t["A5"], 32, 0)
-        self._conv("L5b", t["A5"], 32, 0, t["A5b"], 32, 0)
-        self._conv("head", t["A5b"], 32, 0, t["OUT"], HEAD, 0, out_f32=True)
 
     # --------------------------------------------------------------- backward
     def _layer_bwd(self, name, x, x_cs, x_co, dy, dy_cs, dy_co, y, y_cs, y_co, dx, dx_cs,
@@ -585,6 +627,7 @@ class Screener:
         self.sums_a = torch.zeros(self.n * NF, dtype=torch.float64, device=net.dev)
         self.time = 0  # LB steps screened so far (the batch's own counter only
         # moves when some grid falls back to the LB)
+        self.fused = True  # network tail, head and prediction in one launch
 
     def predict(self):
         """Export every grid's fields, run the network, apply its output:
@@ -595,11 +638,15 @@ class Screener:
         _ck(L.lbfz_nn_pack_images(_p(self.before), self.n, NEXP * S * S, NIN, S,
                                   _p(self.norm.in_shift), _p(self.norm.in_scale),
                                   _p(net.t["X0"]), CIN0, st), "pack_images")
-        net.forward()
-        _ck(L.lbfz_nn_apply_images(_p(net.t["OUT"]), HEAD, _p(self.before), self.n, NEXP * S * S,
-                                   NF, S, _p(self.norm.d_shift), _p(self.norm.d_scale),
-                                   _p(self.norm.resid), _p(self.pred), NF * S * S, st),
-            "apply_images")
+        if self.fused:
+            net.predict_fields(self.n, self.before, NEXP * S * S, self.pred, NF * S * S, NF,
+                               self.norm.d_shift, self.norm.d_scale, self.norm.resid)
+        else:
+            net.forward()
+            _ck(L.lbfz_nn_apply_images(_p(net.t["OUT"]), HEAD, _p(self.before), self.n,
+                                       NEXP * S * S, NF, S, _p(self.norm.d_shift),
+                                       _p(self.norm.d_scale), _p(self.norm.resid),
+                                       _p(self.pred), NF * S * S, st), "apply_images")
         _ck(L.lbfz_nn_plane_sums(_p(self.before), self.n * NEXP, S * S, S * S, _p(self.sums_b),
                                  st), "plane_sums")
         _ck(L.lbfz_nn_plane_sums(_p(self.pred), self.n * NF, S * S, S * S, _p(self.sums_a),

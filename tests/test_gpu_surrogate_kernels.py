@@ -273,3 +273,87 @@ def test_training_reduces_loss():
     print(f"[unet] training loss {losses[0]:.4f} -> {losses[-1]:.4f}", flush=True)
     assert np.isfinite(losses).all()
     assert losses[-1] < 0.25 * losses[0]
+
+
+@pytest.mark.parametrize("B,S,Cin", [(3, 72, 32), (2, 20, 64)])
+def test_conv_tail_fused_head_and_prediction(B, S, Cin):
+    """lbfz_nn_conv_tail (the last 3 x 3 convolution, the 1 x 1 head and the
+    prediction of whole grids in one launch) against (a) the CPU float64
+    reference -- convolution of the bf16 operands, bias, ReLU, rounded to
+    bf16 as the network stores it, head, prediction -- within the bf16 bar
+    (6e-3 of the largest increment), and (b) the unfused kernels (convolution,
+    1 x 1 head with FP32 output, lbfz_nn_apply_images) within 1e-5 of the
+    largest increment (the two heads sum the same bf16 inputs in FP32 in
+    different orders); the convolution output, when also requested, equals
+    lbfz_nn_conv's bit for bit; nothing is written past a grid's planes.
+    Ragged tiles: S = 72 (two tile columns, the second partial), S = 20
+    (partial tile rows)."""
+    import ctypes
+    import torch
+    import torch.nn.functional as F
+    from paper_2511_09422_amd import surrogate as sg
+    rng = np.random.default_rng(7 * B + S + Cin)
+    N, NH, NF = 32, 8, 6
+    npx = S * S
+    x = _bf16(rng.standard_normal((B, S, S, Cin)))
+    w = _bf16(rng.standard_normal((N, 9, Cin)) / np.sqrt(9 * Cin))
+    bias = rng.standard_normal(N).astype(np.float32) * 0.1
+    hw = _bf16(rng.standard_normal((NH, N)) / np.sqrt(N))
+    hb = rng.standard_normal(NH).astype(np.float32) * 0.1
+    shift = rng.standard_normal(NF).astype(np.float32) * 0.01
+    scale = (1.0 + rng.random(NF)).astype(np.float32)
+    resid = np.array([1, 1, 1, 1, 0, 0], np.float32)
+    bstride, pstride = NF * npx + 40, NF * npx + 24
+    before = np.full((B, bstride), np.nan, np.float32)
+    before[:, :NF * npx] = rng.standard_normal((B, NF * npx))
+    # CPU reference
+    tw = torch.tensor(np.transpose(w, (0, 2, 1)).reshape(N, Cin, 3, 3))
+    tx = torch.tensor(x).permute(0, 3, 1, 2)
+    y = F.conv2d(tx, tw, torch.tensor(bias, dtype=torch.float64), padding=1)
+    y = _bf16(np.maximum(y.permute(0, 2, 3, 1).numpy(), 0.0))          # B, S, S, N
+    head = y @ hw.astype(np.float64).T + hb.astype(np.float64)          # B, S, S, NH
+    inc_ref = np.stack([head[..., f] / scale[f] for f in range(NF)], 1).reshape(B, NF, npx)
+    # GPU
+    L = sg.nnlib()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    dx_, dw_ = _dev(x, torch.bfloat16), _dev(w, torch.bfloat16)
+    db, dhw, dhb = torch.tensor(bias).cuda(), _dev(hw, torch.bfloat16), torch.tensor(hb).cuda()
+    dsh, dsc, dre = torch.tensor(shift).cuda(), torch.tensor(scale).cuda(), torch.tensor(resid).cuda()
+    dbefore = torch.tensor(before).cuda()
+
+    def tail(out):
+        pred = torch.full((B, pstride), float("nan"), dtype=torch.float32, device="cuda")
+        a = sg.conv_args(dx_, Cin, 0, Cin, dw_, N, out, N, 0, B, S, S, 9, bias=db, relu=True)
+        t = sg.lbfz_tail_args()
+        t.head_w, t.head_b, t.nh, t.nf = dhw.data_ptr(), dhb.data_ptr(), NH, NF
+        t.before, t.before_stride = dbefore.data_ptr(), bstride
+        t.shift, t.scale, t.resid = dsh.data_ptr(), dsc.data_ptr(), dre.data_ptr()
+        t.pred, t.pred_stride = pred.data_ptr(), pstride
+        assert L.lbfz_nn_conv_tail(ctypes.byref(a), ctypes.byref(t), st) == 0
+        torch.cuda.synchronize()
+        return pred.cpu().numpy()
+
+    y_tail = torch.zeros(B * npx * N, dtype=torch.bfloat16, device="cuda")
+    p1 = tail(None)
+    p2 = tail(y_tail)
+    assert np.array_equal(p1, p2, equal_nan=True)
+    assert np.isnan(p1[:, NF * npx:]).all()
+    pf = p1[:, :NF * npx].reshape(B, NF, npx).astype(np.float64)
+    bf = before[:, :NF * npx].reshape(B, NF, npx).astype(np.float64)
+    inc = pf - resid[None, :, None] * bf - shift[None, :, None]
+    assert _rel(inc, inc_ref) <= 6e-3, _rel(inc, inc_ref)
+    # unfused kernels
+    y_conv = torch.zeros(B * npx * N, dtype=torch.bfloat16, device="cuda")
+    a = sg.conv_args(dx_, Cin, 0, Cin, dw_, N, y_conv, N, 0, B, S, S, 9, bias=db, relu=True)
+    assert L.lbfz_nn_conv(ctypes.byref(a), st) == 0
+    out = torch.zeros(B * npx * NH, dtype=torch.float32, device="cuda")
+    a = sg.conv_args(y_conv, N, 0, N, dhw, NH, out, NH, 0, B, S, S, 1, bias=dhb, out_f32=True)
+    assert L.lbfz_nn_conv(ctypes.byref(a), st) == 0
+    pred_u = torch.full((B, pstride), float("nan"), dtype=torch.float32, device="cuda")
+    assert L.lbfz_nn_apply_images(sg._p(out), NH, sg._p(dbefore), B, bstride, NF, S, sg._p(dsh),
+                                  sg._p(dsc), sg._p(dre), sg._p(pred_u), pstride, st) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(y_tail, y_conv)
+    pu = pred_u.cpu().numpy()[:, :NF * npx].reshape(B, NF, npx).astype(np.float64)
+    e = float(np.abs(pf - pu).max() / np.abs(inc_ref).max())
+    assert e <= 1e-5, e
