@@ -245,8 +245,9 @@ def time_surrogate(iters: int, ngrids: int, warm: int, nacc: int) -> dict:
     160 sweep seeds (4000 pairs at 256^2), then on ngrids held-out seeds past
     `warm` strides of LB: one-stride predictions against the LB (accuracy,
     acceptance by the phase-field mass check) over `nacc` strides, and the
-    time of one screened stride (batched forward, LB on the rejected grids,
-    restarts) against the LB stride of all grids."""
+    time of a screened stride (batched forward, LB on the rejected grids,
+    restarts) against the LB stride of all grids, medians over fresh copies
+    of the held-out batch."""
     import torch
     from paper_2511_09422_amd import lbfz
     from paper_2511_09422_amd import surrogate as sg
@@ -268,12 +269,9 @@ def time_surrogate(iters: int, ngrids: int, warm: int, nacc: int) -> dict:
           f"({(t2 - t1) / iters * 1e3:.2f} ms each)", file=sys.stderr, flush=True)
     cases = [sweep_case(k, side=S) for k in range(10000, 10000 + ngrids)]
     ref = lbfz.Batch(cases)
-    scr = lbfz.Batch(cases)
     ref.step(warm * sg.STRIDE)
-    scr.step(warm * sg.STRIDE)
     net_b = sg.UNet(net.weights(), ngrids, S)
     on_ref = sg.Screener(net_b, norm, ref)
-    on_scr = sg.Screener(net_b, norm, scr)
     rows = []
     names = sg.FIELD_NAMES
 
@@ -290,25 +288,40 @@ def time_surrogate(iters: int, ngrids: int, warm: int, nacc: int) -> dict:
     acc = np.array([r[0] for r in rows])
     err = np.array([r[1] for r in rows])
     slow = err[:, :4].max(1)
-    # timing: the LB stride of all grids (graph replays, HIP events) and a
-    # screened stride (host logic included: wall clock around synchronised
-    # work) from the same LB states; the code paths ran above.  A second
-    # screened stride starts from partly restarted states (a rollout).
-    torch.cuda.synchronize()
+    # timing, from the same LB states: the LB stride of all grids (graph
+    # replays, HIP events), then a screened stride (host logic included: wall
+    # clock around synchronised work), then a second screened stride, which
+    # starts from partly restarted states (a rollout).  Medians over `reps`
+    # fresh copies of the held-out batch (the code paths ran above).
+    reps = 5
+    lbs, scs, sc2s, accs, accs2 = [], [], [], [], []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(scr.stream)
-    scr.step(sg.STRIDE)
-    ev1.record(scr.stream)
-    torch.cuda.synchronize()
-    lb_ms = ev0.elapsed_time(ev1)
-    t3 = time.perf_counter()
-    accs, _ = on_scr.stride()
-    torch.cuda.synchronize()
-    sc_ms = (time.perf_counter() - t3) * 1e3
-    t4 = time.perf_counter()
-    accs2, _ = on_scr.stride()
-    torch.cuda.synchronize()
-    sc2_ms = (time.perf_counter() - t4) * 1e3
+    for r in range(reps):
+        scr = lbfz.Batch(cases)
+        scr.step(warm * sg.STRIDE)
+        on_scr = sg.Screener(net_b, norm, scr)
+        torch.cuda.synchronize()
+        ev0.record(scr.stream)
+        scr.step(sg.STRIDE)
+        ev1.record(scr.stream)
+        torch.cuda.synchronize()
+        lbs.append(ev0.elapsed_time(ev1))
+        t3 = time.perf_counter()
+        a1, _ = on_scr.stride()
+        torch.cuda.synchronize()
+        scs.append((time.perf_counter() - t3) * 1e3)
+        t4 = time.perf_counter()
+        a2, _ = on_scr.stride()
+        torch.cuda.synchronize()
+        sc2s.append((time.perf_counter() - t4) * 1e3)
+        accs.append(np.mean(a1))
+        accs2.append(np.mean(a2))
+        bad = sum(scr.totals(i)["nonfinite"] for i in range(ngrids))
+        scr.close()
+        if bad:
+            print("bench: non-finite LB state in the surrogate section", file=sys.stderr)
+            sys.exit(1)
+    lb_ms, sc_ms, sc2_ms = (float(np.median(v)) for v in (lbs, scs, sc2s))
     ev0.record(net_b.stream)
     net_b.forward()
     ev1.record(net_b.stream)
@@ -317,19 +330,20 @@ def time_surrogate(iters: int, ngrids: int, warm: int, nacc: int) -> dict:
     flops = unet_flops_per_image(S) * ngrids
     bad = sum(ref.totals(i)["nonfinite"] for i in range(ngrids))
     ref.close()
-    scr.close()
     if bad:
         print("bench: non-finite LB state in the surrogate section", file=sys.stderr)
         sys.exit(1)
     print(f"bench: surrogate stride of {ngrids} grids: LB {lb_ms:.2f} ms, screened "
-          f"{sc_ms:.2f} ms ({np.mean(accs):.2f} accepted), forward {fwd_ms:.2f} ms",
-          file=sys.stderr, flush=True)
+          f"{sc_ms:.2f} ms ({np.mean(accs):.2f} accepted; each copy "
+          f"{' '.join(f'{v:.2f}' for v in scs)}), rollout {sc2_ms:.2f} ms, forward "
+          f"{fwd_ms:.2f} ms", file=sys.stderr, flush=True)
     return {"value": round(lb_ms / sc_ms, 3), "unit": "x (LB-only stride time / screened)",
             "workload": f"{ngrids} held-out sweep seeds at {S}^2 after {warm} LB strides; "
                         f"stride {sg.STRIDE} steps; U-Net 32/64/128, BF16 MFMA",
             "train": {"pairs": npairs, "iterations": iters, "batch": 8,
                       "ms_per_iteration": round((t2 - t1) / iters * 1e3, 2),
                       "data_s": round(t1 - t0, 1)},
+            "timing": f"medians over {reps} copies of the held-out batch",
             "lb_stride_ms": round(lb_ms, 3), "screened_stride_ms": round(sc_ms, 3),
             "screened_accepted": round(float(np.mean(accs)), 3),
             "rollout_stride": {"ms": round(sc2_ms, 3), "accepted": round(float(np.mean(accs2)), 3),
