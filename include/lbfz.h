@@ -233,7 +233,10 @@ int lbfz_batch_select(lbfz_batch* b, int32_t n, const int32_t* idx);
 int lbfz_batch_restart_fields(lbfz_batch* b, int32_t i, const float* const* d_fields);
 
 /* The same for the n grids idx[0 .. n-1]: field m of grid i at d_fields[m] +
- * i * case_stride[m] (floats; m < 7, order as lbfz_restart_fields). */
+ * i * case_stride[m] (floats; m < 7, order as lbfz_restart_fields).  FP32
+ * storage: one launch for all n grids from a job table uploaded by this
+ * call, which then synchronises the stream; 16-bit storage: one restart (and
+ * its encoding pass) per grid, asynchronous. */
 int lbfz_batch_restart_many(lbfz_batch* b, int32_t n, const int32_t* idx,
                             const float* const* d_fields, const int64_t* case_stride);
 

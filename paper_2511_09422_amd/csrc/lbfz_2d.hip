@@ -831,10 +831,9 @@ __global__ __launch_bounds__(256) void k_import2d(KParams P, StepArgs A,
 // pure substance's mushy band is the single temperature T_m).  The flow's
 // momentum is rho u / (1 - f_s / 2) (the solid drag's half-step undone, the
 // interface force's half-step left out).  Non-equilibrium parts are zero.
-__global__ __launch_bounds__(256) void k_equil2d(KParams P, EquilFields F, StatePlanes S) {
-  const long N = P.N;
-  for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < N;
-       n += (long)gridDim.x * blockDim.x) {
+__device__ __forceinline__ void equil_node(const KParams& P, const EquilFields& F,
+                                           const StatePlanes& S, long n) {
+  {
     const float phi = F.phi[n], T = F.T[n], C = F.C[n];
     const float ux = F.ux[n], uy = F.uy[n], p = F.p[n];
     const float psi = clamp01(0.5f * (1.0f + phi));
@@ -883,6 +882,21 @@ __global__ __launch_bounds__(256) void k_equil2d(KParams P, EquilFields F, State
     S.p[28][n] = phi;
     S.p[29][n] = C;
   }
+}
+
+__global__ __launch_bounds__(256) void k_equil2d(KParams P, EquilFields F, StatePlanes S) {
+  for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < P.N;
+       n += (long)gridDim.x * blockDim.x)
+    equil_node(P, F, S, n);
+}
+
+// Batched restart: grid blockIdx.y of the job table, nodes strided over
+// blockIdx.x (the job is read by every thread from the same address).
+__global__ __launch_bounds__(256) void k_equil2d_batch(const EquilJob* __restrict__ jobs) {
+  const EquilJob& J = jobs[blockIdx.y];
+  for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < J.P.N;
+       n += (long)gridDim.x * blockDim.x)
+    equil_node(J.P, J.F, J.S, n);
 }
 
 int grid_of(long N) { return (int)std::min<long>((N + 255) / 256, 65536); }
@@ -1008,6 +1022,13 @@ hipError_t launch_import2d(const KParams& P, int storage, const StepArgs& A, con
 hipError_t launch_equil2d(const KParams& P, const EquilFields& F, const StatePlanes& S,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_equil2d, dim3(grid_of(P.N)), dim3(256), 0, st, P, F, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_equil2d_batch(const EquilJob* jobs, int njobs, long max_n, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  const int bx = (int)std::min<long>((max_n + 255) / 256, std::max(1L, 8192L / njobs));
+  hipLaunchKernelGGL(k_equil2d_batch, dim3(bx, njobs), dim3(256), 0, st, jobs);
   return hipGetLastError();
 }
 

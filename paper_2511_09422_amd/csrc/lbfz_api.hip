@@ -506,6 +506,26 @@ int lbfz_set_state(lbfz_handle* h, const float* host_src) {
   return LBFZ_OK;
 }
 
+}  // extern "C"
+
+namespace lbfz {
+int restart_job(lbfz_handle* h, const float* const* d_fields, EquilJob* job) {
+  if (!h || !d_fields || !job) return LBFZ_EINVAL;
+  for (int k = 0; k < 7; ++k)
+    if (!d_fields[k]) return LBFZ_EINVAL;
+  if (h->prm.dim != 2 || h->narrow) return LBFZ_EUNSUPPORTED;
+  std::vector<float*> planes;
+  if (state_planes(h, planes) != 30) return LBFZ_EUNSUPPORTED;
+  job->P = h->kp;
+  job->F = EquilFields{d_fields[0], d_fields[1], d_fields[2], d_fields[3],
+                       d_fields[4], d_fields[5], d_fields[6]};
+  for (int k = 0; k < 30; ++k) job->S.p[k] = planes[k];
+  return LBFZ_OK;
+}
+}  // namespace lbfz
+
+extern "C" {
+
 int lbfz_restart_fields(lbfz_handle* h, const float* const* d_fields) {
   if (!h || !d_fields) return LBFZ_EINVAL;
   for (int k = 0; k < 7; ++k)

@@ -61,6 +61,7 @@ struct lbfz_batch {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int64_t step = 0;
+  EquilJob* d_jobs = nullptr;  // device table of a batched restart (ncases entries)
   std::vector<char> selected;  // per grid: advanced by the steps
   std::vector<char> stale;     // per grid: left behind by a subset step
 };
@@ -200,6 +201,7 @@ int lbfz_batch_workspace_bytes(int32_t ncases, const lbfz_params* params, size_t
   }
   total += align256(sizeof(BatchCase) * (size_t)ncases);
   total += 2 * (align256(sizeof(int2) * items) + 256 * 2 * (size_t)ncases);
+  total += align256(sizeof(EquilJob) * (size_t)ncases);
   *bytes = total;
   return LBFZ_OK;
 }
@@ -273,6 +275,8 @@ int lbfz_batch_create(int32_t ncases, const lbfz_params* params, const double* c
       }
     }
   }
+  b->d_jobs = (EquilJob*)q;
+  q += align256(sizeof(EquilJob) * (size_t)ncases);
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
     b->cap = nullptr;
     lbfz_batch_destroy(b);
@@ -478,13 +482,34 @@ int lbfz_batch_restart_many(lbfz_batch* b, int32_t n, const int32_t* idx,
   for (int k = 0; k < n; ++k)
     if (idx[k] < 0 || idx[k] >= b->ncases) return LBFZ_EINVAL;
   sync_handles(b);
-  for (int k = 0; k < n; ++k) {
-    const float* f[7];
-    for (int m = 0; m < 7; ++m) f[m] = d_fields[m] + idx[k] * case_stride[m];
-    const int rc = lbfz_restart_fields(b->h[idx[k]], f);
-    if (rc != LBFZ_OK) return rc;
-    b->stale[idx[k]] = 0;
+  if (n == 0) return LBFZ_OK;
+  if (b->storage == LBFZ_STORE_F32) {
+    // FP32 storage: every grid's restart in one launch (a job table)
+    std::vector<EquilJob> jobs(n);
+    long max_n = 0;
+    for (int k = 0; k < n; ++k) {
+      const float* f[7];
+      for (int m = 0; m < 7; ++m) f[m] = d_fields[m] + idx[k] * case_stride[m];
+      const int rc = restart_job(b->h[idx[k]], f, &jobs[k]);
+      if (rc != LBFZ_OK) return rc;
+      max_n = std::max<long>(max_n, jobs[k].P.N);
+    }
+    HIPCHK(hipMemcpyAsync(b->d_jobs, jobs.data(), sizeof(EquilJob) * n, hipMemcpyHostToDevice,
+                          b->stream));
+    for (int k0 = 0; k0 < n; k0 += 65535)
+      HIPCHK(launch_equil2d_batch(b->d_jobs + k0, std::min(n - k0, 65535), max_n, b->stream));
+    // the job table is host memory of this call
+    HIPCHK(hipStreamSynchronize(b->stream));
+  } else {
+    // 16-bit storage: the restart's encoding pass is per grid
+    for (int k = 0; k < n; ++k) {
+      const float* f[7];
+      for (int m = 0; m < 7; ++m) f[m] = d_fields[m] + idx[k] * case_stride[m];
+      const int rc = lbfz_restart_fields(b->h[idx[k]], f);
+      if (rc != LBFZ_OK) return rc;
+    }
   }
+  for (int k = 0; k < n; ++k) b->stale[idx[k]] = 0;
   return LBFZ_OK;
 }
 

@@ -41,4 +41,8 @@ namespace lbfz {
 StepArgs base_args(lbfz_handle* h);
 // One step (dry: fields / totals only) of h on its stream.
 hipError_t launch_step(lbfz_handle* h, const StepArgs& a, bool dry);
+// The equilibrium restart of a 2D FP32-storage grid from device fields
+// (lbfz_restart_fields) as a job of a batched launch; LBFZ_EUNSUPPORTED for
+// 3D or 16-bit storage (their restart needs the per-grid import pass).
+int restart_job(lbfz_handle* h, const float* const* d_fields, EquilJob* job);
 }  // namespace lbfz

@@ -81,6 +81,14 @@ struct StatePlanes {
 };
 hipError_t launch_equil2d(const KParams& P, const EquilFields& F, const StatePlanes& S,
                           hipStream_t st);
+// One grid of a batched restart: its parameters, fields and state planes.
+struct EquilJob {
+  KParams P;
+  EquilFields F;
+  StatePlanes S;
+};
+// The restarts of njobs grids (jobs: a device table) in one launch.
+hipError_t launch_equil2d_batch(const EquilJob* jobs, int njobs, long max_n, hipStream_t st);
 
 int tiles3d(int nx, int ny, int nz, int storage, int* nbx, int* nby, int* nbz);
 size_t pop_bytes3d(int storage, size_t ps);

@@ -117,3 +117,46 @@ def test_batch_subset_step_and_restart(storage):
         assert part.totals(i)["nonfinite"] == 0
     full.close()
     part.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_batch_restart_many_equals_per_grid_restarts(storage):
+    """lbfz_batch_restart_many over several grids of two sizes (FP32 storage:
+    one batched launch over a job table; 16-bit: per grid) leaves every grid
+    in the state lbfz_batch_restart_fields gives it, bit for bit: the fields
+    right after the restart and 12 steps later agree exactly; the grids not
+    restarted are untouched."""
+    import torch
+    from paper_2511_09422_amd.lbfz import Batch
+    cases = [sweep_case(k, side=64) for k in (11, 12)] + [sweep_case(k, side=128) for k in (13, 14)]
+    a, b = Batch(cases, storage=storage), Batch(cases, storage=storage)
+    a.step(12)
+    b.step(12)
+    from paper_2511_09422_amd.lbfz import RESTART_FIELDS
+    n_max = 128 * 128
+    # field m of grid i at R[i, m, :N_i]: grid i's own fields at this level
+    # (the restart drops their non-equilibrium parts)
+    R = torch.zeros((4, 7, n_max), dtype=torch.float32, device="cuda")
+    for i in range(4):
+        f = a.fields(i, RESTART_FIELDS)
+        for m, nm in enumerate(RESTART_FIELDS):
+            R[i, m, :f[nm].size] = torch.from_numpy(f[nm].reshape(-1)).cuda()
+    idx = [0, 2, 3]
+    a.restart_many(idx, [R[:, m] for m in range(7)], [7 * n_max] * 7)
+    for i in idx:
+        n = cases[i][0]["nx"] * cases[i][0]["ny"]
+        b.restart_fields(i, [R[i, m, :n] for m in range(7)])
+    torch.cuda.synchronize()
+    for i in range(4):
+        fa, fb = a.fields(i), b.fields(i)
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]), (storage, i, k)
+    a.step(12)
+    b.step(12)
+    for i in range(4):
+        fa, fb = a.fields(i), b.fields(i)
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]), (storage, i, k, "after 12 steps")
+        assert a.totals(i)["nonfinite"] == 0
+    a.close()
+    b.close()
