@@ -5,7 +5,7 @@
  * skip connections by channel concatenation, a 1x1 head) that maps the six
  * fields phi, f_l, T, C, u_x, u_y of a crop of the 2D step to their change
  * over 64 steps.  The paper itself has no learned component; the surrogate
- * screens parameter sweeps of its model, with the LB step as the judge.
+ * screens parameter sweeps of its model, with the LB step as the reference.
  *
  * Conventions (all calls):
  *   - Activations and gradients: bf16, NHWC (pixel-major, channels
