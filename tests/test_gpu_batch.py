@@ -157,3 +157,39 @@ def test_fields_all_equals_per_grid_fields(storage):
             tail = host[i * stride + len(bits) * n:(i + 1) * stride]
             assert np.isnan(tail).all(), (storage, mask, i)
     b.close()
+
+
+def test_full_sweep_sampled_cases_against_oracle():
+    """The benchmark's sweep in its launch configuration -- the 512 cases
+    sweep_case(k), k < 512 (41.6 M nodes), tuned, stepped from the captured
+    graph -- with eight sampled cases, two of each side, checked against the
+    FP64 oracle run from the same initial fields for as many steps (the
+    tuner's trial steps are real steps: 24 + those): every field within 1e-4
+    of its maximum; and every grid's state finite."""
+    from paper_2511_09422_amd.lbfz import Batch
+    from paper_2511_09422_amd.workloads import sweep_params
+    n = 512
+    sides = [sweep_params(k)[0] for k in range(n)]
+    sample = []
+    for side in (64, 128, 256, 512):
+        sample += [k for k in range(n) if sides[k] == side][:2]
+    cases = [sweep_case(k) for k in range(n)]
+    b = Batch(cases)
+    b.tune(2)
+    b.step(24)
+    print(f"[sweep512] groups {b.groups()}", flush=True)
+    for k in sample:
+        cfg, phi, T, C = cases[k]
+        steps = b.totals(k)["step"]
+        assert steps >= 24
+        o = Oracle(cfg, phi, T, C, threads=THREADS)
+        o.step(steps)
+        ref, got = o.fields(), b.fields(k)
+        errs = {f: float(np.abs(got[f] - ref[f]).max() / max(np.abs(ref[f]).max(), 1e-30))
+                for f in FIELDS}
+        print(f"[sweep512] case {k} side {sides[k]} after {steps} steps: " +
+              " ".join(f"{f}={e:.1e}" for f, e in errs.items()), flush=True)
+        for f, e in errs.items():
+            assert e <= 1e-4, (k, f, e)
+    assert sum(b.totals(i)["nonfinite"] for i in range(n)) == 0
+    b.close()

@@ -44,7 +44,18 @@ def test_initial_state_equals_fp32(storage, case):
 @pytest.mark.parametrize("case,K", [("64x64", 0), ("64x64", 300), ("150x37", 100),
                                     ("periodic", 100), ("walls", 200)])
 def test_one_step_quantisation_bound(storage, case, K):
-    cfg, phi, T, C = CASES[case]()
+    _one_step_check(storage, case, K, *CASES[case]())
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_one_step_quantisation_bound_full_size(storage):
+    """The same bound on the 2048^2 droplet (radius 512) in the benchmark's
+    launch configuration, after 200 steps."""
+    from paper_2511_09422_amd.workloads import droplet_2d
+    _one_step_check(storage, "2048x2048", 200, *droplet_2d(2048, 2048, R=512.0, seed=0))
+
+
+def _one_step_check(storage, case, K, cfg, phi, T, C):
     print(f"[16bit one-step] {storage} {case} after {K} steps", flush=True)
     s = Solver(cfg, phi, T, C, storage=storage)
     s.step(K)
