@@ -87,3 +87,38 @@ def test_create_rejects_bad_inputs_before_device_work():
     with pytest.raises(lbfz.LbfzError) as e:
         lbfz.lbfz_create(base_params(nx=16, ny=8, tau_h=0.4), phi, T, C, None, fake, need, 0)
     assert e.value.code == lbfz.LBFZ_EINVAL
+
+
+def test_tail_args_struct_and_conv_tail_rejections():
+    """lbfz_tail_args mirrors the header, and lbfz_nn_conv_tail rejects each
+    invalid argument before any launch (fake pointers, never dereferenced)."""
+    from paper_2511_09422_amd import surrogate as sg
+    txt = open(os.path.join(ROOT, "include", "lbfz_nn.h")).read()
+    body = txt[txt.index("typedef struct lbfz_tail_args"):txt.index("} lbfz_tail_args;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S).split("{", 1)[1]
+    fields = re.findall(r"\b([a-zA-Z_][a-zA-Z0-9_]*)\s*[,;]", body)
+    assert fields == [f for f, _ in sg.lbfz_tail_args._fields_]
+    L = sg.nnlib()
+    fake = 1 << 20
+
+    def args(**over):
+        a = sg.lbfz_conv_args()
+        a.in_, a.in_cs, a.in_co, a.Cin = fake, 32, 0, 32
+        a.w, a.N, a.bias, a.out = fake, 32, fake, None
+        a.out_cs, a.out_co, a.relu, a.sign = 32, 0, 1, 1
+        a.B, a.H, a.W, a.taps, a.up = 2, 16, 16, 9, 0
+        t = sg.lbfz_tail_args()
+        t.head_w, t.head_b, t.nh, t.nf = fake, fake, 8, 6
+        t.before, t.before_stride = fake, 6 * 256
+        t.shift = t.scale = t.resid = fake
+        t.pred, t.pred_stride = fake, 6 * 256
+        for k, v in over.items():
+            setattr(t if hasattr(t, k) else a, k, v)
+        return a, t
+
+    for bad in (dict(N=64), dict(Cin=48), dict(taps=1), dict(sign=-1), dict(up=1),
+                dict(out_f32=1), dict(pool=fake), dict(nf=9), dict(nh=33), dict(nf=0),
+                dict(before_stride=6 * 256 - 1), dict(pred_stride=100), dict(head_w=None),
+                dict(pred=None), dict(in_=None), dict(out=fake, out_co=8)):
+        a, t = args(**bad)
+        assert L.lbfz_nn_conv_tail(ctypes.byref(a), ctypes.byref(t), None) == sg.LBFZ_NN_EINVAL, bad
