@@ -6,6 +6,7 @@ printed results:
   error shrinking as the interface is resolved;
 * 1-D Stefan problem: front s(t) = 2 k sqrt(alpha t) with k the root of the
   transcendental equation of Sec. 4.3 (one- and two-phase);
+* binary solidification: the solute redistribution of Sec. 4.3's closed form;
 * three-phase Stefan problem with volume change: final height
   h_f = rho_l h_0 / rho_s (Sec. 4.2, Table 1);
 * two-layer thermocapillary channel: temperature and velocity of Appendix A.
@@ -94,6 +95,52 @@ def test_stefan_front_follows_neumann(ste, T0):
         done = t
         s = (1.0 - o.fields()["fl"][:, 0]).sum()       # frozen thickness
         assert abs(s / (2 * k * math.sqrt(alpha * t)) - 1) < 5e-3, (t, s)
+
+
+def test_binary_stefan_solute_redistribution():
+    """Binary solidification (Sec. 4.3): a liquid of concentration C0 = 0.1
+    at the melting temperature freezes from a wall at T_b = -1 (L = 10, so
+    Ste = 0.1), partition coefficient k_p = 0.5, no diffusion in the solid.
+    The closed form of Sec. 4.3: front s = 2 k sqrt(alpha t), uniform solid
+    concentration C_s = k_p C0 exp(-k^2 a/D) / den, liquid C0 + A erfc(x /
+    (2 sqrt(D t))) with A = (1 - k_p) C0 k sqrt(pi a/D) / den, den =
+    exp(-k^2 a/D) - (1 - k_p) k sqrt(pi a/D) erfc(k sqrt(a/D)).  The front
+    follows it within 0.5 %; the solute, which crosses the enthalpy method's
+    one-node mushy zone, within 15 % on the solid plateau and 12 % of A in
+    the liquid, errors that fall as the diffusion length grows; the solid
+    holds less solute than the melt and the melt piles it up ahead of the
+    front (a sign error in the partition term reverses both); total solute
+    conserved."""
+    ny, kp, C0, L = 256, 0.5, 0.1, 10.0
+    cfg = base_params(nx=2, ny=ny, rho_s=1.0, rhoc_ref=1.0, latent=L, sigma_T=0.0, k_p=kp,
+                      Ds_over_Dl=0.0)
+    shape = (ny, 2)
+    o = Oracle(cfg, np.ones(shape), np.zeros(shape), np.full(shape, C0), threads=THREADS)
+    k = _neumann_k(-1.0, 0.0, 0.0, L)
+    a = (1 / 3) * (cfg["tau_h"] - 0.5)
+    D = (1 / 3) * (cfg["tau_c"] - 0.5)
+    r = a / D
+    den = math.exp(-k * k * r) - (1 - kp) * k * math.sqrt(math.pi * r) * erfc(k * math.sqrt(r))
+    Cs = kp * C0 * math.exp(-k * k * r) / den
+    A = (1 - kp) * C0 * k * math.sqrt(math.pi * r) / den
+    y = np.arange(ny) + 0.5                     # distance from the wall
+    errs, done = [], 0
+    for t in (5000, 20000):
+        o.step(t - done)
+        done = t
+        f = o.fields()
+        C, fs = f["C"][:, 0], 1.0 - f["fl"][:, 0]
+        s = fs.sum()
+        assert abs(s / (2 * k * math.sqrt(a * t)) - 1) < 5e-3, (t, s)
+        solid = np.where(fs > 0.999)[0][2:-2]   # the plateau, off the wall and the front
+        liq = y > s + 4
+        e_s = abs(C[solid].mean() / Cs - 1)
+        e_l = np.abs(C[liq] - (C0 + A * erfc(y[liq] / (2 * math.sqrt(D * t))))).max() / A
+        errs.append((e_s, e_l))
+        assert e_s < 0.15 and e_l < 0.12, (t, e_s, e_l)
+        assert C[solid].max() < 0.7 * C0 < C0 < C[~(fs > 0.5)].max()
+        assert abs(C.sum() / (C0 * ny) - 1) < 1e-10   # FP64 rounding over 2e4 steps
+    assert errs[1][0] < errs[0][0] and errs[1][1] < errs[0][1]
 
 
 def test_neumann_roots_match_known_values():
