@@ -601,6 +601,26 @@ def check(sums_before, sums_after, n: int, ratio: float, mass_tol: float = MASS_
     return ok, r, d
 
 
+def check_all(sums_before, sums_after, n: int, ratios, mass_tol: float = MASS_TOL,
+              solute_tol: float = SOLUTE_TOL):
+    """check() for many grids at once (row i: grid i's sums, ratios[i] its
+    1 - rho_s / rho_l), in array arithmetic: the same values, without a
+    Python loop over the grids.  Returns the list of (accept, residual,
+    drift)."""
+    sb = np.asarray(sums_before, dtype=np.float64)
+    sa = np.asarray(sums_after, dtype=np.float64)
+    ratios = np.asarray(ratios, dtype=np.float64)
+    dphi = sa[:, 0] - sb[:, 0]
+    dfs = -(sa[:, 1] - sb[:, 1])
+    denom = np.maximum(0.5 * (n + sb[:, 0]), 1e-30)
+    r = np.abs(dphi - ratios * dfs) / denom
+    d = np.abs(sa[:, 3] - sb[:, 3]) / np.maximum(np.abs(sb[:, 3]), 1e-30)
+    ok = np.all(np.isfinite(sa), axis=1) & (r <= mass_tol)
+    if solute_tol is not None:
+        ok &= d <= solute_tol
+    return [(bool(ok[i]), float(r[i]), float(d[i])) for i in range(sb.shape[0])]
+
+
 class Screener:
     """Screens a batched sweep (an lbfz.Batch of equal S x S grids) STRIDE
     steps at a time: one surrogate forward over every grid; grids whose
@@ -623,8 +643,11 @@ class Screener:
         f = dict(dtype=torch.float32, device=net.dev)
         self.before = torch.zeros((self.n, NEXP, S, S), **f)
         self.pred = torch.zeros((self.n, NF, S, S), **f)
-        self.sums_b = torch.zeros(self.n * NEXP, dtype=torch.float64, device=net.dev)
-        self.sums_a = torch.zeros(self.n * NF, dtype=torch.float64, device=net.dev)
+        # per-grid sums before the stride and of the prediction, in one
+        # buffer so that the check needs one device-to-host copy
+        self.sums = torch.zeros(self.n * (NEXP + NF), dtype=torch.float64, device=net.dev)
+        self.sums_b = self.sums[:self.n * NEXP]
+        self.sums_a = self.sums[self.n * NEXP:]
         self.time = 0  # LB steps screened so far (the batch's own counter only
         # moves when some grid falls back to the LB)
         self.fused = True  # network tail, head and prediction in one launch
@@ -651,10 +674,10 @@ class Screener:
                                  st), "plane_sums")
         _ck(L.lbfz_nn_plane_sums(_p(self.pred), self.n * NF, S * S, S * S, _p(self.sums_a),
                                  st), "plane_sums")
-        sb = self.sums_b.cpu().numpy().reshape(self.n, NEXP)
-        sa = self.sums_a.cpu().numpy().reshape(self.n, NF)
-        return [check(sb[i], sa[i], S * S, self.ratios[i], self.mass_tol, self.solute_tol)
-                for i in range(self.n)]
+        host = self.sums.cpu().numpy()
+        sb = host[:self.n * NEXP].reshape(self.n, NEXP)
+        sa = host[self.n * NEXP:].reshape(self.n, NF)
+        return check_all(sb, sa, S * S, self.ratios, self.mass_tol, self.solute_tol)
 
     def stride(self):
         """One screened stride; returns the accept mask (list of bool) and the

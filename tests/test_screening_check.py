@@ -78,3 +78,22 @@ def test_solute_drift_and_non_finite_predictions():
     a[0] = a[0].copy()
     a[0][5, 5] = np.nan
     assert not sg.check(_sums(b), _sums(a), n, 0.1)[0]
+
+
+def test_check_all_equals_check_per_grid():
+    """The vectorised check over many grids returns exactly what check()
+    returns grid by grid: random sums around the accept threshold, a
+    non-finite prediction, a zero solute sum, with and without the solute
+    tolerance."""
+    rng = np.random.default_rng(3)
+    n, npx = 40, 256 * 256
+    sb = rng.uniform(-1, 1, size=(n, 8)) * npx * np.array([0.3, 1, 0.1, 0.05, 1e-3, 1e-3, 1, 1])
+    sa = sb[:, :6] + rng.normal(0, 1, size=(n, 6)) * np.array([30, 10, 1, 1e-3, 1e-4, 1e-4])
+    sa[5, 2] = np.nan
+    sb[7, 3] = 0.0
+    ratios = rng.uniform(0, 0.15, size=n)
+    for tol in (None, 1e-4):
+        got = sg.check_all(sb, sa, npx, ratios, sg.MASS_TOL, tol)
+        ref = [sg.check(sb[i], sa[i], npx, ratios[i], sg.MASS_TOL, tol) for i in range(n)]
+        assert got == ref
+    assert 0 < sum(g[0] for g in got) < n and not got[5][0]
