@@ -7,7 +7,8 @@
  *   1. closure       phi0 = sum f, E0 = sum h, C = sum l; enthalpy map (Eq. Hfl)
  *                    with a liquid-fraction weight psi; phase-change source
  *                    mdot (Eq. NS1); phi from the phase-field moment equation
- *                    (Sec. 3.1) with div u = mdot; property interpolation
+ *                    (Sec. 3.1) with div u the isotropic-stencil divergence
+ *                    of the previous step's velocity; property interpolation
  *                    (end of Sec. 2).
  *   2. stencils      isotropic gradient / Laplacian (end of Sec. 3.4).
  *   3. forces        chemical potential, capillary + Marangoni force (Eq. Fs),
@@ -577,7 +578,13 @@ static double forces_node(const lbref_state* s, int n, double* u, double* F, dou
    * bulk, where grad phi is rounding noise; it is taken as
    * grad phi / max(|grad phi|, 1e-6), exact wherever an interface is resolved
    * and continuous, so that noise cannot pick its direction. */
+#ifdef LBREF_HARD_NORMAL_CUTOFF
+  /* the literal normal with a hard cut-off in the bulk, built only by the
+   * test that compares the two forms */
+  for (int a = 0; a < 3; ++a) nvec[a] = ng >= 1e-10 ? gphi[a] / ng : 0.0;
+#else
   for (int a = 0; a < 3; ++a) nvec[a] = gphi[a] / fmax(ng, 1e-6);
+#endif
   /* Chemical potential with phi1 = 1, phi2 = -1, k = 1, beta = 1/(4 eps^2). */
   double mu = phi * (phi * phi - 1.0) / (P->eps * P->eps) - s->lapphi[n];
   double sigma = P->sigma0 + P->sigma_T * (s->T[n] - P->T_ref) + P->sigma_c * (s->C[n] - P->c_ref);
@@ -617,8 +624,13 @@ static double forces_node(const lbref_state* s, int n, double* u, double* F, dou
   for (int i = 1; i < Lg->q; ++i) sum_nz += s->g[i * N + n];
   double tau_g = P->nu / CS2 + 0.5;
   double s0 = Lg->w[0] * (-dot3(u, u) / (2.0 * CS2));
-  /* Sec. 3.2 pressure, with the literal tau dt G_0 term. */
-  return CS2 / (1.0 - Lg->w[0]) * (sum_nz + 0.5 * S + tau_g * G[0] + rho * s0);
+  /* Sec. 3.2 pressure.  Reading: the rest population's non-equilibrium part
+   * enters as (tau - 1/2) dt G_0.  The collision adds the source with the
+   * weight (1 - 1/(2 tau)), so to first order g_0 - g_0^eq = -tau dt d_t g_0^eq
+   * + (tau - 1/2) dt G_0; the printed "tau dt G_0" leaves dt G_0 / 2 of the
+   * source in the pressure, which makes the volume change of freezing in a
+   * closed box depend on the viscosity. */
+  return CS2 / (1.0 - Lg->w[0]) * (sum_nz + 0.5 * S + (tau_g - 0.5) * G[0] + rho * s0);
 }
 
 static void collide_all(lbref_state* s) {

@@ -36,28 +36,39 @@ class LbrefParams(ctypes.Structure):
                 + [("body_force", ctypes.c_double * 3)])
 
 
-def build(force: bool = False) -> str:
+# Variants of the oracle built from the same source with one reading
+# switched, for the tests that compare readings: name -> gcc defines.
+VARIANTS = {"hard_cutoff": ["-DLBREF_HARD_NORMAL_CUTOFF"]}
+
+
+def _lib_path(variant=None) -> str:
+    return _LIB_PATH if variant is None else os.path.join(_HERE, f"liblbref_{variant}.so")
+
+
+def build(force: bool = False, variant=None) -> str:
     """Compile ``lbref.c`` with gcc (-O2, no fast-math, OpenMP for loops)."""
     src = os.path.join(_HERE, "lbref.c")
-    if force or not os.path.exists(_LIB_PATH) or (
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(src)):
-        tmp = _LIB_PATH + ".tmp"
+    path = _lib_path(variant)
+    if force or not os.path.exists(path) or (os.path.getmtime(path) < os.path.getmtime(src)):
+        tmp = path + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
-               "-fopenmp", "-Wall", "-Wno-unknown-pragmas", "-o", tmp, src, "-lm"]
+               "-fopenmp", "-Wall", "-Wno-unknown-pragmas"]
+        cmd += VARIANTS[variant] if variant is not None else []
+        cmd += ["-o", tmp, src, "-lm"]
         subprocess.check_call(cmd, cwd=_HERE)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, path)
+    return path
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build()
-        L = ctypes.CDLL(_LIB_PATH)
+def lib(variant=None):
+    if variant not in _libs:
+        path = _lib_path(variant)
+        if variant is not None or not os.path.exists(path):
+            build(variant=variant)
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(LbrefParams)
         L.lbref_create.argtypes = [pp, dp, dp, dp, ctypes.c_void_p, ctypes.c_void_p]
@@ -88,8 +99,8 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         L.lbref_lattice.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, ip]
         L.lbref_lattice.restype = ctypes.c_int
-        _lib = L
-    return _lib
+        _libs[variant] = L
+    return _libs[variant]
 
 
 def _dptr(a: np.ndarray):
@@ -114,7 +125,8 @@ def make_params(cfg: dict, threads: int = 1) -> LbrefParams:
 class Oracle:
     """One FP64 oracle instance: create from initial (phi, T, C[, mask])."""
 
-    def __init__(self, cfg: dict, phi, T, C, mask=None, threads: int = 1):
+    def __init__(self, cfg: dict, phi, T, C, mask=None, threads: int = 1, variant=None):
+        self._L = lib(variant)
         self.cfg = dict(cfg)
         self.P = make_params(cfg, threads)
         self.shape = (self.P.nz, self.P.ny, self.P.nx) if self.P.dim == 3 else (self.P.ny, self.P.nx)
@@ -131,7 +143,7 @@ class Oracle:
             self._mask = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
             mptr = self._mask.ctypes.data_as(ctypes.c_void_p)
         h = ctypes.c_void_p()
-        rc = lib().lbref_create(ctypes.byref(self.P), _dptr(phi), _dptr(T), _dptr(C), mptr,
+        rc = self._L.lbref_create(ctypes.byref(self.P), _dptr(phi), _dptr(T), _dptr(C), mptr,
                                 ctypes.byref(h))
         if rc != 0:
             raise ValueError(f"lbref_create failed with code {rc}")
@@ -140,51 +152,51 @@ class Oracle:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().lbref_destroy(h)
+            self._L.lbref_destroy(h)
             self._h = None
 
     def step(self, n: int = 1):
-        rc = lib().lbref_step(self._h, int(n))
+        rc = self._L.lbref_step(self._h, int(n))
         if rc != 0:
             raise RuntimeError(f"lbref_step failed with code {rc}")
 
     def fields(self) -> dict:
         names = ("phi", "fl", "T", "C", "ux", "uy", "uz", "p", "rho")
         out = {k: np.empty(self.N) for k in names}
-        rc = lib().lbref_fields(self._h, *[_dptr(out[k]) for k in names])
+        rc = self._L.lbref_fields(self._h, *[_dptr(out[k]) for k in names])
         if rc != 0:
             raise RuntimeError("lbref_fields failed")
         return {k: v.reshape(self.shape) for k, v in out.items()}
 
     def totals(self) -> dict:
         out = np.empty(9)
-        lib().lbref_totals(self._h, _dptr(out))
+        self._L.lbref_totals(self._h, _dptr(out))
         keys = ("sum_f", "sum_l", "sum_h", "mpc", "vol_solid", "vol_sl", "step", "nonfinite",
                 "qsum")
         return dict(zip(keys, out.tolist()))
 
     def q(self, which: int) -> int:
-        return lib().lbref_q(self.P.dim, which)
+        return self._L.lbref_q(self.P.dim, which)
 
     def get_pops(self, which: int) -> np.ndarray:
         out = np.empty(self.q(which) * self.N)
-        lib().lbref_get_pops(self._h, which, _dptr(out))
+        self._L.lbref_get_pops(self._h, which, _dptr(out))
         return out.reshape((self.q(which),) + self.shape)
 
     def set_pops(self, which: int, arr) -> None:
         a = np.ascontiguousarray(arr, dtype=np.float64).reshape(-1)
         assert a.size == self.q(which) * self.N
-        lib().lbref_set_pops(self._h, which, _dptr(a))
+        self._L.lbref_set_pops(self._h, which, _dptr(a))
 
     def get_state(self, which: int) -> np.ndarray:
         out = np.empty(self.N)
-        lib().lbref_get_state(self._h, which, _dptr(out))
+        self._L.lbref_get_state(self._h, which, _dptr(out))
         return out.reshape(self.shape)
 
     def set_state(self, which: int, arr) -> None:
         a = np.ascontiguousarray(arr, dtype=np.float64).reshape(-1)
         assert a.size == self.N
-        lib().lbref_set_state(self._h, which, _dptr(a))
+        self._L.lbref_set_state(self._h, which, _dptr(a))
 
 
 def enthalpy_map(cfg: dict, E: float, psi: float):

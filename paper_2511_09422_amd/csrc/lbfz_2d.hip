@@ -248,12 +248,6 @@ __device__ __forceinline__ Slot close_slot(const KParams& P, const Raw& r, int y
   return s;
 }
 
-#ifdef LBFZ_WPE
-#define LBFZ_OCC __attribute__((amdgpu_waves_per_eu(LBFZ_WPE, 8)))
-#else
-#define LBFZ_OCC
-#endif
-
 // One tile of one step (the body of the single-grid and the batched kernels).
 template <bool DRY, int ST, int TY>
 __device__ __forceinline__ void step2d_tile(const KParams& P, const StepArgs& A, const int tile) {
@@ -436,7 +430,7 @@ __device__ __forceinline__ void step2d_tile(const KParams& P, const StepArgs& A,
 #pragma unroll
   for (int i = 1; i < 9; ++i) sum_nz += g[i];
   const float s0 = W9[0] * (-1.5f * uu);
-  const float pn = (kCs2 / (1.0f - W9[0])) * (sum_nz + 0.5f * S + P.tau_g * G[0] + rho * s0);
+  const float pn = (kCs2 / (1.0f - W9[0])) * (sum_nz + 0.5f * S + P.tau_gp * G[0] + rho * s0);
 
   if (DRY) {
     if (valid) {
@@ -635,7 +629,7 @@ __device__ __forceinline__ void step2d_tile(const KParams& P, const StepArgs& A,
 }
 
 template <bool DRY, int ST, int TY>
-__global__ __launch_bounds__(Geo<TY>::NT) LBFZ_OCC void k_step2d(KParams P, StepArgs A) {
+__global__ __launch_bounds__(Geo<TY>::NT) void k_step2d(KParams P, StepArgs A) {
   // consecutive steps walk the tiles in opposite directions
   step2d_tile<DRY, ST, TY>(
       P, A, A.rev ? xcd_tile_rev(blockIdx.x, P.nblk) : xcd_tile(blockIdx.x, P.nblk));

@@ -584,7 +584,7 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
       for (int i = 1; i < 19; ++i) sum_nz += g[i];
       const float srest = W19[0] * (-1.5f * uu);
       const float pn =
-          (kCs2 / (1.0f - W19[0])) * (sum_nz + 0.5f * S_ + P.tau_g * G0 + rho * srest);
+          (kCs2 / (1.0f - W19[0])) * (sum_nz + 0.5f * S_ + P.tau_gp * G0 + rho * srest);
       if (DRY) {
         float* const* o = A.out;
         if (o[0]) st_keep(rsrc(o[0], NB), on, 0, phi);

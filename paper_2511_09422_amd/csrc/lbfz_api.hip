@@ -26,11 +26,11 @@ struct Layout {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-#ifndef LBFZ_PLANE_PAD
-#define LBFZ_PLANE_PAD 1088
-#endif
-// Elements between consecutive planes of a population or velocity array.
-size_t plane_stride(size_t N) { return ((N + 63) / 64) * 64 + LBFZ_PLANE_PAD; }
+// Elements between consecutive planes of a population or velocity array: the
+// node count rounded up to 64 plus a skew of 4 KiB + 256 B, so that the planes
+// of one node do not all start on the same HBM channel and bank.
+constexpr size_t kPlanePad = 1088;
+size_t plane_stride(size_t N) { return ((N + 63) / 64) * 64 + kPlanePad; }
 
 bool valid_params(const lbfz_params* p) {
   if (!p) return false;
@@ -39,6 +39,18 @@ bool valid_params(const lbfz_params* p) {
   if (p->dim == 2 && p->nz != 1) return false;
   if (p->dim == 3 && p->nz < 2) return false;
   if ((long long)p->nx * p->ny * p->nz > (1ll << 26)) return false;
+  // Every global access goes through a buffer descriptor with a 32-bit byte
+  // range and 32-bit offsets; the widest one spans a whole population set
+  // (the flow set: 19 planes of 4 bytes in 3D FP32, 18 of 2 bytes in 3D
+  // 16-bit storage, 9 of 4 bytes in 2D) plus the set's leading pad, so that
+  // span must stay below 2^32 bytes.
+  {
+    const long long N = (long long)p->nx * p->ny * p->nz;
+    const long long ps = (long long)plane_stride((size_t)N);
+    const long long widest =
+        p->dim == 3 ? (p->storage == LBFZ_STORE_F32 ? 19 * 4 : 18 * 2) : 9 * 4;
+    if (widest * ps + 4096 >= (1ll << 32)) return false;
+  }
   if (!(p->tau_phi > 0.5 && p->tau_h > 0.5 && p->tau_c > 0.5 && p->nu > 0.0)) return false;
   if (!(p->eps > 0.0 && p->rhoc_ref > 0.0)) return false;
   if (!(p->rho_l > 0 && p->rho_g > 0 && p->rho_s > 0)) return false;
@@ -122,7 +134,7 @@ KParams make_kparams(const lbfz_params* p, int nbx, int nby, int nbz) {
   k.ratio = (float)(1.0 - p->rho_s / p->rho_l);
   const double cs2 = 1.0 / 3.0;
   const double tau_g = p->nu / cs2 + 0.5;
-  k.tau_g = (float)tau_g;
+  k.tau_gp = (float)(tau_g - 0.5);
   k.itau_g = (float)(1.0 / tau_g);
   k.wg = (float)(1.0 - 0.5 / tau_g);
   k.itau_f = (float)(1.0 / p->tau_phi);

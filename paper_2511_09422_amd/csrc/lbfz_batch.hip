@@ -479,8 +479,15 @@ int lbfz_batch_select(lbfz_batch* b, int32_t n, const int32_t* idx) {
 int lbfz_batch_restart_many(lbfz_batch* b, int32_t n, const int32_t* idx,
                             const float* const* d_fields, const int64_t* case_stride) {
   if (!b || n < 0 || (n > 0 && (!idx || !d_fields || !case_stride))) return LBFZ_EINVAL;
-  for (int k = 0; k < n; ++k)
-    if (idx[k] < 0 || idx[k] >= b->ncases) return LBFZ_EINVAL;
+  // the device job table holds ncases entries: at most one job per grid
+  if (n > b->ncases) return LBFZ_EINVAL;
+  {
+    std::vector<char> seen(b->ncases, 0);
+    for (int k = 0; k < n; ++k) {
+      if (idx[k] < 0 || idx[k] >= b->ncases || seen[idx[k]]) return LBFZ_EINVAL;
+      seen[idx[k]] = 1;
+    }
+  }
   sync_handles(b);
   if (n == 0) return LBFZ_OK;
   if (b->storage == LBFZ_STORE_F32) {

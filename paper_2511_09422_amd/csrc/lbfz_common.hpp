@@ -26,7 +26,9 @@ struct KParams {
   float rhoc_ref, rho_l_latent, T_sol, T_liq;
   float ratio;  // 1 - rho_s / rho_l (Eq. NS1)
   // relaxation (Sec. 3.1-3.4)
-  float tau_g, itau_g, wg;  // wg = 1 - 1/(2 tau)
+  // tau_gp = tau_g - 1/2: the weight of G_0 in the pressure (Sec. 3.2; the
+  // first-order non-equilibrium part of the rest population); wg = 1 - 1/(2 tau)
+  float tau_gp, itau_g, wg;
   float itau_f, wf;
   float itau_a, itau_s, ws;  // enthalpy TRT: antisymmetric / symmetric
   float Dl, Ds, k_p;
@@ -118,12 +120,8 @@ __device__ __forceinline__ double block_sum(double v, double* sred) {
 // absorb (FP32 step 217 -> 209 us at 2048^2).  The planes' padding holds the
 // one element a plane reaches past either end.  The 3D step keeps its planes
 // unshifted: shifted, its FP32 step was no faster and its 16-bit step slower
-// (its reads are the critical path).  LBFZ_XSHIFT 0 builds 2D unshifted too
-// (for comparison).
-#ifndef LBFZ_XSHIFT
-#define LBFZ_XSHIFT 1
-#endif
-constexpr int kXS = LBFZ_XSHIFT;
+// (its reads are the critical path).
+constexpr int kXS = 1;
 // A 2D population set's buffer descriptor starts this many bytes before its
 // first plane, so that the (unsigned) plane offsets stay positive for a
 // first plane shifted by -1 element.
@@ -145,20 +143,17 @@ __device__ __forceinline__ rsrc_t rsrc(const void* base, uint32_t bytes) {
 // (every plane a step writes is read only by the next step, after the whole
 // grid has streamed through the caches; 2048^2 FP32 step 208 -> 200 us),
 // loads the default policy (non-temporal loads lose the reuse of the halo
-// rows between neighbouring tiles: 254 us).
-#ifndef LBFZ_LD_AUX
-#define LBFZ_LD_AUX 0
-#endif
-#ifndef LBFZ_ST_AUX
-#define LBFZ_ST_AUX 2
-#endif
+// rows between neighbouring tiles: 254 us).  The values are the cache-policy
+// operand of the buffer instructions: 0 default, 2 non-temporal.
+constexpr int kLdPolicy = 0;
+constexpr int kStPolicy = 2;
 __device__ __forceinline__ float ld(rsrc_t r, uint32_t off, uint32_t soff = 0) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff,
-                                                                          LBFZ_LD_AUX));
+                                                                          kLdPolicy));
 }
 __device__ __forceinline__ void st(rsrc_t r, uint32_t off, uint32_t soff, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, (int)soff,
-                                        LBFZ_ST_AUX);
+                                        kStPolicy);
 }
 // Stores with the default cache policy: the 3D step's (its two launches read
 // the closure fields back at once, and its population writes measured
@@ -170,13 +165,13 @@ __device__ __forceinline__ void st16_keep(rsrc_t r, uint32_t off, uint32_t soff,
   __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, (int)soff, 0);
 }
 __device__ __forceinline__ uint16_t ld16(rsrc_t r, uint32_t off, uint32_t soff) {
-  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, LBFZ_LD_AUX);
+  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, kLdPolicy);
 }
 __device__ __forceinline__ uint8_t ld8(rsrc_t r, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
 }
 __device__ __forceinline__ void st16(rsrc_t r, uint32_t off, uint32_t soff, uint16_t v) {
-  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, (int)soff, LBFZ_ST_AUX);
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, (int)soff, kStPolicy);
 }
 
 // 16-bit storage: offsets from the reference are scaled by these powers of two

@@ -143,7 +143,7 @@ def step(P, pops, state):
             G.append(W9[i] * (S + (cx * (Fx + r * fdx) + cy * (Fy + r * fdy)) / CS2 + A / (2 * CS2 ** 2)))
         uu = ux * ux + uy * uy
         s0 = W9[0] * (-uu / (2 * CS2))
-        pn = CS2 / (1 - W9[0]) * (sum(g[1:]) + S / 2 + tau_g * G[0] + r * s0)
+        pn = CS2 / (1 - W9[0]) * (sum(g[1:]) + S / 2 + (tau_g - mpf(1) / 2) * G[0] + r * s0)
         for i in range(9):
             cx, cy = C9[i]
             cu = cx * ux + cy * uy

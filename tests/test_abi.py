@@ -122,3 +122,17 @@ def test_tail_args_struct_and_conv_tail_rejections():
                 dict(pred=None), dict(in_=None), dict(out=fake, out_co=8)):
         a, t = args(**bad)
         assert L.lbfz_nn_conv_tail(ctypes.byref(a), ctypes.byref(t), None) == sg.LBFZ_NN_EINVAL, bad
+
+
+def test_descriptor_range_limits_grid_size():
+    """Every access goes through a buffer descriptor with a 32-bit byte range:
+    a 3D FP32 grid whose 19-plane flow set spans 2^32 bytes or more (384^3:
+    76 B x 56.6 M nodes) is rejected, the same grid with 16-bit storage (36 B
+    per node in its widest set) is accepted, as is the largest 2D grid."""
+    big = dict(dim=3, nx=384, ny=384, nz=384)
+    with pytest.raises(lbfz.LbfzError) as e:
+        lbfz.lbfz_workspace_bytes(base_params(**big))
+    assert e.value.code == lbfz.LBFZ_EINVAL
+    assert lbfz.lbfz_workspace_bytes(base_params(**big), "f16") > 0
+    assert lbfz.lbfz_workspace_bytes(base_params(dim=3, nx=320, ny=320, nz=320)) > 0
+    assert lbfz.lbfz_workspace_bytes(base_params(nx=8192, ny=8192)) > 0

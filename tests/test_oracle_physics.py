@@ -205,16 +205,14 @@ def _table1():
     return np.array(rows)
 
 
-@pytest.mark.parametrize("ratio", [0.8, 0.9, 1.2])
-def test_stefan_volume_change_final_height(ratio):
-    """Liquid layer h_0 = 20 under gas, frozen from the cold low wall; the
-    final height of the phase-change material is rho_l h_0 / rho_s."""
-    tab = _table1()
-    row = tab[np.isclose(tab[:, 0], ratio)][0]
-    assert abs(row[1] - 1.0 / ratio) < 1e-3          # the printed analytical column
-    ny, h0 = 64, 20.0
-    cfg = base_params(nx=2, ny=ny, rho_s=ratio, rho_g=0.1, rhoc_ref=0.1, tau_h=3.5,
-                      latent=1.0, sigma_T=0.0)
+def _final_height(ratio, h0=20.0, ny=128, rho_g=0.1, nu=0.1):
+    """Final phi = 0 height of a liquid layer h_0 under gas, frozen from the
+    cold low wall (Sec. 4.2): T = T_m initially, Ste = 1, closed box.  The
+    enthalpy reference (rho C)_ref is the gas heat capacity, with tau_h set
+    for the conductivity 0.1."""
+    rhoc = rho_g
+    cfg = base_params(nx=2, ny=ny, rho_s=ratio, rho_g=rho_g, rhoc_ref=rhoc,
+                      tau_h=0.1 / (rhoc / 3.0) + 0.5, latent=1.0, sigma_T=0.0, nu=nu)
     y = (np.arange(ny) + 0.5)[:, None] * np.ones((1, 2))
     phi = np.tanh((h0 - y) / 2.0)
     o = Oracle(cfg, phi, np.zeros_like(phi), np.zeros_like(phi))
@@ -227,12 +225,42 @@ def test_stefan_volume_change_final_height(ratio):
         if prev is not None and abs(h - prev) < 1e-3:
             break
         prev = h
-    hf = h / h0
-    # direction and size of the volume change; tolerance covers the
-    # diffuse-interface error at this resolution (the paper's Table 1 errors
-    # reach 7e-3)
+    return h / h0
+
+
+@pytest.mark.parametrize("ratio,rho_g,bar", [(0.9, 0.02, 7e-3), (0.8, 0.1, 2.5e-2),
+                                             (1.2, 0.1, 2.5e-2)])
+def test_stefan_volume_change_final_height(ratio, rho_g, bar):
+    """Liquid layer h_0 = 20 under gas in a closed 128-node column, frozen
+    from the cold low wall; the final height of the phase-change material is
+    rho_l h_0 / rho_s (Sec. 4.2, Table 1).  At rho_s / rho_l = 0.9 with a
+    light gas (rho_g = 0.02, so the gas takes nearly all of the closed box's
+    compression) within the paper's largest printed error, 7e-3 (measured
+    -0.56 %).  At 0.8 and 1.2 with the workloads' gas (rho_g = 0.1) within
+    2.5 % (measured -2.35 % / +1.55 %) and always on the side of a smaller
+    volume change: the phase-change material takes its share of the closed
+    box's compression, and the part of the volume source released while the
+    surface layer freezes inside the diffuse interface is counted at the
+    weight (1 + phi)/2 there."""
+    tab = _table1()
+    row = tab[np.isclose(tab[:, 0], ratio)][0]
+    assert abs(row[1] - 1.0 / ratio) < 1e-3          # the printed analytical column
+    hf = _final_height(ratio, rho_g=rho_g)
     assert (hf - 1.0) * (1.0 / ratio - 1.0) > 0
-    assert abs(hf / row[1] - 1.0) < 2.5e-2
+    assert abs(hf / row[1] - 1.0) < bar, (ratio, hf)
+    assert abs(hf - 1.0) < abs(row[1] - 1.0)          # never more than the full change
+
+
+def test_stefan_volume_change_does_not_depend_on_viscosity():
+    """The final height of the closed-box three-phase Stefan problem is a
+    volume budget and cannot depend on the viscosity.  It does not when the
+    pressure of Sec. 3.2 takes the rest population's non-equilibrium part as
+    (tau - 1/2) G_0 (measured h_f / h_0 = 1.0991 at nu = 0.1, 1.0988 at
+    nu = 0.5, 64-node column); with the printed tau G_0 they differ by 1.6 %
+    (1.1289 vs 1.1107), and by 2.8 % more at nu = 0.02."""
+    a = _final_height(0.9, ny=64, nu=0.1)
+    b = _final_height(0.9, ny=64, nu=0.5)
+    assert abs(a / b - 1.0) < 1.5e-3, (a, b)
 
 
 def test_two_layer_thermocapillary_matches_appendix_a():
@@ -287,3 +315,59 @@ def test_two_layer_thermocapillary_matches_appendix_a():
     xi = Lx // 4
     expect = sigT * (-w) * T0 * f * math.sinh(Ht)
     assert abs(Fx[:, xi].sum() / expect - 1) < 0.08
+
+
+def test_normal_regularisation_leaves_the_physics_pins_unchanged():
+    """Reading R19: the interface normal n = grad phi / |grad phi| (Sec. 3.1,
+    3.4) is taken as grad phi / max(|grad phi|, 1e-6) instead of the literal
+    form with a hard cut-off at |grad phi| < 1e-10.  Where an interface is
+    resolved |grad phi| is of order 1/(sqrt(2) eps) and the two agree; in the
+    bulk the compressive flux (1 - phi^2) n and the solute flux carry
+    (1 - phi^2) or (1 - phi), which vanish there.  The pins that involve the
+    normal give the same results with both forms, each difference far
+    inside its pin's bar: the flat tanh profile (phi differs by 3.4e-6 after
+    2000 steps, in the bulk where |grad phi| lies between the two cut-offs;
+    the pin allows 2e-2), Laplace's law (dp R / sigma 0.93566 both; pin
+    3 %), the freezing front under a gas layer (relative 9e-7; pin 5e-3) and
+    the Table 1 final height (relative 1.3e-5; pin 7e-3)."""
+    # flat tanh interface
+    n, w = 64, 2.0
+    cfg = base_params(nx=4, ny=n, walls=0, sigma_T=0.0, T_sol=-10.0, T_liq=-10.0)
+    y = np.arange(n, dtype=float)[:, None] * np.ones((1, 4))
+    phi = np.tanh((y - 16.0) / w) - np.tanh((y - 48.0) / w) - 1.0
+    res = []
+    for v in (None, "hard_cutoff"):
+        o = Oracle(cfg, phi, np.ones_like(phi), 0.05 * np.clip((1 + phi) / 2, 0, 1), variant=v)
+        o.step(2000)
+        res.append(o.fields()["phi"])
+    assert np.abs(res[0] - res[1]).max() < 2e-5          # profile pin: 2e-2
+    # Laplace's law, W = 4, R = 12
+    eps = 4.0 / (2 * math.sqrt(2))
+    cfg = base_params(nx=64, ny=64, walls=0, sigma_T=0.0, T_sol=-10.0, T_liq=-10.0, eps=eps)
+    yy, xx = np.meshgrid(np.arange(64, dtype=float), np.arange(64, dtype=float), indexing="ij")
+    d = np.hypot(xx - 32, yy - 32)
+    phi = np.tanh((12.0 - d) / (math.sqrt(2) * eps))
+    dp = []
+    for v in (None, "hard_cutoff"):
+        o = Oracle(cfg, phi, np.ones_like(phi), 0.05 * np.clip((1 + phi) / 2, 0, 1),
+                   threads=THREADS, variant=v)
+        o.step(3000)
+        p = o.fields()["p"]
+        dp.append((p[d < 8].mean() - p[d > 16].mean()) * 12.0 / cfg["sigma0"])
+    assert abs(dp[0] - dp[1]) < 1e-4, dp                  # Laplace pin: 3e-2
+    # freezing front under a gas layer (Stefan problem with volume change)
+    cfg = base_params(nx=2, ny=64, rho_s=0.9, rho_g=0.1, rhoc_ref=0.1,
+                      tau_h=0.1 / (0.1 / 3.0) + 0.5, latent=1.0, sigma_T=0.0)
+    yc = (np.arange(64) + 0.5)[:, None] * np.ones((1, 2))
+    phi = np.tanh((20.0 - yc) / 2.0)
+    fronts, heights = [], []
+    for v in (None, "hard_cutoff"):
+        o = Oracle(cfg, phi, np.zeros_like(phi), np.zeros_like(phi), variant=v)
+        o.step(1500)
+        fronts.append((1.0 - o.fields()["fl"][:, 0])[:12].sum())
+        o.step(6500)
+        p = o.fields()["phi"][:, 0]
+        j = int(np.where(p < 0)[0][0])
+        heights.append((j - 1) + p[j - 1] / (p[j - 1] - p[j]) + 0.5)
+    assert abs(fronts[0] / fronts[1] - 1) < 1e-5, fronts   # front pin: 5e-3
+    assert abs(heights[0] / heights[1] - 1) < 1e-4, heights  # Table 1 pin: 7e-3

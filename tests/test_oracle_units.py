@@ -207,3 +207,60 @@ def test_alpha_normalises_delta():
     dphi = (1.0 / (math.sqrt(2) * eps)) / np.cosh(x / (math.sqrt(2) * eps)) ** 2
     integral = np.trapezoid(3 * math.sqrt(2) * eps / 4 * dphi ** 2, x)
     assert abs(integral - 1.0) < 1e-8
+
+
+def _d3q19():
+    cs = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    cs += [(a, b, 0) for a in (1, -1) for b in (1, -1)]
+    cs += [(a, 0, b) for a in (1, -1) for b in (1, -1)]
+    cs += [(0, a, b) for a in (1, -1) for b in (1, -1)]
+    ws = [1 / 3] + [1 / 18] * 6 + [1 / 36] * 12
+    return cs, ws
+
+
+def _stencil_on_extension(ext, nz):
+    """Isotropic gradient and Laplacian (flow-lattice weights) of the nz
+    interior z planes of a field given on z = -1 .. nz (ghost planes
+    included), periodic in x and y."""
+    cs, ws = _d3q19()
+    core = ext[1:nz + 1]
+    g = np.zeros((3,) + core.shape)
+    lp = np.zeros(core.shape)
+    for (cx, cy, cz), w in zip(cs[1:], ws[1:]):
+        nb = np.roll(np.roll(ext, -cx, axis=2), -cy, axis=1)[1 + cz:nz + 1 + cz]
+        for a, c in enumerate((cx, cy, cz)):
+            g[a] += w * c * nb / CS2
+        lp += 2 * w * (nb - core) / CS2
+    return g, lp
+
+
+def test_stencil_wall_ghosts_3d():
+    """3D, walls on z: the oracle's stencils equal the same stencil applied
+    to an explicitly extended field -- mirror planes beyond each wall for the
+    phase-field kind, 2 T_w - T of the mirror plane for the temperature at
+    Dirichlet walls (the low one modulated in x) -- for fields that vary in
+    x, y and z, so that the D3Q19 edge links crossing a wall are exercised;
+    and a temperature linear in z through T_w gets its exact gradient."""
+    nx, ny, nz = 6, 5, 7
+    Tlo, amp, Thi = -0.7, 0.2, 0.3
+    cfg = base_params(dim=3, nx=nx, ny=ny, nz=nz, walls=1, t_lo_dirichlet=1, t_hi_dirichlet=1,
+                      T_lo=Tlo, T_lo_amp=amp, T_hi=Thi)
+    rng = np.random.default_rng(9)
+    fld = rng.normal(size=(nz, ny, nx))
+    ext = np.concatenate([fld[:1], fld, fld[-1:]], axis=0)
+    g, lp = lbref.grad_lap(cfg, fld, kind=0)
+    ge, le = _stencil_on_extension(ext, nz)
+    assert np.allclose(g, ge, atol=1e-13) and np.allclose(lp, le, atol=1e-13)
+    x = np.arange(nx, dtype=float)
+    tw = Tlo + amp * np.cos(2 * np.pi * x / nx)
+    T = rng.normal(size=(nz, ny, nx))
+    ext = np.concatenate([2 * tw[None, None, :] - T[:1], T, 2 * Thi - T[-1:]], axis=0)
+    g, lp = lbref.grad_lap(cfg, T, kind=1)
+    ge, le = _stencil_on_extension(ext, nz)
+    assert np.allclose(g, ge, atol=1e-13) and np.allclose(lp, le, atol=1e-13)
+    # exactness: T = T_w + s (z + 1/2) with uniform wall temperatures
+    cfg0 = dict(cfg, T_lo_amp=0.0, T_hi=Tlo + 0.1 * nz)
+    z = np.arange(nz, dtype=float)[:, None, None] * np.ones((1, ny, nx))
+    g, lp = lbref.grad_lap(cfg0, Tlo + 0.1 * (z + 0.5), kind=1)
+    assert np.allclose(g[2], 0.1, atol=1e-13) and np.allclose(g[:2], 0.0, atol=1e-13)
+    assert np.allclose(lp, 0.0, atol=1e-12)
