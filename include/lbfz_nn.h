@@ -137,6 +137,21 @@ int lbfz_nn_fill_u32(void* p, long n, uint32_t v, void* stream);
 int lbfz_nn_mse(const float* out, int out_cs, const float* tgt, long P, int C, const float* wch,
                 void* dout, double* part, int nblocks, double* loss, void* stream);
 
+/* lbfz_nn_mse without a caller-provided partial-sum buffer, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops
+ * that forbid hipMalloc).  The nblocks FP64 partials live in a fixed array of
+ * LBFZ_NN_MSE_NOALLOC_MAX_BLOCKS doubles (32 KiB) inside the library, one per
+ * GPU, held until the process ends; the call allocates nothing.  Results are
+ * those of lbfz_nn_mse with the same nblocks.  Errors: LBFZ_NN_EINVAL for
+ * nblocks outside 1 .. LBFZ_NN_MSE_NOALLOC_MAX_BLOCKS or the arguments
+ * lbfz_nn_mse rejects; LBFZ_NN_EHIP if the array's device address cannot be
+ * found or a launch fails.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (different streams, or host threads) race
+ * and must be serialised by the caller. */
+#define LBFZ_NN_MSE_NOALLOC_MAX_BLOCKS 4096
+int lbfz_nn_mse_noalloc(const float* out, int out_cs, const float* tgt, long P, int C,
+                        const float* wch, void* dout, int nblocks, double* loss, void* stream);
+
 /* One Adam step (bias-corrected with the 1-based step number) on n FP32
  * weights w with gradients g and moments m, v; wb (bf16, or NULL) receives
  * the updated weights. */

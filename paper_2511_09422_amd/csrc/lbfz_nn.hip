@@ -22,6 +22,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/lbfz_nn.h"
 
@@ -1395,6 +1396,53 @@ int lbfz_nn_mse(const float* out, int out_cs, const float* tgt, long P, int C, c
                 void* dout, double* part, int nblocks, double* loss, void* stream) {
   if (!out || !tgt || !part || !loss || C <= 0 || C > out_cs || nblocks <= 0)
     return LBFZ_NN_EINVAL;
+  hipLaunchKernelGGL(k_mse, dim3(nblocks), dim3(256), 0, (hipStream_t)stream, out, out_cs, tgt, P,
+                     C, wch, static_cast<bf16*>(dout), part);
+  if (hipGetLastError() != hipSuccess) return LBFZ_NN_EHIP;
+  hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, (hipStream_t)stream, part, nblocks, loss);
+  HCHK();
+}
+
+// Per-block partial sums of lbfz_nn_mse_noalloc: a fixed device array, so
+// that the call needs no workspace from its caller.  In host code `scratch`
+// is only a stand-in symbol; kernels get the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[LBFZ_NN_MSE_NOALLOC_MAX_BLOCKS];
+
+// Device address of `scratch`, looked up once per device with that device
+// current; nullptr when the lookup fails.
+static double* scratch_ptr_for_current_device(int* err) {
+  static std::mutex mu;
+  static double* ptrs[256] = {};
+  static bool looked[256] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 256) {
+    *err = LBFZ_NN_EHIP;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!looked[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      *err = LBFZ_NN_EHIP;
+      return nullptr;
+    }
+    ptrs[dev] = static_cast<double*>(p);
+    looked[dev] = true;
+  }
+  return ptrs[dev];
+}
+
+int lbfz_nn_mse_noalloc(const float* out, int out_cs, const float* tgt, long P, int C,
+                        const float* wch, void* dout, int nblocks, double* loss, void* stream) {
+  if (!out || !tgt || !loss || C <= 0 || C > out_cs || nblocks <= 0)
+    return LBFZ_NN_EINVAL;
+  if (nblocks > LBFZ_NN_MSE_NOALLOC_MAX_BLOCKS) return LBFZ_NN_EINVAL;
+  int err = 0;
+  double* part = scratch_ptr_for_current_device(&err);
+  if (!part) return err;
+  // every one of the nblocks partial slots is written by k_mse before
+  // k_sum_f64 reads it, so the array needs no clearing between calls
   hipLaunchKernelGGL(k_mse, dim3(nblocks), dim3(256), 0, (hipStream_t)stream, out, out_cs, tgt, P,
                      C, wch, static_cast<bf16*>(dout), part);
   if (hipGetLastError() != hipSuccess) return LBFZ_NN_EHIP;
