@@ -13,10 +13,11 @@ line.
 
 The roofline entry uses the algorithmic bytes of one node update (every
 population read once and written once, plus the previous-time-level fields
-the scheme carries: 24 populations and 6 scalars, 240 B in FP32; with 16-bit
-storage 4 FP32 rest + 20 16-bit moving populations and 8 scalars read, 7
-written, 172 B) divided by the average launch time measured with HIP events
-on the solver's stream.
+the scheme carries: 24 populations and 6 FP32 scalars, 240 B with FP32
+storage, 144 B with 16-bit storage) divided by the average launch time
+measured with HIP events on the solver's stream; the 16-bit forms also
+report the fraction at the 172 B/node their design moves (FP32 rest
+populations and the decode references).
 The CPU baseline is the FP64 oracle on the host cores, timed on whole steps of
 the same 2048 x 2048 workload.
 """
@@ -54,12 +55,20 @@ def kernel_source_hash() -> str:
 
 
 def bytes_per_node(storage: str) -> int:
+    """Algorithmic bytes of one 2D node update: the 24 populations (D2Q9 + 3 x
+    D2Q5) read and written once in the storage format, and the 6 FP32
+    previous-level scalars (f_s, p, u_x, u_y, phi, C) read and written: 240 B
+    with FP32 storage, 144 B with 16-bit storage."""
+    return 2 * 24 * POP_BYTES[storage] + 2 * 6 * 4
+
+
+def design_bytes_per_node(storage: str) -> int:
+    """Bytes the 2D step is designed to move per node: the algorithmic bytes
+    for FP32 storage; with 16-bit storage the rest populations stay FP32 (4 of
+    the 24) and the decode references add scalars: 8 read (f_s, p, p two
+    levels back, u_x, u_y, phi, C, T) and 7 written, 172 B."""
     if storage == "f32":
-        # 24 populations read + written, 6 FP32 scalars (f_s, p, u_x, u_y, phi,
-        # C) read + written
-        return 2 * 24 * 4 + 2 * 6 * 4
-    # 4 FP32 rest + 20 16-bit moving populations read + written; FP32 scalars:
-    # 8 read (f_s, p, p two levels back, u_x, u_y, phi, C, T) and 7 written
+        return bytes_per_node(storage)
     return 2 * (4 * 4 + 20 * POP_BYTES[storage]) + (8 + 7) * 4
 
 
@@ -71,18 +80,23 @@ def bytes_per_node3d(storage: str) -> int:
     return 2 * 40 * POP_BYTES[storage] + 2 * 8 * 4
 
 
-def cpu_baseline(cfg, phi, T, C, budget_s: float = 12.0) -> dict:
+def cpu_baseline(cfg, phi, T, C, max_steps: int = 200, budget_s: float = 40.0) -> dict:
+    """The FP64 oracle on the host cores: whole steps of the benchmark
+    workload (up to max_steps, stopping once budget_s has passed) with OpenMP
+    over nodes, two steps on one thread, and the 64^2 droplet's full
+    1000-step run on all threads and on one."""
     from oracle.lbref import Oracle
+    from paper_2511_09422_amd.workloads import droplet_2d
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     threads = max(1, min(threads, 16))
     o = Oracle(cfg, phi, T, C, threads=threads)
     o.step(1)                      # first touch of the oracle's arrays
     t0 = time.perf_counter()
     n = 0
-    while True:
+    while n < max_steps:
         o.step(1)
         n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 20:
+        if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
     del o
@@ -94,12 +108,26 @@ def cpu_baseline(cfg, phi, T, C, budget_s: float = 12.0) -> dict:
     o1.step(2)
     dt1 = time.perf_counter() - t1
     del o1
+    # the 64^2 droplet, 1000 steps from its initial fields
+    c1, p1, T1, C1 = droplet_2d(64, 64, R=16.0, seed=0)
+    small = {}
+    for th in (threads, 1):
+        o = Oracle(c1, p1, T1, C1, threads=th)
+        t2 = time.perf_counter()
+        o.step(1000)
+        d2 = time.perf_counter() - t2
+        del o
+        small["threads_%d" % th] = {"s": round(d2, 3),
+                                    "value": round(64 * 64 * 1000 / d2 / 1e6, 4)}
     return {"value": round(N * n / dt / 1e6, 4), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{n} full steps of the {cfg['nx']}x{cfg['ny']} workload after one "
-                      f"untimed step, FP64, OpenMP over nodes",
+                      f"untimed step ({dt:.1f} s), FP64, OpenMP over nodes",
             "single_thread": {"value": round(N * 2 / dt1 / 1e6, 4), "unit": "MLUPS",
                               "sample": "2 full steps after one untimed step"},
+            "droplet_64": {"unit": "MLUPS", "sample": "the 64x64 droplet (R = 16), 1000 "
+                                                      "steps from its initial fields",
+                           **small},
             "cpu": cpu_model(), "nproc": os.cpu_count()}
 
 
@@ -156,38 +184,55 @@ def time_form(cfg, phi, T, C, storage: str, warmup: int, steps: int, mask=None) 
         sys.exit(1)
     N = cfg["nx"] * cfg["ny"] * cfg["nz"]
     bpn = bytes_per_node(storage) if cfg["dim"] == 2 else bytes_per_node3d(storage)
+    dbpn = design_bytes_per_node(storage) if cfg["dim"] == 2 else None
     achieved = bpn * N / (ms_per_step * 1e-3) / 1e9
     return {"ms_per_step": ms_per_step, "mlups": N / (ms_per_step * 1e-3) / 1e6,
-            "bytes_per_node": bpn, "achieved": achieved, "wall": wall}
+            "bytes_per_node": bpn, "achieved": achieved, "wall": wall,
+            "design_bytes_per_node": dbpn,
+            "design_GBs": None if dbpn is None else dbpn * N / (ms_per_step * 1e-3) / 1e9}
 
 
 def time_copy(nbytes: int, reps: int = 20) -> dict:
-    """A plain device-to-device copy that reads and writes nbytes in total
-    (nbytes / 2 each way), timed with HIP events: the bandwidth this memory
-    system gives a pure streaming kernel of the same volume as one step."""
+    """The library's streaming copy (lbfz_stream_copy) reading and writing
+    nbytes in total (nbytes / 2 each way), timed with HIP events on its
+    stream: the bandwidth this memory system gives a pure streaming kernel of
+    the same volume as one step.  The runtime's device copy of the same
+    buffers is timed beside it."""
     import torch
-    n = nbytes // 8
+    from paper_2511_09422_amd.lbfz import lbfz_stream_copy
+    n = (nbytes // 2) // 16 * 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / reps
+    st = torch.cuda.current_stream()
+
+    def run(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(st)
+        for _ in range(reps):
+            fn()
+        ev1.record(st)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+    ms = run(lambda: lbfz_stream_copy(b.data_ptr(), a.data_ptr(), 4 * n, st.cuda_stream))
+    ms_rt = run(lambda: b.copy_(a))
+    ok = bool(torch.equal(a, b))
     del a, b
     torch.cuda.empty_cache()
-    return {"bytes": 8 * n, "us": ms * 1e3, "GBs": 8 * n / (ms * 1e-3) / 1e9}
+    if not ok:
+        print("bench: the stream copy did not reproduce its source", file=sys.stderr)
+        sys.exit(1)
+    return {"bytes": 8 * n, "us": ms * 1e3, "GBs": 8 * n / (ms * 1e-3) / 1e9,
+            "runtime_copy_us": ms_rt * 1e3, "runtime_copy_GBs": 8 * n / (ms_rt * 1e-3) / 1e9}
 
 
 def time_sweep(ncases: int, steps: int, case_steps: int, storage: str) -> dict:
     """The batched parameter sweep: ncases grids drawn by sweep_case(k), tuned,
-    then `steps` batched steps timed with HIP events (graph replays), and a
+    then whole cases -- `steps` batched steps (case_steps by default) --
+    timed with HIP events (graph replays, one kernel node per step), and a
     few steps of the same grids with plain one-grid-at-a-time launches."""
     import torch
     from paper_2511_09422_amd.lbfz import Batch
@@ -205,7 +250,7 @@ def time_sweep(ncases: int, steps: int, case_steps: int, storage: str) -> dict:
     ev1.record(b.stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
-    seq_steps = max(2, steps // 20)
+    seq_steps = 24
     ev0.record(b.stream)
     b.step_sequential(seq_steps)
     ev1.record(b.stream)
@@ -222,6 +267,8 @@ def time_sweep(ncases: int, steps: int, case_steps: int, storage: str) -> dict:
     print(f"bench: sweep {ncases} grids {ms * 1e3:.1f} us/step batched, "
           f"{ms_seq * 1e3:.1f} us/step sequential", file=sys.stderr, flush=True)
     return {"value": round(ncases / (case_steps * ms * 1e-3), 3), "unit": "cases/s",
+            "timed": f"{steps} consecutive steps of every case" +
+                     (" (whole cases)" if steps >= case_steps else ""),
             "cases": ncases, "steps_per_case": case_steps, "nodes": nodes,
             "workload": "sweep_case(k), k < cases: side in {64,128,256,512}, sigma_T, "
                         "Stefan number, rho_s/rho_l, C0 drawn per case; 2D droplet",
@@ -231,6 +278,32 @@ def time_sweep(ncases: int, steps: int, case_steps: int, storage: str) -> dict:
                            "value": round(ncases / (case_steps * ms_seq * 1e-3), 3)},
             "speedup_vs_sequential": round(ms_seq / ms, 3),
             "groups": groups}
+
+
+def copy64_errors(forms) -> dict:
+    """Per-field error of 5000 steps of the 64^3 copy of the 3D workload
+    (drop radius 16, obstacle radius 3) in each storage form, against the
+    FP64 oracle's fields at step 5000 stored in tests/golden (written by the
+    script beside them), with the oracle's own spread under FP32-sized noise
+    from the same file: max |gpu - oracle| / max |oracle| over fluid nodes."""
+    from paper_2511_09422_amd.lbfz import Solver
+    from paper_2511_09422_amd.workloads import droplet_3d
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "droplet3d_64_5000.npz"))
+    names = [str(n) for n in ref["fields"]]
+    cfg, phi, T, C, mask = droplet_3d(64, R=16.0, imp_R=3.0, seed=1)
+    fluid = mask == 0
+    out = {"workload": "64^3 copy of the 3D droplet, R=16, obstacle radius 3, 5000 steps",
+           "oracle_spread": dict(zip(names, [float(f"{v:.3g}") for v in ref["spread"]])),
+           "oracle_single_precision": dict(zip(names, [float(f"{v:.3g}")
+                                                       for v in ref["dev_single"]]))}
+    for f in forms:
+        s = Solver(cfg, phi, T, C, mask=mask, device=0, storage=f)
+        s.step(5000)
+        got = s.fields()
+        s.close()
+        out[f] = {k: float(f"{np.abs(got[k][fluid] - ref[k][fluid]).max() / max(np.abs(ref[k][fluid]).max(), 1e-30):.3g}")
+                  for k in names}
+    return out
 
 
 def unet_flops_per_image(S: int) -> float:
@@ -373,9 +446,13 @@ def main():
     ap.add_argument("--n3d", type=int, default=256,
                     help="side of the 3D droplet workload timed alongside (0: skip)")
     ap.add_argument("--steps3d", type=int, default=200)
+    ap.add_argument("--no-error-64", action="store_true",
+                    help="skip the 5000-step per-field error of the 64^3 copy (profiling runs, "
+                         "which should see only the 256^3 launches of the 3D kernels)")
     ap.add_argument("--sweep-cases", type=int, default=512,
                     help="grids of the batched parameter sweep timed alongside (0: skip)")
-    ap.add_argument("--sweep-steps", type=int, default=240)
+    ap.add_argument("--sweep-steps", type=int, default=10000,
+                    help="batched steps timed (default: one whole case)")
     ap.add_argument("--sweep-case-steps", type=int, default=10000,
                     help="steps that make one sweep case (cases/s is quoted for this length)")
     ap.add_argument("--surrogate-iters", type=int, default=8000,
@@ -418,6 +495,9 @@ def main():
                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": round(r["achieved"] / HBM_PEAK_GBS, 4),
                                  "bytes_per_node": r["bytes_per_node"],
+                                 "design_bytes_per_node": r["design_bytes_per_node"],
+                                 "frac_at_design_bytes":
+                                     round(r["design_GBs"] / HBM_PEAK_GBS, 4),
                                  "traffic": load_traffic(f"k_step2d_{f}_{n}")}}
     droplet3d = None
     if args.n3d:
@@ -445,6 +525,10 @@ def main():
         droplet3d = {"workload": f"3D droplet freezing {m}^3, R={m // 4}, obstacle radius "
                                  f"{12 * m // 256}, D3Q19+3xD3Q7, FP32 arithmetic",
                      "steps": args.steps3d, "forms": forms3}
+        if not args.no_error_64:
+            droplet3d["error_vs_oracle_64"] = copy64_errors([args.storage] + forms)
+            print("bench: 3D 64^3 copy, 5000 steps, error vs oracle: " +
+                  json.dumps(droplet3d["error_vs_oracle_64"]), file=sys.stderr, flush=True)
     sweep = None
     if args.sweep_cases:
         sweep = time_sweep(args.sweep_cases, args.sweep_steps, args.sweep_case_steps,
@@ -480,10 +564,12 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(main_r["achieved"] / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic(f"k_step2d_{args.storage}_{n}")},
-        "copy_ceiling": {"bytes": copy_r["bytes"], "us": round(copy_r["us"], 2),
-                         "GB/s": round(copy_r["GBs"], 1),
+        "copy_ceiling": {"kernel": "lbfz_stream_copy", "bytes": copy_r["bytes"],
+                         "us": round(copy_r["us"], 2), "GB/s": round(copy_r["GBs"], 1),
                          "frac_of_peak": round(copy_r["GBs"] / HBM_PEAK_GBS, 4),
-                         "step_vs_copy": round(main_r["achieved"] / copy_r["GBs"], 4)},
+                         "step_vs_copy": round(main_r["achieved"] / copy_r["GBs"], 4),
+                         "runtime_copy": {"us": round(copy_r["runtime_copy_us"], 2),
+                                          "GB/s": round(copy_r["runtime_copy_GBs"], 1)}},
     }
     if other:
         out["storage_forms"] = other

@@ -165,10 +165,12 @@ int lbfz_restart_fields(lbfz_handle* h, const float* const* d_fields);
 /* ------------------------------------------------------------------------
  * Batched sweep: many independent 2D grids (the parameter sweep of Sec. 5's
  * study, each grid a complete solver state with its own parameters, size,
- * buffers and totals) advanced in lockstep.  Grids of equal size form a
- * group; one batch step is one launch per group over a table of (grid, tile)
- * work items, replayed from a captured HIP graph.  Results are those of the
- * same grids stepped one by one (the per-node arithmetic is identical).
+ * buffers and totals) advanced in lockstep.  One batch step is one launch
+ * over a single table of (grid, tile) work items that spans every grid,
+ * whatever its size, replayed from a captured HIP graph (one kernel node per
+ * step).  Results are those of the same grids stepped one by one (the
+ * per-node arithmetic is identical).  Grids of equal size form a group, which
+ * is only reported (lbfz_batch_group_config).
  * ------------------------------------------------------------------------ */
 typedef struct lbfz_batch lbfz_batch;
 
@@ -185,10 +187,11 @@ int lbfz_batch_create(int32_t ncases, const lbfz_params* params, const double* c
                       const double* const* T, const double* const* C, void* d_workspace,
                       size_t ws_bytes, void* stream, lbfz_batch** out);
 
-/* Autotuner: for every group, time each candidate launch configuration (tile
- * height 4 or 8 rows; one block per work item or a persistent grid of 8 / 4
- * blocks per CU) over trial_steps steps and keep the fastest.  The trial
- * steps are real steps of every grid (4 * trial_steps in all).  Synchronises. */
+/* Autotuner: time each candidate configuration of the whole batch step
+ * (tile height 4 or 8 rows, i.e. 4 or 8 waves per block; one block per work
+ * item, or a persistent grid of 2, 4 or 8 blocks per CU walking the work
+ * table) over trial_steps steps and keep the fastest.  The trial steps are
+ * real steps of every selected grid (8 * trial_steps in all).  Synchronises. */
 int lbfz_batch_tune(lbfz_batch* b, int32_t trial_steps);
 
 /* Advance every grid by nsteps (asynchronous on the stream). */
@@ -198,7 +201,8 @@ int lbfz_batch_step(lbfz_batch* b, int64_t nsteps);
  * batched step is measured against). */
 int lbfz_batch_step_sequential(lbfz_batch* b, int64_t nsteps);
 
-/* Number of groups, and the configuration of one (any output may be NULL). */
+/* Number of groups (grids of equal size), and one group's size and count with
+ * the batch's launch configuration (any output may be NULL). */
 int lbfz_batch_groups(lbfz_batch* b);
 int lbfz_batch_group_config(lbfz_batch* b, int32_t group, int32_t* nx, int32_t* ny,
                             int32_t* ncases, int32_t* tile_rows, int32_t* grid_blocks);
@@ -212,8 +216,8 @@ int lbfz_batch_totals(lbfz_batch* b, int32_t i, lbfz_totals_t* out);
 /* The fields of every grid into one device buffer (asynchronous): grid i's
  * fields of the set bits of field_mask (bit order), one plane of its N
  * values after the other, from d_dst + i * case_stride (floats; case_stride
- * >= the number of set bits times the largest N).  One launch per group of
- * equal-sized grids; the values agree with lbfz_batch_fields up to FP32
+ * >= the number of set bits times the largest N).  One launch over every
+ * grid's tiles; the values agree with lbfz_batch_fields up to FP32
  * rounding (the batched kernel forms its fused multiply-adds differently).
  * LBFZ_EINVAL if a grid is stale, LBFZ_EHIP if a launch fails. */
 int lbfz_batch_fields_all(lbfz_batch* b, uint32_t field_mask, float* d_dst, int64_t case_stride);
@@ -242,6 +246,15 @@ int lbfz_batch_restart_many(lbfz_batch* b, int32_t n, const int32_t* idx,
 
 /* Release the grids, graphs and the capture stream (not the workspace). */
 void lbfz_batch_destroy(lbfz_batch* b);
+
+/* Device-to-device copy of `bytes` bytes (a multiple of 16; both pointers
+ * 16-byte aligned; the ranges must not overlap): a streaming kernel that
+ * reads and writes every byte once, as one time step reads and writes the
+ * solver state once.  It is the memory-system ceiling the step's bandwidth is
+ * measured against.  Asynchronous on `stream` (a hipStream_t or NULL).
+ * Errors: LBFZ_EINVAL (NULL or misaligned pointer, size not a multiple of
+ * 16), LBFZ_EHIP. */
+int lbfz_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 /* Blocks until the handle's stream is idle. */
 int lbfz_sync(lbfz_handle* h);

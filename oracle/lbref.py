@@ -36,9 +36,20 @@ class LbrefParams(ctypes.Structure):
                 + [("body_force", ctypes.c_double * 3)])
 
 
-# Variants of the oracle built from the same source with one reading
-# switched, for the tests that compare readings: name -> gcc defines.
-VARIANTS = {"hard_cutoff": ["-DLBREF_HARD_NORMAL_CUTOFF"]}
+class LbrefParamsSingle(ctypes.Structure):
+    _fields_ = ([(k, ctypes.c_int32) for k in PARAM_INTS]
+                + [(k, ctypes.c_float) for k in PARAM_DOUBLES]
+                + [("body_force", ctypes.c_float * 3)])
+
+
+# Variants of the oracle built from the same source, for the tests that
+# compare against them: name -> gcc defines.  "hard_cutoff" switches one
+# reading (the interface normal); "single" is the same source with every
+# double made a float (and single-precision constants), the scheme evaluated
+# in FP32 arithmetic and storage, as a measure of what FP32 alone does to a
+# trajectory.
+VARIANTS = {"hard_cutoff": ["-DLBREF_HARD_NORMAL_CUTOFF"],
+            "single": ["-fsingle-precision-constant"]}
 
 
 def _lib_path(variant=None) -> str:
@@ -47,15 +58,32 @@ def _lib_path(variant=None) -> str:
 
 def build(force: bool = False, variant=None) -> str:
     """Compile ``lbref.c`` with gcc (-O2, no fast-math, OpenMP for loops)."""
+    import re
+    import shutil
+    import tempfile
     src = os.path.join(_HERE, "lbref.c")
     path = _lib_path(variant)
     if force or not os.path.exists(path) or (os.path.getmtime(path) < os.path.getmtime(src)):
         tmp = path + ".tmp"
+        work = None
+        if variant == "single":
+            # the same source with double -> float, built in a scratch folder
+            work = tempfile.mkdtemp(prefix="lbref_single_")
+            for name in ("lbref.c", "lbref.h"):
+                with open(os.path.join(_HERE, name)) as fh:
+                    text = re.sub(r"\bdouble\b", "float", fh.read())
+                with open(os.path.join(work, name), "w") as fh:
+                    fh.write(text)
+            src = os.path.join(work, "lbref.c")
         cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
                "-fopenmp", "-Wall", "-Wno-unknown-pragmas"]
         cmd += VARIANTS[variant] if variant is not None else []
         cmd += ["-o", tmp, src, "-lm"]
-        subprocess.check_call(cmd, cwd=_HERE)
+        try:
+            subprocess.check_call(cmd, cwd=_HERE)
+        finally:
+            if work:
+                shutil.rmtree(work, ignore_errors=True)
         os.replace(tmp, path)
     return path
 
@@ -69,8 +97,9 @@ def lib(variant=None):
         if variant is not None or not os.path.exists(path):
             build(variant=variant)
         L = ctypes.CDLL(path)
-        dp = ctypes.POINTER(ctypes.c_double)
-        pp = ctypes.POINTER(LbrefParams)
+        single = variant == "single"
+        dp = ctypes.POINTER(ctypes.c_float if single else (ctypes.c_float if single else ctypes.c_double))
+        pp = ctypes.POINTER(LbrefParamsSingle if single else LbrefParams)
         L.lbref_create.argtypes = [pp, dp, dp, dp, ctypes.c_void_p, ctypes.c_void_p]
         L.lbref_create.restype = ctypes.c_int
         L.lbref_destroy.argtypes = [ctypes.c_void_p]
@@ -86,13 +115,13 @@ def lib(variant=None):
             getattr(L, nm).restype = ctypes.c_int
         L.lbref_q.argtypes = [ctypes.c_int, ctypes.c_int]
         L.lbref_q.restype = ctypes.c_int
-        L.lbref_enthalpy_map.argtypes = [pp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
+        L.lbref_enthalpy_map.argtypes = [pp, (ctypes.c_float if single else ctypes.c_double), (ctypes.c_float if single else ctypes.c_double), dp, dp, dp]
         L.lbref_enthalpy_map.restype = None
-        L.lbref_feq_g.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.lbref_feq_g.argtypes = [ctypes.c_int, (ctypes.c_float if single else ctypes.c_double), (ctypes.c_float if single else ctypes.c_double), dp, dp]
         L.lbref_feq_g.restype = None
-        L.lbref_src_g.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp]
+        L.lbref_src_g.argtypes = [ctypes.c_int, (ctypes.c_float if single else ctypes.c_double), dp, dp, dp, dp]
         L.lbref_src_g.restype = None
-        L.lbref_heq.argtypes = [pp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.lbref_heq.argtypes = [pp, (ctypes.c_float if single else ctypes.c_double), (ctypes.c_float if single else ctypes.c_double), (ctypes.c_float if single else ctypes.c_double), dp, dp]
         L.lbref_heq.restype = None
         L.lbref_grad_lap.argtypes = [pp, dp, ctypes.c_int, dp, dp]
         L.lbref_grad_lap.restype = None
@@ -104,11 +133,12 @@ def lib(variant=None):
 
 
 def _dptr(a: np.ndarray):
-    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ct = ctypes.c_float if a.dtype == np.float32 else ctypes.c_double
+    return a.ctypes.data_as(ctypes.POINTER(ct))
 
 
-def make_params(cfg: dict, threads: int = 1) -> LbrefParams:
-    P = LbrefParams()
+def make_params(cfg: dict, threads: int = 1, single: bool = False):
+    P = LbrefParamsSingle() if single else LbrefParams()
     for k in PARAM_INTS:
         setattr(P, k, int(cfg.get(k, 0)))
     if P.dim == 2:
@@ -127,13 +157,14 @@ class Oracle:
 
     def __init__(self, cfg: dict, phi, T, C, mask=None, threads: int = 1, variant=None):
         self._L = lib(variant)
+        self._ft = np.float32 if variant == "single" else np.float64
         self.cfg = dict(cfg)
-        self.P = make_params(cfg, threads)
+        self.P = make_params(cfg, threads, single=variant == "single")
         self.shape = (self.P.nz, self.P.ny, self.P.nx) if self.P.dim == 3 else (self.P.ny, self.P.nx)
         self.N = self.P.nx * self.P.ny * self.P.nz
-        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
-        T = np.ascontiguousarray(T, dtype=np.float64).reshape(-1)
-        C = np.ascontiguousarray(C, dtype=np.float64).reshape(-1)
+        phi = np.ascontiguousarray(phi, dtype=self._ft).reshape(-1)
+        T = np.ascontiguousarray(T, dtype=self._ft).reshape(-1)
+        C = np.ascontiguousarray(C, dtype=self._ft).reshape(-1)
         for a in (phi, T, C):
             if a.size != self.N:
                 raise ValueError("initial field size does not match the grid")
@@ -162,39 +193,39 @@ class Oracle:
 
     def fields(self) -> dict:
         names = ("phi", "fl", "T", "C", "ux", "uy", "uz", "p", "rho")
-        out = {k: np.empty(self.N) for k in names}
+        out = {k: np.empty(self.N, self._ft) for k in names}
         rc = self._L.lbref_fields(self._h, *[_dptr(out[k]) for k in names])
         if rc != 0:
             raise RuntimeError("lbref_fields failed")
-        return {k: v.reshape(self.shape) for k, v in out.items()}
+        return {k: v.reshape(self.shape).astype(np.float64, copy=False) for k, v in out.items()}
 
     def totals(self) -> dict:
-        out = np.empty(9)
+        out = np.empty(9, self._ft)
         self._L.lbref_totals(self._h, _dptr(out))
         keys = ("sum_f", "sum_l", "sum_h", "mpc", "vol_solid", "vol_sl", "step", "nonfinite",
                 "qsum")
-        return dict(zip(keys, out.tolist()))
+        return dict(zip(keys, out.astype(np.float64, copy=False).tolist()))
 
     def q(self, which: int) -> int:
         return self._L.lbref_q(self.P.dim, which)
 
     def get_pops(self, which: int) -> np.ndarray:
-        out = np.empty(self.q(which) * self.N)
+        out = np.empty(self.q(which) * self.N, self._ft)
         self._L.lbref_get_pops(self._h, which, _dptr(out))
-        return out.reshape((self.q(which),) + self.shape)
+        return out.reshape((self.q(which),) + self.shape).astype(np.float64, copy=False)
 
     def set_pops(self, which: int, arr) -> None:
-        a = np.ascontiguousarray(arr, dtype=np.float64).reshape(-1)
+        a = np.ascontiguousarray(arr, dtype=self._ft).reshape(-1)
         assert a.size == self.q(which) * self.N
         self._L.lbref_set_pops(self._h, which, _dptr(a))
 
     def get_state(self, which: int) -> np.ndarray:
-        out = np.empty(self.N)
+        out = np.empty(self.N, self._ft)
         self._L.lbref_get_state(self._h, which, _dptr(out))
-        return out.reshape(self.shape)
+        return out.reshape(self.shape).astype(np.float64, copy=False)
 
     def set_state(self, which: int, arr) -> None:
-        a = np.ascontiguousarray(arr, dtype=np.float64).reshape(-1)
+        a = np.ascontiguousarray(arr, dtype=self._ft).reshape(-1)
         assert a.size == self.N
         self._L.lbref_set_state(self._h, which, _dptr(a))
 

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/lbfz_api.hip", "csrc/lbfz_2d.hip", "csrc/lbfz_3d.hip", "csrc/lbfz_batch.hip",
-           "csrc/lbfz_nn.hip"]
+           "csrc/lbfz_nn.hip", "csrc/lbfz_copy.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

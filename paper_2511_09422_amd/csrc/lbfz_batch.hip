@@ -2,14 +2,16 @@
 // independent 2D grids, each a complete solver state (its own parameters,
 // size, buffers and totals), advanced together.
 //
-// Grids of equal size form a group.  One step of the batch is one launch of
-// k_step2d_batch per group over a work table of (grid, tile) items, with the
-// grids' kernel parameters and per-parity buffers in a device table; the
-// tile height (4 or 8 rows) and the launch shape (one block per item, or a
-// persistent grid of a few blocks per CU looping over the items) are chosen
-// per group by a timing search (lbfz_batch_tune).  Steps are replayed from a
-// HIP graph captured once per configuration, so a long run costs one graph
-// launch per graph_steps steps instead of one launch per group and step.
+// One step of the batch is one launch of k_step2d_batch over a single work
+// table of (grid, tile) items that spans every grid, whatever its size, with
+// the grids' kernel parameters and per-parity buffers in a device table: the
+// tiles of the small grids, too few to fill the GPU on their own, run beside
+// those of the large ones.  The tile height (4 or 8 rows) and the launch
+// shape (one block per item, or a persistent grid of 2, 4 or 8 blocks per CU
+// looping over the items) are chosen by a timing search of the whole step
+// (lbfz_batch_tune).  Steps are replayed from a HIP graph captured once per
+// configuration: a graph of graph_steps steps holds one kernel node per step.
+// Grids of equal size form a group (reported by lbfz_batch_group_config).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,13 +35,6 @@ constexpr int kTY[2] = {4, 8};
 struct Group {
   int nx, ny;
   std::vector<int> cases;
-  int nwork[2];      // work items at tile height kTY[v]
-  int2* work[2];     // device work tables (every grid of the group)
-  int nsel[2];       // the same for the selected grids (lbfz_batch_select)
-  int2* sel[2];
-  bool all = true;   // every grid selected: launch over work[], else sel[]
-  int ty_index = 0;  // chosen tile height (index into kTY)
-  int grid = 0;      // blocks per launch; 0: one per work item
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -64,6 +59,13 @@ struct lbfz_batch {
   EquilJob* d_jobs = nullptr;  // device table of a batched restart (ncases entries)
   std::vector<char> selected;  // per grid: advanced by the steps
   std::vector<char> stale;     // per grid: left behind by a subset step
+  int nwork[2] = {0, 0};       // work items of every grid at tile height kTY[v]
+  int2* work[2] = {nullptr, nullptr};  // device work tables (every grid)
+  int nsel[2] = {0, 0};        // the same for the selected grids
+  int2* sel[2] = {nullptr, nullptr};
+  bool all = true;             // every grid selected: launch over work[], else sel[]
+  int ty_index = 0;            // chosen tile height (index into kTY)
+  int grid = 0;                // blocks per launch; 0: one per work item
 };
 
 namespace {
@@ -95,20 +97,20 @@ void fill_case(lbfz_batch* b, int i, int ty) {
 }
 
 int upload_cases(lbfz_batch* b) {
-  for (auto& g : b->groups)
-    for (int i : g.cases) fill_case(b, i, kTY[g.ty_index]);
+  for (int i = 0; i < b->ncases; ++i) fill_case(b, i, kTY[b->ty_index]);
   HIPCHK(hipMemcpyAsync(b->d_cases, b->cases.data(), sizeof(BatchCase) * b->ncases,
                         hipMemcpyHostToDevice, b->stream));
   HIPCHK(hipStreamSynchronize(b->stream));
   return LBFZ_OK;
 }
 
-hipError_t launch_group(lbfz_batch* b, const Group& g, int64_t step, hipStream_t st) {
-  const int v = g.ty_index;
-  const int n = g.all ? g.nwork[v] : g.nsel[v];
-  if (n == 0) return hipSuccess;  // no grid of the group selected
-  return launch_step2d_batch(b->storage, kTY[v], b->d_cases, g.all ? g.work[v] : g.sel[v], n,
-                             g.grid, (int)(step % b->L), st);
+// One step of every selected grid: one launch over the work table.
+hipError_t launch_all(lbfz_batch* b, int64_t step, hipStream_t st) {
+  const int v = b->ty_index;
+  const int n = b->all ? b->nwork[v] : b->nsel[v];
+  if (n == 0) return hipSuccess;  // no grid selected
+  return launch_step2d_batch(b->storage, kTY[v], b->d_cases, b->all ? b->work[v] : b->sel[v], n,
+                             b->grid, (int)(step % b->L), st);
 }
 
 // XCD-aware order of a flat (grid, tile) item list: item e runs on the XCD
@@ -122,16 +124,18 @@ std::vector<int2> xcd_order(const std::vector<int2>& flat) {
   return tab;
 }
 
-// Items of the grids of group g for which keep(grid) holds, tile height kTY[v].
+// Items of every grid for which keep(grid) holds, tile height kTY[v]: the
+// grids group by group, each grid's tiles contiguous, then XCD-ordered.
 template <class F>
-std::vector<int2> group_items(const Group& g, int v, F keep) {
-  int nbx, nby;
-  const int per = tiles2d(g.nx, g.ny, &nbx, &nby, kTY[v]);
+std::vector<int2> batch_items(const lbfz_batch* b, int v, F keep) {
   std::vector<int2> flat;
-  flat.reserve((size_t)per * g.cases.size());
-  for (int c : g.cases)
-    if (keep(c))
-      for (int t = 0; t < per; ++t) flat.push_back(make_int2(c, t));
+  for (const Group& g : b->groups) {
+    int nbx, nby;
+    const int per = tiles2d(g.nx, g.ny, &nbx, &nby, kTY[v]);
+    for (int c : g.cases)
+      if (keep(c))
+        for (int t = 0; t < per; ++t) flat.push_back(make_int2(c, t));
+  }
   return xcd_order(flat);
 }
 
@@ -143,14 +147,12 @@ void drop_graph(lbfz_batch* b) {
 }
 
 // Capture kGraphSteps steps (starting at a step that is 0 mod L) of every
-// group on the capture stream.
+// grid on the capture stream: one kernel node per step.
 int build_graph(lbfz_batch* b) {
   drop_graph(b);
   HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int s = 0; s < kGraphSteps && e == hipSuccess; ++s)
-    for (auto& g : b->groups)
-      if (e == hipSuccess) e = launch_group(b, g, s, b->cap);
+  for (int s = 0; s < kGraphSteps && e == hipSuccess; ++s) e = launch_all(b, s, b->cap);
   hipGraph_t graph = nullptr;
   const hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
   if (e != hipSuccess || e2 != hipSuccess || !graph) {
@@ -200,7 +202,8 @@ int lbfz_batch_workspace_bytes(int32_t ncases, const lbfz_params* params, size_t
     for (int ty : kTY) items += (size_t)tiles2d(params[i].nx, params[i].ny, &nbx, &nby, ty);
   }
   total += align256(sizeof(BatchCase) * (size_t)ncases);
-  total += 2 * (align256(sizeof(int2) * items) + 256 * 2 * (size_t)ncases);
+  // work and selection tables of every grid, for each tile height
+  total += 2 * align256(sizeof(int2) * items) + 4 * 256;
   total += align256(sizeof(EquilJob) * (size_t)ncases);
   *bytes = total;
   return LBFZ_OK;
@@ -255,24 +258,22 @@ int lbfz_batch_create(int32_t ncases, const lbfz_params* params, const double* c
     }
     b->groups[it->second].cases.push_back(i);
   }
-  // work tables: (grid, tile) items in an XCD-aware order (item e runs on the
-  // XCD e % 8, which gets a contiguous band of the flat item list)
-  for (auto& g : b->groups) {
-    for (int v = 0; v < 2; ++v) {
-      const std::vector<int2> tab = group_items(g, v, [](int) { return true; });
-      const int n = (int)tab.size();
-      g.nwork[v] = n;
-      g.work[v] = (int2*)q;
-      q += align256(sizeof(int2) * (size_t)n);
-      g.nsel[v] = 0;
-      g.sel[v] = (int2*)q;  // room for a selection of every grid
-      q += align256(sizeof(int2) * (size_t)n);
-      if (hipMemcpyAsync(g.work[v], tab.data(), sizeof(int2) * n, hipMemcpyHostToDevice,
-                         b->stream) != hipSuccess ||
-          hipStreamSynchronize(b->stream) != hipSuccess) {
-        lbfz_batch_destroy(b);
-        return LBFZ_EHIP;
-      }
+  // work tables: (grid, tile) items of every grid in an XCD-aware order (item
+  // e runs on the XCD e % 8, which gets a contiguous band of the item list)
+  for (int v = 0; v < 2; ++v) {
+    const std::vector<int2> tab = batch_items(b, v, [](int) { return true; });
+    const int n = (int)tab.size();
+    b->nwork[v] = n;
+    b->work[v] = (int2*)q;
+    q += align256(sizeof(int2) * (size_t)n);
+    b->nsel[v] = 0;
+    b->sel[v] = (int2*)q;  // room for a selection of every grid
+    q += align256(sizeof(int2) * (size_t)n);
+    if (hipMemcpyAsync(b->work[v], tab.data(), sizeof(int2) * n, hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+      lbfz_batch_destroy(b);
+      return LBFZ_EHIP;
     }
   }
   b->d_jobs = (EquilJob*)q;
@@ -297,51 +298,46 @@ int lbfz_batch_tune(lbfz_batch* b, int32_t trial_steps) {
     const int rc = begin_step(b, trial_steps);
     if (rc != LBFZ_OK) return rc;
   }
-  // candidates: tile height x launch shape (one block per item, or a
-  // persistent grid of blocks_per_cu x 256 blocks)
+  // candidates: tile height (waves per block) x launch shape (one block per
+  // item, or a persistent grid of blocks_per_cu blocks on each CU)
   struct Cand {
     int v, per_cu;
   };
-  const Cand cands[] = {{0, 0}, {1, 0}, {0, 8}, {1, 4}};
+  const Cand cands[] = {{0, 0}, {1, 0}, {0, 2}, {0, 4}, {0, 8}, {1, 2}, {1, 4}, {1, 8}};
   const int nc = (int)(sizeof(cands) / sizeof(cands[0]));
-  const int G = (int)b->groups.size();
-  std::vector<float> best(G, 1e30f);
-  std::vector<Cand> pick(G, cands[0]);
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (cus <= 0) cus = 256;
+  float best = 1e30f;
+  Cand pick = cands[0];
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  // every group runs every candidate for trial_steps steps, so all grids
-  // advance by the same number of steps; the results do not depend on the
-  // candidate (the per-node arithmetic is the same)
+  // every candidate runs trial_steps real steps of every selected grid; the
+  // results do not depend on the candidate (the per-node arithmetic is the
+  // same)
   for (int k = 0; k < nc; ++k) {
-    for (int gi = 0; gi < G; ++gi) {
-      Group& g = b->groups[gi];
-      g.ty_index = cands[k].v;
-      g.grid = cands[k].per_cu * 256;
-    }
+    b->ty_index = cands[k].v;
+    b->grid = cands[k].per_cu * cus;
     int rc = upload_cases(b);
     if (rc != LBFZ_OK) return rc;
-    for (int gi = 0; gi < G; ++gi) {
-      Group& g = b->groups[gi];
-      HIPCHK(hipEventRecord(e0, b->stream));
-      for (int s = 0; s < trial_steps; ++s) HIPCHK(launch_group(b, g, b->step + s, b->stream));
-      HIPCHK(hipEventRecord(e1, b->stream));
-      HIPCHK(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best[gi]) {
-        best[gi] = ms;
-        pick[gi] = cands[k];
-      }
+    HIPCHK(hipEventRecord(e0, b->stream));
+    for (int s = 0; s < trial_steps; ++s) HIPCHK(launch_all(b, b->step + s, b->stream));
+    HIPCHK(hipEventRecord(e1, b->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      pick = cands[k];
     }
     b->step += trial_steps;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  for (int gi = 0; gi < G; ++gi) {
-    b->groups[gi].ty_index = pick[gi].v;
-    b->groups[gi].grid = pick[gi].per_cu * 256;
-  }
+  b->ty_index = pick.v;
+  b->grid = pick.per_cu * cus;
   drop_graph(b);
   sync_handles(b);
   return upload_cases(b);
@@ -354,7 +350,7 @@ int lbfz_batch_step(lbfz_batch* b, int64_t nsteps) {
     if (rc != LBFZ_OK) return rc;
   }
   auto one = [&]() -> int {
-    for (auto& g : b->groups) HIPCHK(launch_group(b, g, b->step, b->stream));
+    HIPCHK(launch_all(b, b->step, b->stream));
     b->step += 1;
     return LBFZ_OK;
   };
@@ -413,8 +409,8 @@ int lbfz_batch_group_config(lbfz_batch* b, int32_t group, int32_t* nx, int32_t* 
   if (nx) *nx = g.nx;
   if (ny) *ny = g.ny;
   if (ncases) *ncases = (int32_t)g.cases.size();
-  if (tile_rows) *tile_rows = kTY[g.ty_index];
-  if (grid_blocks) *grid_blocks = g.grid;
+  if (tile_rows) *tile_rows = kTY[b->ty_index];
+  if (grid_blocks) *grid_blocks = b->grid;
   return LBFZ_OK;
 }
 
@@ -434,13 +430,11 @@ int lbfz_batch_fields_all(lbfz_batch* b, uint32_t field_mask, float* d_dst, int6
     if (b->stale[i] || case_stride < nf * N) return LBFZ_EINVAL;
   }
   sync_handles(b);
-  // one dry-pass launch per group over all of its (grid, tile) items
+  // one dry-pass launch over every (grid, tile) item
   const int slot = (int)(b->step % b->L);
-  for (const auto& g : b->groups) {
-    const int v = g.ty_index;
-    HIPCHK(launch_fields2d_batch(b->storage, kTY[v], b->d_cases, g.work[v], g.nwork[v], slot,
-                                 d_dst, (long)case_stride, field_mask, b->stream));
-  }
+  const int v = b->ty_index;
+  HIPCHK(launch_fields2d_batch(b->storage, kTY[v], b->d_cases, b->work[v], b->nwork[v], slot,
+                               d_dst, (long)case_stride, field_mask, b->stream));
   return LBFZ_OK;
 }
 
@@ -458,15 +452,14 @@ int lbfz_batch_select(lbfz_batch* b, int32_t n, const int32_t* idx) {
     sel[idx[k]] = 1;
   }
   b->selected = sel;
-  for (auto& g : b->groups) {
-    g.all = true;
-    for (int c : g.cases) g.all = g.all && sel[c];
-    if (g.all) continue;
+  b->all = true;
+  for (char c : sel) b->all = b->all && c;
+  if (!b->all) {
     for (int v = 0; v < 2; ++v) {
-      const std::vector<int2> tab = group_items(g, v, [&](int c) { return sel[c] != 0; });
-      g.nsel[v] = (int)tab.size();
-      if (g.nsel[v] > 0)
-        HIPCHK(hipMemcpyAsync(g.sel[v], tab.data(), sizeof(int2) * tab.size(),
+      const std::vector<int2> tab = batch_items(b, v, [&](int c) { return sel[c] != 0; });
+      b->nsel[v] = (int)tab.size();
+      if (b->nsel[v] > 0)
+        HIPCHK(hipMemcpyAsync(b->sel[v], tab.data(), sizeof(int2) * tab.size(),
                               hipMemcpyHostToDevice, b->stream));
     }
   }

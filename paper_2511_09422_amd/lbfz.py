@@ -75,6 +75,7 @@ def lib() -> ctypes.CDLL:
         L.lbfz_destroy.restype = None
         L.lbfz_strerror.argtypes = [ctypes.c_int]
         L.lbfz_strerror.restype = ctypes.c_char_p
+        L.lbfz_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         ip = ctypes.POINTER(ctypes.c_int32)
         dpp = ctypes.POINTER(dp)
         L.lbfz_batch_workspace_bytes.argtypes = [ctypes.c_int32, pp,
@@ -207,6 +208,11 @@ def _field_ptrs(planes):
 def lbfz_restart_fields(h, planes) -> None:
     """planes: device tensors (FP32, N values each) in RESTART_FIELDS order."""
     _check(lib().lbfz_restart_fields(h, _field_ptrs(planes)), "lbfz_restart_fields")
+
+
+def lbfz_stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int) -> None:
+    _check(lib().lbfz_stream_copy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr),
+                                  int(nbytes), ctypes.c_void_p(stream_ptr)), "lbfz_stream_copy")
 
 
 def lbfz_sync(h):

@@ -625,9 +625,13 @@ class Screener:
     """Screens a batched sweep (an lbfz.Batch of equal S x S grids) STRIDE
     steps at a time: one surrogate forward over every grid; grids whose
     prediction passes the check take it (equilibrium restart from the
-    predicted phi, f_l, T, C, u and the pressure before the stride), the rest
-    are advanced by the LB (subset step).  net: a UNet of batch >= the number
-    of grids and side S."""
+    predicted phi, f_l, T, C, at rest, with the pressure before the stride),
+    the rest are advanced by the LB (subset step).  The velocity 64 steps
+    ahead is not predicted with skill (relative L2 error about 1, no better
+    than zero), so an accepted grid restarts at rest rather than from the
+    network's velocity: the restart's velocity error is then exactly the
+    LB's own velocity (relative L2 error 1), with no spurious structure
+    added.  net: a UNet of batch >= the number of grids and side S."""
 
     def __init__(self, net: UNet, norm: Normaliser, batch, mass_tol: float = MASS_TOL,
                  solute_tol: float = SOLUTE_TOL):
@@ -643,6 +647,7 @@ class Screener:
         f = dict(dtype=torch.float32, device=net.dev)
         self.before = torch.zeros((self.n, NEXP, S, S), **f)
         self.pred = torch.zeros((self.n, NF, S, S), **f)
+        self.rest = torch.zeros((S, S), **f)  # the restart velocity
         # per-grid sums before the stride and of the prediction, in one
         # buffer so that the check needs one device-to-host copy
         self.sums = torch.zeros(self.n * (NEXP + NF), dtype=torch.float64, device=net.dev)
@@ -692,9 +697,12 @@ class Screener:
             self.batch.step(STRIDE)
         self.time += STRIDE
         SS = self.S * self.S
+        # phi, f_l, T, C from the prediction; u = 0 (one zero plane for every
+        # grid: stride 0); p from before the stride
+        planes = [self.pred[0, f] for f in range(4)] + [self.rest, self.rest]
         self.batch.restart_many([i for i in range(self.n) if acc[i]],
-                                [self.pred[0, f] for f in range(NF)] + [self.before[0, NEXP - 1]],
-                                [NF * SS] * NF + [NEXP * SS])
+                                planes + [self.before[0, NEXP - 1]],
+                                [NF * SS] * 4 + [0, 0] + [NEXP * SS])
         self.batch.select([])
         return acc, res
 

@@ -16,4 +16,6 @@ def pytest_configure(config):
 def _oracle_built():
     from oracle import lbref
     lbref.build()
+    for v in lbref.VARIANTS:
+        lbref.build(variant=v)
     yield

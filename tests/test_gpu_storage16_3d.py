@@ -3,6 +3,8 @@ reference moments, FP32 arithmetic) against the FP64 oracle, through the C
 ABI; the same bars as the 2D 16-bit tests (one step: every moving population
 within u |v - w_i r| of the oracle, u the format's unit roundoff; long runs:
 printed per-field errors under a loose regression bound)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -68,6 +70,37 @@ def test_one_step_quantisation_bound_3d(storage, case, K):
 LONG_BOUND = {"f16": 2e-2, "bf16": 1.5e-1}
 
 
+def _state3d(o, shape):
+    """Oracle populations and previous-level fields in the GPU state layout."""
+    st = np.zeros((47,) + tuple(shape))
+    for w, sl in ((0, slice(0, 7)), (1, slice(7, 26)), (2, slice(26, 33)), (3, slice(33, 40))):
+        st[sl] = o.get_pops(w)
+    for k in range(7):
+        st[40 + k] = o.get_state(k)
+    return st
+
+
+def _dev_spread(cfg, st0, shape, mask, steps, ref, dev, seeds=(1, 2, 3)):
+    """Spread of the FP64 oracle started from st0 when every population and
+    previous-level value is moved by dev * U(-1, 1) before each step."""
+    spread = {k: 0.0 for k in FIELDS}
+    for sd in seeds:
+        rng = np.random.default_rng(sd)
+        o = _oracle_from_state(cfg, st0, shape, mask)
+        for _ in range(steps):
+            st = _state3d(o, shape) + dev * rng.uniform(-1, 1, size=dev.shape)
+            for w, sl in ((0, slice(0, 7)), (1, slice(7, 26)), (2, slice(26, 33)),
+                          (3, slice(33, 40))):
+                o.set_pops(w, st[sl])
+            for k in range(7):
+                o.set_state(k, st[40 + k])
+            o.step(1)
+        f = o.fields()
+        for k in FIELDS:
+            spread[k] = max(spread[k], rel_linf(f[k], ref[k], mask))
+    return spread
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_3d_64_copy_100_steps_error(storage):
     """Per-field error of 100 steps of the 64^3 copy of the 3D workload
@@ -75,7 +108,25 @@ def test_3d_64_copy_100_steps_error(storage):
     cfg, phi, T, C, mask = droplet_3d(64, R=16.0, imp_R=3.0, seed=1)
     s = Solver(cfg, phi, T, C, mask=mask, storage=storage)
     t0 = s.totals()
-    s.step(100)
+    if storage == "f32":
+        # the GPU's one-step deviation from the oracle at every entry, held to
+        # the one-step bar, then used as the per-step perturbation of the
+        # oracle whose spread sets the 100-step bar
+        st0 = s.get_state().astype(np.float64)
+        o1 = _oracle_from_state(cfg, st0, s.shape, mask)
+        s.step(1)
+        o1.step(1)
+        dev = np.abs(s.get_state().astype(np.float64) - _state3d(o1, s.shape))
+        ost = _state3d(o1, s.shape)
+        for name, sl in (("f", slice(0, 7)), ("g", slice(7, 26)), ("h", slice(26, 33)),
+                         ("l", slice(33, 40))) + tuple((f"state{k}", slice(k, k + 1))
+                                                       for k in range(40, 47)):
+            worst = dev[sl].max() / max(np.abs(ost[sl]).max(), 1e-30)
+            assert worst <= 2e-5, (name, worst)
+        del o1
+        s.step(99)
+    else:
+        s.step(100)
     got = s.fields()
     t1 = s.totals()
     o = Oracle(cfg, phi, T, C, mask=mask, threads=THREADS)
@@ -87,11 +138,28 @@ def test_3d_64_copy_100_steps_error(storage):
           " ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
           f" | phase-field budget per node {budget:.2e}", flush=True)
     assert t1["nonfinite"] == 0
-    # FP32 is the baseline of the comparison (its trajectory parity is checked
-    # against the oracle's own noise spread in test_gpu_parity3d.py); every
-    # form is held to the same regression guard
-    for k, e in errs.items():
-        assert e <= LONG_BOUND.get(storage, LONG_BOUND["f16"]), (storage, k, e)
+    if storage == "f32":
+        # FP32 storage is held to 1e-4, or three times the spread of the FP64
+        # oracle perturbed before every step by the GPU's own (bounded)
+        # one-step deviation, or 1.25 times the deviation of the oracle's own
+        # single-precision build after the same 100 steps (what evaluating the
+        # scheme in FP32 does by itself; two FP32 evaluations with different
+        # rounding sequences land within 10 % of each other)
+        spread = _dev_spread(cfg, st0, s.shape, mask, 100, ref, dev)
+        o32 = Oracle(cfg, phi, T, C, mask=mask, threads=THREADS, variant="single")
+        o32.step(100)
+        r32 = o32.fields()
+        dev32 = {k: rel_linf(r32[k], ref[k], mask) for k in FIELDS}
+        print("[3d 16bit long] f32 oracle spread " +
+              " ".join(f"{k}={v:.2e}" for k, v in spread.items()) + " | single-precision oracle " +
+              " ".join(f"{k}={v:.2e}" for k, v in dev32.items()), flush=True)
+        for k, e in errs.items():
+            assert e <= max(1e-4, 3.0 * spread[k], 1.25 * dev32[k]), (storage, k, e, spread[k],
+                                                                        dev32[k])
+    else:
+        # 16-bit storage: a regression guard on the stated per-field errors
+        for k, e in errs.items():
+            assert e <= LONG_BOUND[storage], (storage, k, e)
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
@@ -110,3 +178,42 @@ def test_state_round_trip_3d(storage):
     assert np.array_equal(a[40:], b[40:])
     s.step(5)
     assert s.totals()["nonfinite"] == 0
+
+
+GOLDEN_5000 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "droplet3d_64_5000.npz")
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_3d_64_copy_5000_steps_against_stored_oracle(storage):
+    """The 64^3 copy of the 3D workload (drop radius 16, obstacle radius 3)
+    after 5000 steps against the FP64 oracle's fields at step 5000, stored by
+    tests/golden/make_droplet3d_64_5000.py (which calls only the oracle),
+    with the spread of the same oracle under FP32-sized noise stored beside
+    them, and the deviation of the oracle's own single-precision build after
+    the same 5000 steps.  FP32 storage within max(1e-4, 3 x that spread, 1.25
+    x the single-precision deviation) per field: after 5000 steps the
+    trajectory's FP32 sensitivity dominates (both the GPU and the oracle's
+    single-precision build deviate by 9e-3 on phi and 0.18 on u_x); the
+    16-bit forms' per-field errors are stated (printed) and held to a guard
+    against blow-ups only."""
+    ref = np.load(GOLDEN_5000)
+    names = [str(n) for n in ref["fields"]]
+    spread = dict(zip(names, ref["spread"].tolist()))
+    dev32 = dict(zip(names, ref["dev_single"].tolist()))
+    cfg, phi, T, C, mask = droplet_3d(64, R=16.0, imp_R=3.0, seed=1)
+    print(f"[3d 5000] {storage}", flush=True)
+    s = Solver(cfg, phi, T, C, mask=mask, storage=storage)
+    s.step(5000)
+    got = s.fields()
+    errs = {k: rel_linf(got[k], ref[k].astype(np.float64), mask) for k in names}
+    print(f"[3d 5000] {storage} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
+          " | oracle spread " + " ".join(f"{k}={v:.2e}" for k, v in spread.items()) +
+          " | single-precision oracle " + " ".join(f"{k}={v:.2e}" for k, v in dev32.items()),
+          flush=True)
+    assert s.totals()["nonfinite"] == 0
+    for k, e in errs.items():
+        if storage == "f32":
+            assert e <= max(1e-4, 3.0 * spread[k], 1.25 * dev32[k]), (k, e, spread[k], dev32[k])
+        else:
+            assert e <= 0.5, (storage, k, e)
