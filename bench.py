@@ -315,12 +315,14 @@ def unet_flops_per_image(S: int) -> float:
 
 def time_surrogate(iters: int, ngrids: int, warm: int, nacc: int) -> dict:
     """The learned surrogate screening a sweep: train on LB snapshot pairs of
-    160 sweep seeds (4000 pairs at 256^2), then on ngrids held-out seeds past
-    `warm` strides of LB: one-stride predictions against the LB (accuracy,
-    acceptance by the phase-field mass check) over `nacc` strides, and the
-    time of a screened stride (batched forward, LB on the rejected grids,
-    restarts) against the LB stride of all grids, medians over fresh copies
-    of the held-out batch."""
+    160 sweep seeds (25 snapshot levels of 256^2 grids, two input levels per
+    pair), then on ngrids held-out seeds past `warm` strides of LB:
+    one-stride predictions against the LB (accuracy per field, acceptance by
+    the phase-field mass check, the check's false rejections of the LB's own
+    pairs) over `nacc` strides, and the time of a screened stride (batched
+    forward, LB on the rejected grids, restarts from the predicted fields)
+    against the LB stride of all grids, medians over fresh copies of the
+    held-out batch."""
     import torch
     from paper_2511_09422_amd import lbfz
     from paper_2511_09422_amd import surrogate as sg
@@ -342,11 +344,17 @@ def time_surrogate(iters: int, ngrids: int, warm: int, nacc: int) -> dict:
           f"({(t2 - t1) / iters * 1e3:.2f} ms each)", file=sys.stderr, flush=True)
     cases = [sweep_case(k, side=S) for k in range(10000, 10000 + ngrids)]
     ref = lbfz.Batch(cases)
-    ref.step(warm * sg.STRIDE)
+    ref.step((warm - 1) * sg.STRIDE)
     net_b = sg.UNet(net.weights(), ngrids, S)
     on_ref = sg.Screener(net_b, norm, ref)
+    on_ref.observe()
+    ref.step(sg.STRIDE)
     rows = []
+    lb_res = []
     names = sg.FIELD_NAMES
+    L = sg.nnlib()
+    qsum = torch.zeros(ngrids, dtype=torch.float64, device=net_b.dev)
+    after = torch.zeros((ngrids, sg.NEXP, S, S), dtype=torch.float32, device=net_b.dev)
 
     def rel(a, b):
         return float(np.linalg.norm(a.astype(np.float64) - b) /
@@ -354,10 +362,21 @@ def time_surrogate(iters: int, ngrids: int, warm: int, nacc: int) -> dict:
     for _ in range(nacc):
         res = on_ref.predict()
         pred = on_ref.pred.cpu().numpy()
+        before_phi = on_ref.before[:, 0].double().sum(dim=(1, 2)).cpu().numpy()
+        qb = on_ref.sums[on_ref.nsb + on_ref.nsa:on_ref.nsb + on_ref.nsa + ngrids].cpu().numpy()
         ref.step(sg.STRIDE)
+        # the check on the LB's own pair (before, after the stride)
+        ref.fields_all_to_device(sg.NEXP, after)
+        sg._ck(L.lbfz_nn_phi_div_sums(sg._p(after), ngrids, sg.NEXP * S * S, S, S, 1, 0, 4, 5,
+                                      sg._p(qsum), net_b.st), "phi_div_sums")
+        qa = qsum.cpu().numpy()
+        after_phi = after[:, 0].double().sum(dim=(1, 2)).cpu().numpy()
+        for i in range(ngrids):
+            lb_res.append(sg.mass_residual(before_phi[i], after_phi[i], qb[i], qa[i], S * S))
         for i in range(ngrids):
             f = ref.fields(i, names)
-            rows.append((res[i][0], [rel(pred[i, k], f[nm]) for k, nm in enumerate(names)]))
+            rows.append((res[i][0], [rel(pred[i, k], f[nm]) for k, nm in enumerate(names)
+                                     if nm != "uz"]))
     acc = np.array([r[0] for r in rows])
     err = np.array([r[1] for r in rows])
     slow = err[:, :4].max(1)
@@ -371,8 +390,9 @@ def time_surrogate(iters: int, ngrids: int, warm: int, nacc: int) -> dict:
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for r in range(reps):
         scr = lbfz.Batch(cases)
-        scr.step(warm * sg.STRIDE)
+        scr.step((warm - 1) * sg.STRIDE)
         on_scr = sg.Screener(net_b, norm, scr)
+        on_scr.observe()   # the older input level: the LB stride timed next follows it
         torch.cuda.synchronize()
         ev0.record(scr.stream)
         scr.step(sg.STRIDE)
@@ -423,9 +443,12 @@ def time_surrogate(iters: int, ngrids: int, warm: int, nacc: int) -> dict:
                                "speedup": round(lb_ms / sc2_ms, 3)},
             "one_stride": {"predictions": len(rows), "accepted": round(float(acc.mean()), 3),
                            "mass_tol": sg.MASS_TOL,
+                           "lb_pairs_rejected": round(float((np.array(lb_res) > sg.MASS_TOL).mean()), 3),
+                           "lb_pair_residual_median": float(f"{np.median(lb_res):.3g}"),
                            "accepted_all_slow_within_1e-2": round(float((slow[acc] <= 1e-2).mean()), 3),
                            "accepted_slow_max_p90": round(float(np.percentile(slow[acc], 90)), 5),
-                           "median_rel_l2": dict(zip(names, np.median(err, 0).round(5).tolist()))},
+                           "median_rel_l2": dict(zip([n for n in names if n != "uz"],
+                                                     np.median(err, 0).round(5).tolist()))},
             "forward": {"ms": round(fwd_ms, 3), "images": ngrids,
                         "roofline": {"bound": "mfma", "achieved": round(flops / fwd_ms / 1e9, 1),
                                      "peak": 2500.0, "unit": "TFLOP/s",
@@ -455,7 +478,7 @@ def main():
                     help="batched steps timed (default: one whole case)")
     ap.add_argument("--sweep-case-steps", type=int, default=10000,
                     help="steps that make one sweep case (cases/s is quoted for this length)")
-    ap.add_argument("--surrogate-iters", type=int, default=8000,
+    ap.add_argument("--surrogate-iters", type=int, default=12000,
                     help="training iterations of the surrogate (0: skip the surrogate section)")
     ap.add_argument("--surrogate-grids", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -181,6 +181,20 @@ int lbfz_nn_apply_images(const float* out, int out_cs, const float* before, int 
 int lbfz_nn_plane_sums(const float* src, int nplanes, long n, long stride, double* out,
                        void* stream);
 
+/* Phase-field budget term of nimg grids of nx x ny nodes: out[g] = sum over
+ * the nodes of phi * div u (FP64, fixed order), with div u the isotropic
+ * D2Q9 stencil divergence the step uses for the phase-field source (Sec. 3.1;
+ * stencil weights at the end of Sec. 3.4).  Grid g's FP32 planes at planes +
+ * g * img_stride, plane f at f * nx * ny: phi is plane f_phi, u_x plane f_ux,
+ * u_y plane f_uy.  x periodic; y periodic (walls = 0) or closed by no-slip
+ * walls (walls != 0: the ghost rows carry -u of the rows they mirror).  The
+ * screening check integrates it over a stride (trapezoid rule) to predict
+ * the change of sum phi.  Device pointers; out holds nimg doubles.  EINVAL
+ * for null pointers, nimg < 1, a side below 2, a negative plane index or
+ * img_stride shorter than the highest plane used. */
+int lbfz_nn_phi_div_sums(const float* planes, int nimg, long img_stride, int nx, int ny,
+                         int walls, int f_phi, int f_ux, int f_uy, double* out, void* stream);
+
 /* Wt[c][t][n] = W[n][t][c] (weights of the data-gradient convolution). */
 int lbfz_nn_transpose_w(const void* w, int N, int taps, int C, void* wt, void* stream);
 

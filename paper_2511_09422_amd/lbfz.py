@@ -456,10 +456,12 @@ class Batch:
         _check(lib().lbfz_batch_restart_many(self._b, len(idx), arr, ptrs, st),
                "lbfz_batch_restart_many")
 
-    def fields_all_to_device(self, nfields: int, dst) -> None:
-        """The first nfields fields (order FIELDS) of every grid into the
-        device tensor dst [grids][nfields][...] (asynchronous)."""
-        per = dst.numel() // dst.shape[0]
+    def fields_all_to_device(self, nfields: int, dst, case_stride: int = 0) -> None:
+        """The first nfields fields (order FIELDS) of every grid into device
+        memory at dst (a tensor or a view of one; asynchronous): grid i's
+        planes at dst + i * case_stride floats (default: dst is
+        [grids][nfields][...] and the stride its per-grid size)."""
+        per = case_stride or dst.numel() // dst.shape[0]
         _check(lib().lbfz_batch_fields_all(self._b, (1 << nfields) - 1, dst.data_ptr(), per),
                "lbfz_batch_fields_all")
 

@@ -1,26 +1,32 @@
 """Learned surrogate of the coupled LB freezing step: a 3-level U-Net that maps
-the six fields (phi, f_l, T, C, u_x, u_y) of a 2D grid to their change over
-64 LB steps, built from the BF16 MFMA kernels of ``liblbfz.so``
-(``include/lbfz_nn.h``).  The binding marshals arguments only; PyTorch holds
-the device memory.
+the fields of a 2D grid at two time levels, 64 LB steps apart, to the fields
+64 steps ahead (the change of phi, f_l, T, C; the new value of u and p),
+built from the BF16 MFMA kernels of ``liblbfz.so`` (``include/lbfz_nn.h``).
+The binding marshals arguments only; PyTorch holds the device memory.
 
 Network (NHWC, bf16 activations, FP32 master weights; 3x3 convolutions with
 zero padding, ReLU after every convolution but the head):
 
-    X0 (16 ch: phi, f_l, T, C, u_x, u_y, u_z = 0, p + zero padding)
+    X0 (16 ch: phi, f_l, T, C, u_x, u_y, u_z = 0, p 64 steps ago, then now)
     L1a 16->32, L1b 32->32 = S1 ........................ CAT1[:, 32:64]
     maxpool -> L2a 32->64, L2b 64->64 = S2 .............. CAT2[:, 64:128]
     maxpool -> L3a 64->128, L3b 128->128
     upsample -> U2 128->64 ............................. CAT2[:, 0:64]
     L4a 128->64, L4b 64->64
     upsample -> U1 64->32 .............................. CAT1[:, 0:32]
-    L5a 64->32, L5b 32->32, head 1x1 32->8 (6 used), FP32 output
+    L5a 64->32, L5b 32->32, head 1x1 32->8 (the eight fields), FP32 output
 
 The skip concatenations are channel slices of CAT1 / CAT2 written in place by
-the layers that produce them.  Screening: the prediction of a grid is
-accepted when its phase-field mass residual
-|sum dphi - (1 - rho_s / rho_l) sum df_s| / sum (1 + phi_in) / 2 is at most
-1e-3, else the grid is advanced by the LB step instead.
+the layers that produce them.  The pressure and the earlier time level are
+what make the velocity predictable: in the weakly compressible flow, u and p
+together fix the acoustic part of the flow, and the two levels its phase.
+Screening: the prediction of a grid is accepted when its phase-field mass
+residual -- how far the change of sum phi over the stride is from the
+scheme's own budget, sum phi div u per step (Sec. 3.1), integrated by the
+trapezoid rule between the two ends -- is at most 1e-3 of the grid's liquid
+volume and its solute sum is within 1e-3 of the one before the stride (the
+solute budget of Sec. 3.4 is exact), else the grid is advanced by the LB
+step instead.
 """
 from __future__ import annotations
 
@@ -31,12 +37,16 @@ import numpy as np
 
 from . import lbfz
 
-NF = 6           # predicted fields: phi, f_l, T, C, u_x, u_y
-NIN = 6          # input planes: phi, f_l, T, C, u_x, u_y (the predicted fields)
-NEXP = 8         # planes exported per grid by the screening: the six, u_z, p
-CIN0 = 16        # padded input channels
-HEAD = 8         # padded head channels
-FIELD_NAMES = ("phi", "fl", "T", "C", "ux", "uy")
+NEXP = 8         # fields of one time level: phi, f_l, T, C, u_x, u_y, u_z (0 in 2D), p
+NF = NEXP        # predicted fields: the same eight, 64 steps ahead
+NLEV = 2         # input time levels: 64 steps ago and now
+NIN = NLEV * NEXP  # input planes
+CIN0 = 16        # input channels
+HEAD = 8         # head channels
+FIELD_NAMES = ("phi", "fl", "T", "C", "ux", "uy", "uz", "p")
+# the fields the screening restarts an accepted grid from (RESTART_FIELDS of
+# the batch: phi, f_l, T, C, u_x, u_y, p), as indices into FIELD_NAMES
+RESTART_IDX = (0, 1, 2, 3, 4, 5, 7)
 LBFZ_NN_EINVAL = -1  # codes of the lbfz_nn_* calls (include/lbfz_nn.h)
 LBFZ_NN_EHIP = -3
 
@@ -84,6 +94,7 @@ def nnlib():
             "lbfz_nn_fill_u32": [vp, lg, u32, vp],
             "lbfz_nn_mse": [vp, i32, vp, lg, i32, vp, vp, vp, i32, vp, vp],
             "lbfz_nn_plane_sums": [vp, i32, lg, lg, vp, vp],
+            "lbfz_nn_phi_div_sums": [vp, i32, lg, i32, i32, i32, i32, i32, i32, vp, vp],
             "lbfz_nn_pack_images": [vp, i32, lg, i32, i32, vp, vp, vp, i32, vp],
             "lbfz_nn_apply_images": [vp, i32, vp, i32, lg, i32, i32, vp, vp, vp, vp, lg, vp],
             "lbfz_nn_adam": [vp, vp, vp, vp, vp, lg, f32, f32, f32, f32, i32, vp],
@@ -460,20 +471,21 @@ MASS_TOL = 1e-3  # screening: largest accepted phase-field mass residual
 
 def generate_snapshots(case_ids, side: int, nsnap: int, device: int = 0, storage: str = "f32"):
     """Run the LB step (batched, on the GPU) for the sweep grids case_ids with
-    their side replaced by `side`, and keep the NIN input planes every STRIDE
-    steps: a device tensor [ncases][nsnap][NIN][side][side] FP32 (snapshot 0 =
-    the initial state).  Returns (snapshots, params of each grid)."""
+    their side replaced by `side`, and keep the NEXP fields every STRIDE
+    steps: a device tensor [ncases][nsnap][NEXP][side][side] FP32 (snapshot 0
+    = the initial state).  Snapshots s - 1 and s of a grid are adjacent in
+    memory: together they are the network input of time level s.  Returns
+    (snapshots, params of each grid)."""
     import torch
     from .workloads import sweep_case
     cases = [sweep_case(k, side=side) for k in case_ids]
     b = lbfz.Batch(cases, device=device, storage=storage)
-    snaps = torch.zeros((len(cases), nsnap, NIN, side, side), dtype=torch.float32,
+    snaps = torch.zeros((len(cases), nsnap, NEXP, side, side), dtype=torch.float32,
                         device=b.device)
     for s in range(nsnap):
         if s:
             b.step(STRIDE)
-        for i in range(len(cases)):
-            b.fields_to_device(i, [snaps[i, s, f] for f in range(NIN)])
+        b.fields_all_to_device(NEXP, snaps[:, s], nsnap * NEXP * side * side)
     torch.cuda.synchronize()
     bad = sum(b.totals(i)["nonfinite"] for i in range(len(cases)))
     b.close()
@@ -483,28 +495,26 @@ def generate_snapshots(case_ids, side: int, nsnap: int, device: int = 0, storage
 
 
 # 1: the network learns the change of the field over STRIDE steps (phi, f_l,
-# T, C evolve slowly); 0: its new value (the velocity relaxes within a few
-# steps to the flow the slow fields drive, so its change is as large as itself)
-RESIDUAL = (1.0, 1.0, 1.0, 1.0, 0.0, 0.0)
-# loss weight per field: the velocity 64 steps ahead is largely unpredictable
-# from one snapshot (grid-scale currents decorrelate within the stride), so
-# it is weighted down to keep its irreducible error from swamping the rest
-LOSS_WEIGHT = (1.0, 1.0, 2.0, 1.0, 0.1, 0.1)
+# T, C evolve slowly); 0: its new value (u and p oscillate acoustically, and
+# their change over a stride is as large as they are)
+RESIDUAL = (1.0, 1.0, 1.0, 1.0, 0.0, 0.0, 0.0, 0.0)
+# loss weight per field (u_z is identically zero in 2D)
+LOSS_WEIGHT = (1.0, 1.0, 2.0, 1.0, 1.0, 1.0, 0.0, 1.0)
 
 
 class Normaliser:
-    """Per-field shift / scale of the network input (the fields) and of its
-    target (the change over STRIDE steps, or the new value -- RESIDUAL), from a
-    snapshot tensor [grids][snapshots][NF][S][S]."""
+    """Per-field shift / scale of the network input (the fields, the same for
+    both time levels) and of its target (the change over STRIDE steps, or the
+    new value -- RESIDUAL), from a snapshot tensor [grids][snapshots][NEXP][S][S]."""
 
     def __init__(self, snaps):
         import torch
-        x = snaps[:, :-1].transpose(0, 2).reshape(NIN, -1)
+        x = snaps[:, :-1].transpose(0, 2).reshape(NEXP, -1)
         r = torch.tensor(RESIDUAL, dtype=snaps.dtype, device=snaps.device)
         d = (snaps[:, 1:, :NF] - r[None, None, :, None, None] * snaps[:, :-1, :NF])
         d = d.transpose(0, 2).reshape(NF, -1)
-        self.in_shift = x.mean(dim=1)
-        self.in_scale = 1.0 / x.std(dim=1).clamp_min(1e-12)
+        self.in_shift = x.mean(dim=1).repeat(NLEV)
+        self.in_scale = (1.0 / x.std(dim=1).clamp_min(1e-12)).repeat(NLEV)
         self.d_shift = d.mean(dim=1)
         self.d_scale = 1.0 / d.std(dim=1).clamp_min(1e-12)
         self.resid = r
@@ -514,12 +524,13 @@ class Normaliser:
 
 def load_pairs(net: UNet, snaps, norm: Normaliser, pairs) -> None:
     """Images b = 0..len(pairs)-1 of the network input and target from the
-    (grid, snapshot) pairs: input = snapshot s, target = snapshot s+1 minus s."""
+    (grid, snapshot) pairs, s >= NLEV - 1: input = snapshots s - 1 and s (the
+    two time levels, adjacent in memory), target = snapshot s + 1 against s."""
     L = nnlib()
     S = net.S
     for b, (i, s) in enumerate(pairs):
         before, after = snaps[i, s], snaps[i, s + 1]
-        _ck(L.lbfz_nn_pack_fields(_p(before), NIN, S, S, 0, 0, S, _p(norm.in_shift),
+        _ck(L.lbfz_nn_pack_fields(_p(snaps[i, s - NLEV + 1]), NIN, S, S, 0, 0, S, _p(norm.in_shift),
                                   _p(norm.in_scale), _p(net.t["X0"]), CIN0, b, net.st),
             "pack_fields")
         _ck(L.lbfz_nn_pack_delta(_p(after), _p(before), NF, S, S, 0, 0, S, _p(norm.d_shift),
@@ -538,7 +549,8 @@ def train(net: UNet, snaps, norm: Normaliser, iters: int, lr: float = 1e-3, seed
     wch = torch.tensor(LOSS_WEIGHT, dtype=torch.float32, device=net.dev)
     hist = []
     for it in range(iters):
-        pairs = [(int(rng.integers(ng)), int(rng.integers(ns))) for _ in range(net.B)]
+        pairs = [(int(rng.integers(ng)), int(rng.integers(NLEV - 1, ns)))
+                 for _ in range(net.B)]
         load_pairs(net, snaps, norm, pairs)
         net.forward()
         net.loss(channel_weights=wch)
@@ -550,12 +562,12 @@ def train(net: UNet, snaps, norm: Normaliser, iters: int, lr: float = 1e-3, seed
 
 
 def predict(net: UNet, snaps, norm: Normaliser, pairs, out):
-    """Predicted fields after STRIDE steps for the (grid, snapshot) pairs into
-    out [len(pairs)][NF][S][S] (device, FP32)."""
+    """Predicted fields after STRIDE steps for the (grid, snapshot) pairs
+    (s >= NLEV - 1) into out [len(pairs)][NF][S][S] (device, FP32)."""
     L = nnlib()
     S = net.S
     for b, (i, s) in enumerate(pairs):
-        _ck(L.lbfz_nn_pack_fields(_p(snaps[i, s]), NIN, S, S, 0, 0, S, _p(norm.in_shift),
+        _ck(L.lbfz_nn_pack_fields(_p(snaps[i, s - NLEV + 1]), NIN, S, S, 0, 0, S, _p(norm.in_shift),
                                   _p(norm.in_scale), _p(net.t["X0"]), CIN0, b, net.st),
             "pack_fields")
     net.forward()
@@ -566,18 +578,25 @@ def predict(net: UNet, snaps, norm: Normaliser, pairs, out):
 
 
 # ---------------------------------------------------------------- screening
-SOLUTE_TOL = None  # screening: largest accepted relative drift of sum C (None: not checked)
+# screening: largest accepted relative drift of sum C (None: not checked).  The
+# LB conserves the solute to FP32 rounding (relative drift about 1e-7 over a
+# stride), so the check rejects no LB state; the predictions it rejects are
+# mostly those of grids holding little solute, whose C the network gets
+# least right relative to its size
+SOLUTE_TOL = 1e-3
 
 
-def mass_residual(sum_phi_b, sum_phi_a, sum_fl_b, sum_fl_a, n: int, ratio: float) -> float:
-    """Phase-field mass residual of a prediction from per-grid sums:
-    |sum dphi - ratio * sum df_s| / sum (1 + phi_before) / 2 over the n nodes,
-    with df_s = -df_l and ratio = 1 - rho_s / rho_l (the volume change of
-    freezing, Eq. NS1)."""
+def mass_residual(sum_phi_b, sum_phi_a, q_b, q_a, n: int) -> float:
+    """Phase-field mass residual of a prediction from per-grid sums: each LB
+    step adds sum phi div u to sum phi (the phase-field source, Sec. 3.1;
+    freezing enters through div u = mdot, Eq. NS1, and so does the flow's
+    compression), so over a stride
+        |sum phi_after - sum phi_before - (STRIDE / 2) (q_b + q_a)|
+    over the liquid volume sum (1 + phi_before) / 2 of the n nodes, where q is
+    sum phi div u of the state at either end (the trapezoid rule)."""
     dphi = sum_phi_a - sum_phi_b
-    dfs = -(sum_fl_a - sum_fl_b)
     denom = 0.5 * (n + sum_phi_b)
-    return abs(dphi - ratio * dfs) / max(denom, 1e-30)
+    return abs(dphi - 0.5 * STRIDE * (q_b + q_a)) / max(denom, 1e-30)
 
 
 def solute_drift(sum_c_b, sum_c_a) -> float:
@@ -587,51 +606,50 @@ def solute_drift(sum_c_b, sum_c_a) -> float:
     return abs(sum_c_a - sum_c_b) / max(abs(sum_c_b), 1e-30)
 
 
-def check(sums_before, sums_after, n: int, ratio: float, mass_tol: float = MASS_TOL,
+def check(sums_before, sums_after, n: int, q_b: float, q_a: float, mass_tol: float = MASS_TOL,
           solute_tol: float = SOLUTE_TOL):
     """Accept a prediction (True) or send its grid to the LB (False): the
     phase-field mass residual within mass_tol and, when solute_tol is given,
     the solute drift within it; a non-finite prediction is never accepted.
     sums_*: per-field sums (phi, f_l, T, C, ...) of the grid before the
-    stride and of the prediction.  Returns (accept, mass residual, drift)."""
-    r = mass_residual(sums_before[0], sums_after[0], sums_before[1], sums_after[1], n, ratio)
+    stride and of the prediction; q_b, q_a: sum phi div u of the two.
+    Returns (accept, mass residual, drift)."""
+    r = mass_residual(sums_before[0], sums_after[0], q_b, q_a, n)
     d = solute_drift(sums_before[3], sums_after[3])
-    ok = bool(np.all(np.isfinite(sums_after)) and r <= mass_tol and
+    ok = bool(np.all(np.isfinite(sums_after)) and np.isfinite(q_a) and r <= mass_tol and
               (solute_tol is None or d <= solute_tol))
     return ok, r, d
 
 
-def check_all(sums_before, sums_after, n: int, ratios, mass_tol: float = MASS_TOL,
+def check_all(sums_before, sums_after, n: int, q_b, q_a, mass_tol: float = MASS_TOL,
               solute_tol: float = SOLUTE_TOL):
-    """check() for many grids at once (row i: grid i's sums, ratios[i] its
-    1 - rho_s / rho_l), in array arithmetic: the same values, without a
-    Python loop over the grids.  Returns the list of (accept, residual,
-    drift)."""
+    """check() for many grids at once (row i / entry i: grid i), in array
+    arithmetic: the same values, without a Python loop over the grids.
+    Returns the list of (accept, residual, drift)."""
     sb = np.asarray(sums_before, dtype=np.float64)
     sa = np.asarray(sums_after, dtype=np.float64)
-    ratios = np.asarray(ratios, dtype=np.float64)
+    q_b = np.asarray(q_b, dtype=np.float64)
+    q_a = np.asarray(q_a, dtype=np.float64)
     dphi = sa[:, 0] - sb[:, 0]
-    dfs = -(sa[:, 1] - sb[:, 1])
     denom = np.maximum(0.5 * (n + sb[:, 0]), 1e-30)
-    r = np.abs(dphi - ratios * dfs) / denom
+    r = np.abs(dphi - 0.5 * STRIDE * (q_b + q_a)) / denom
     d = np.abs(sa[:, 3] - sb[:, 3]) / np.maximum(np.abs(sb[:, 3]), 1e-30)
-    ok = np.all(np.isfinite(sa), axis=1) & (r <= mass_tol)
+    ok = np.all(np.isfinite(sa), axis=1) & np.isfinite(q_a) & (r <= mass_tol)
     if solute_tol is not None:
         ok &= d <= solute_tol
     return [(bool(ok[i]), float(r[i]), float(d[i])) for i in range(sb.shape[0])]
 
 
 class Screener:
-    """Screens a batched sweep (an lbfz.Batch of equal S x S grids) STRIDE
-    steps at a time: one surrogate forward over every grid; grids whose
-    prediction passes the check take it (equilibrium restart from the
-    predicted phi, f_l, T, C, at rest, with the pressure before the stride),
-    the rest are advanced by the LB (subset step).  The velocity 64 steps
-    ahead is not predicted with skill (relative L2 error about 1, no better
-    than zero), so an accepted grid restarts at rest rather than from the
-    network's velocity: the restart's velocity error is then exactly the
-    LB's own velocity (relative L2 error 1), with no spurious structure
-    added.  net: a UNet of batch >= the number of grids and side S."""
+    """Screens a batched sweep (an lbfz.Batch of equal S x S grids with walls
+    on y) STRIDE steps at a time: one surrogate forward over every grid;
+    grids whose prediction passes the check are restarted from it
+    (equilibrium populations of the predicted phi, f_l, T, C, u and p), the
+    rest are advanced by the LB (subset step).  The network reads two time
+    levels: observe() records the grids' state, and a prediction needs the
+    state of STRIDE steps earlier recorded first (observe(), then STRIDE
+    steps of the batch, then predict() or stride()).  net: a UNet of batch >=
+    the number of grids and side S."""
 
     def __init__(self, net: UNet, norm: Normaliser, batch, mass_tol: float = MASS_TOL,
                  solute_tol: float = SOLUTE_TOL):
@@ -642,47 +660,76 @@ class Screener:
         if any(sh != (S, S) for sh in batch.shapes) or self.n > net.B:
             raise ValueError("screening needs grids of the network's side, at most its batch")
         self.S = S
-        self.ratios = [1.0 - c["rho_s"] / c["rho_l"] for c in batch.cfgs]
+        self.walls = [int(c.get("walls", 1)) for c in batch.cfgs]
+        if len(set(self.walls)) != 1:
+            raise ValueError("screening needs grids with the same boundaries")
         self.mass_tol, self.solute_tol = mass_tol, solute_tol
         f = dict(dtype=torch.float32, device=net.dev)
-        self.before = torch.zeros((self.n, NEXP, S, S), **f)
+        # the two time levels of every grid, as the network reads them:
+        # hist[i, :NEXP] STRIDE steps ago, hist[i, NEXP:] now
+        self.hist = torch.zeros((self.n, NIN, S, S), **f)
+        self.before = self.hist[:, NEXP:]          # the current level (a view)
         self.pred = torch.zeros((self.n, NF, S, S), **f)
-        self.rest = torch.zeros((S, S), **f)  # the restart velocity
-        # per-grid sums before the stride and of the prediction, in one
-        # buffer so that the check needs one device-to-host copy
-        self.sums = torch.zeros(self.n * (NEXP + NF), dtype=torch.float64, device=net.dev)
-        self.sums_b = self.sums[:self.n * NEXP]
-        self.sums_a = self.sums[self.n * NEXP:]
+        # per-grid sums of both levels and of the prediction, and sum phi div u
+        # now and predicted, in one buffer so that the check needs one
+        # device-to-host copy
+        self.nsb, self.nsa = self.n * NIN, self.n * NF
+        self.sums = torch.zeros(self.nsb + self.nsa + 2 * self.n, dtype=torch.float64,
+                                device=net.dev)
+        self.levels = 0  # time levels recorded so far
         self.time = 0  # LB steps screened so far (the batch's own counter only
         # moves when some grid falls back to the LB)
         self.fused = True  # network tail, head and prediction in one launch
 
+    def observe(self):
+        """Record the grids' current state as the newer time level (the
+        previous newer one becomes the older)."""
+        SS = self.S * self.S
+        if self.levels:
+            self.hist[:, :NEXP].copy_(self.hist[:, NEXP:])
+        self.batch.fields_all_to_device(NEXP, self.before, NIN * SS)
+        self.levels += 1
+
     def predict(self):
-        """Export every grid's fields, run the network, apply its output:
-        self.pred holds the fields STRIDE steps ahead.  Returns the per-grid
-        (accept, mass residual, solute drift) of the check."""
+        """Record the current state (observe()), run the network on the two
+        levels, apply its output: self.pred holds the fields STRIDE steps
+        ahead.  Returns the per-grid (accept, mass residual, solute drift) of
+        the check."""
+        if self.levels < 1:
+            raise RuntimeError("observe() the grids STRIDE steps before the first prediction")
+        self.observe()
         L, net, S, st = nnlib(), self.net, self.S, self.net.st
-        self.batch.fields_all_to_device(NEXP, self.before)
-        _ck(L.lbfz_nn_pack_images(_p(self.before), self.n, NEXP * S * S, NIN, S,
+        SS = S * S
+        _ck(L.lbfz_nn_pack_images(_p(self.hist), self.n, NIN * SS, NIN, S,
                                   _p(self.norm.in_shift), _p(self.norm.in_scale),
                                   _p(net.t["X0"]), CIN0, st), "pack_images")
+        cur = self.hist[0, NEXP]                   # plane 0 of grid 0's current level
         if self.fused:
-            net.predict_fields(self.n, self.before, NEXP * S * S, self.pred, NF * S * S, NF,
+            net.predict_fields(self.n, cur, NIN * SS, self.pred, NF * SS, NF,
                                self.norm.d_shift, self.norm.d_scale, self.norm.resid)
         else:
             net.forward()
-            _ck(L.lbfz_nn_apply_images(_p(net.t["OUT"]), HEAD, _p(self.before), self.n,
-                                       NEXP * S * S, NF, S, _p(self.norm.d_shift),
-                                       _p(self.norm.d_scale), _p(self.norm.resid),
-                                       _p(self.pred), NF * S * S, st), "apply_images")
-        _ck(L.lbfz_nn_plane_sums(_p(self.before), self.n * NEXP, S * S, S * S, _p(self.sums_b),
-                                 st), "plane_sums")
-        _ck(L.lbfz_nn_plane_sums(_p(self.pred), self.n * NF, S * S, S * S, _p(self.sums_a),
-                                 st), "plane_sums")
-        host = self.sums.cpu().numpy()
-        sb = host[:self.n * NEXP].reshape(self.n, NEXP)
-        sa = host[self.n * NEXP:].reshape(self.n, NF)
-        return check_all(sb, sa, S * S, self.ratios, self.mass_tol, self.solute_tol)
+            _ck(L.lbfz_nn_apply_images(_p(net.t["OUT"]), HEAD, _p(cur), self.n, NIN * SS, NF,
+                                       S, _p(self.norm.d_shift), _p(self.norm.d_scale),
+                                       _p(self.norm.resid), _p(self.pred), NF * SS, st),
+                "apply_images")
+        sums = self.sums
+        sb = sums[:self.nsb]
+        sa = sums[self.nsb:self.nsb + self.nsa]
+        qb = sums[self.nsb + self.nsa:self.nsb + self.nsa + self.n]
+        qa = sums[self.nsb + self.nsa + self.n:]
+        _ck(L.lbfz_nn_plane_sums(_p(self.hist), self.n * NIN, SS, SS, _p(sb), st), "plane_sums")
+        _ck(L.lbfz_nn_plane_sums(_p(self.pred), self.n * NF, SS, SS, _p(sa), st), "plane_sums")
+        walls = self.walls[0]
+        _ck(L.lbfz_nn_phi_div_sums(_p(cur), self.n, NIN * SS, S, S, walls, 0, 4, 5, _p(qb), st),
+            "phi_div_sums")
+        _ck(L.lbfz_nn_phi_div_sums(_p(self.pred), self.n, NF * SS, S, S, walls, 0, 4, 5, _p(qa),
+                                   st), "phi_div_sums")
+        host = sums.cpu().numpy()
+        hb = host[:self.nsb].reshape(self.n, NIN)[:, NEXP:]
+        ha = host[self.nsb:self.nsb + self.nsa].reshape(self.n, NF)
+        q = host[self.nsb + self.nsa:]
+        return check_all(hb, ha, SS, q[:self.n], q[self.n:], self.mass_tol, self.solute_tol)
 
     def stride(self):
         """One screened stride; returns the accept mask (list of bool) and the
@@ -697,12 +744,8 @@ class Screener:
             self.batch.step(STRIDE)
         self.time += STRIDE
         SS = self.S * self.S
-        # phi, f_l, T, C from the prediction; u = 0 (one zero plane for every
-        # grid: stride 0); p from before the stride
-        planes = [self.pred[0, f] for f in range(4)] + [self.rest, self.rest]
         self.batch.restart_many([i for i in range(self.n) if acc[i]],
-                                planes + [self.before[0, NEXP - 1]],
-                                [NF * SS] * 4 + [0, 0] + [NEXP * SS])
+                                [self.pred[0, f] for f in RESTART_IDX], [NF * SS] * 7)
         self.batch.select([])
         return acc, res
 

@@ -357,3 +357,34 @@ def test_conv_tail_fused_head_and_prediction(B, S, Cin):
     pu = pred_u.cpu().numpy()[:, :NF * npx].reshape(B, NF, npx).astype(np.float64)
     e = float(np.abs(pf - pu).max() / np.abs(inc_ref).max())
     assert e <= 1e-5, e
+
+
+@pytest.mark.parametrize("nx,ny,walls,nimg", [(64, 48, 1, 3), (40, 72, 0, 2), (256, 256, 1, 2)])
+def test_phi_div_sums_against_cpu(nx, ny, walls, nimg):
+    """lbfz_nn_phi_div_sums (the screening check's sum of phi div u per grid)
+    against the FP64 reference on the same FP32 fields: equal to FP64
+    summation-order rounding (1e-12 of the sum of |phi div u|), for planes at
+    a stride larger than the fields a grid holds."""
+    import torch
+    from paper_2511_09422_amd import surrogate as sg
+    from tests.divergence_ref import div_d2q9
+    rng = np.random.default_rng(nx + ny + walls)
+    npx = nx * ny
+    stride = 9 * npx
+    host = rng.standard_normal((nimg, 9, ny, nx)).astype(np.float32)
+    host[:, 4:6] *= 1e-3
+    dev = torch.tensor(host.reshape(-1)).cuda()
+    out = torch.zeros(nimg, dtype=torch.float64).cuda()
+    L = sg.nnlib()
+    st = torch.cuda.current_stream().cuda_stream
+    assert L.lbfz_nn_phi_div_sums(sg._p(dev), nimg, stride, nx, ny, walls, 0, 4, 5, sg._p(out),
+                                  st) == 0
+    got = out.cpu().numpy()
+    for g in range(nimg):
+        t = host[g, 0].astype(np.float64) * div_d2q9(host[g, 4], host[g, 5], walls)
+        assert abs(got[g] - t.sum()) <= 1e-12 * np.abs(t).sum(), (g, got[g], t.sum())
+    # argument checks: a stride too short for the highest plane, a bad side
+    assert L.lbfz_nn_phi_div_sums(sg._p(dev), nimg, 5 * npx, nx, ny, walls, 0, 4, 5,
+                                  sg._p(out), st) == sg.LBFZ_NN_EINVAL
+    assert L.lbfz_nn_phi_div_sums(sg._p(dev), nimg, stride, 1, ny, walls, 0, 4, 5,
+                                  sg._p(out), st) == sg.LBFZ_NN_EINVAL
