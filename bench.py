@@ -229,6 +229,40 @@ def time_copy(nbytes: int, reps: int = 20) -> dict:
             "runtime_copy_us": ms_rt * 1e3, "runtime_copy_GBs": 8 * n / (ms_rt * 1e-3) / 1e9}
 
 
+def time_pattern(n: int, reps: int = 20) -> dict:
+    """The step's own memory pattern without its arithmetic (lbfz_stream_planes:
+    30 FP32 planes of an n x n grid read at each node and written to the rows
+    the step's pushes land on), timed with HIP events on its stream: the
+    bandwidth this access pattern can reach."""
+    import torch
+    from paper_2511_09422_amd.lbfz import lbfz_stream_planes
+    N = n * n
+    ps = (N + 63) // 64 * 64 + 1088
+    a = torch.ones(30 * ps, dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    st = torch.cuda.current_stream()
+    fn = lambda: lbfz_stream_planes(b.data_ptr(), a.data_ptr(), n, n, ps, st.cuda_stream)
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    for _ in range(reps):
+        fn()
+    ev1.record(st)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    ok = bool(torch.equal(b[:N], a[:N]))
+    del a, b
+    torch.cuda.empty_cache()
+    if not ok:
+        print("bench: the plane pattern did not move its source", file=sys.stderr)
+        sys.exit(1)
+    nbytes = 2 * 30 * 4 * N
+    return {"bytes": nbytes, "us": ms * 1e3, "GBs": nbytes / (ms * 1e-3) / 1e9}
+
+
 def time_sweep(ncases: int, steps: int, case_steps: int, storage: str) -> dict:
     """The batched parameter sweep: ncases grids drawn by sweep_case(k), tuned,
     then whole cases -- `steps` batched steps (case_steps by default) --
@@ -368,7 +402,8 @@ def time_surrogate(iters: int, ngrids: int, warm: int, nacc: int) -> dict:
         # the check on the LB's own pair (before, after the stride)
         ref.fields_all_to_device(sg.NEXP, after)
         sg._ck(L.lbfz_nn_phi_div_sums(sg._p(after), ngrids, sg.NEXP * S * S, S, S, 1, 0, 4, 5,
-                                      sg._p(qsum), net_b.st), "phi_div_sums")
+                                      sg._p(on_ref.parts), sg.PHI_DIV_PARTS, sg._p(qsum),
+                                      net_b.st), "phi_div_sums")
         qa = qsum.cpu().numpy()
         after_phi = after[:, 0].double().sum(dim=(1, 2)).cpu().numpy()
         for i in range(ngrids):
@@ -507,6 +542,9 @@ def main():
     copy_r = time_copy(main_r["bytes_per_node"] * n * n)
     print(f"bench: copy of the same {copy_r['bytes'] / 1e6:.0f} MB {copy_r['us']:.2f} us "
           f"({copy_r['GBs']:.0f} GB/s)", file=sys.stderr, flush=True)
+    pat_r = time_pattern(n)
+    print(f"bench: the step's plane pattern {pat_r['us']:.2f} us ({pat_r['GBs']:.0f} GB/s)",
+          file=sys.stderr, flush=True)
     other = {}
     for f in forms:
         r = time_form(cfg, phi, T, C, f, args.warmup, args.steps)
@@ -592,7 +630,13 @@ def main():
                          "frac_of_peak": round(copy_r["GBs"] / HBM_PEAK_GBS, 4),
                          "step_vs_copy": round(main_r["achieved"] / copy_r["GBs"], 4),
                          "runtime_copy": {"us": round(copy_r["runtime_copy_us"], 2),
-                                          "GB/s": round(copy_r["runtime_copy_GBs"], 1)}},
+                                          "GB/s": round(copy_r["runtime_copy_GBs"], 1)},
+                         "step_pattern": {"kernel": "lbfz_stream_planes", "bytes": pat_r["bytes"],
+                                          "us": round(pat_r["us"], 2),
+                                          "GB/s": round(pat_r["GBs"], 1),
+                                          "frac_of_peak": round(pat_r["GBs"] / HBM_PEAK_GBS, 4),
+                                          "step_vs_pattern":
+                                              round(main_r["achieved"] / pat_r["GBs"], 4)}},
     }
     if other:
         out["storage_forms"] = other

@@ -256,6 +256,19 @@ void lbfz_batch_destroy(lbfz_batch* b);
  * 16), LBFZ_EHIP. */
 int lbfz_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
 
+/* The memory pattern of one 2D FP32 step of an nx x ny grid without its
+ * arithmetic: for every node, the 30 FP32 planes a node update reads (24
+ * populations and 6 previous-level fields; plane k of src at k *
+ * plane_stride floats) are read at the node and written into the same plane
+ * of dst one row down, in place or one row up (k mod 3; y periodic), as the
+ * step's pushed populations land on their target rows.  The bandwidth of
+ * this kernel, beside lbfz_stream_copy's, bounds what the step's access
+ * pattern can reach.  Both buffers hold 30 planes, device memory, not
+ * overlapping; asynchronous on `stream`.  Errors: LBFZ_EINVAL (NULL pointer,
+ * empty grid, plane_stride below nx * ny), LBFZ_EHIP. */
+int lbfz_stream_planes(float* dst, const float* src, int nx, int ny, long plane_stride,
+                       void* stream);
+
 /* Blocks until the handle's stream is idle. */
 int lbfz_sync(lbfz_handle* h);
 

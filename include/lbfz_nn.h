@@ -189,11 +189,15 @@ int lbfz_nn_plane_sums(const float* src, int nplanes, long n, long stride, doubl
  * u_y plane f_uy.  x periodic; y periodic (walls = 0) or closed by no-slip
  * walls (walls != 0: the ghost rows carry -u of the rows they mirror).  The
  * screening check integrates it over a stride (trapezoid rule) to predict
- * the change of sum phi.  Device pointers; out holds nimg doubles.  EINVAL
- * for null pointers, nimg < 1, a side below 2, a negative plane index or
- * img_stride shorter than the highest plane used. */
+ * the change of sum phi.  Each grid is summed in nparts interleaved row sets
+ * into the caller's parts buffer (nimg * nparts doubles, overwritten), then
+ * the parts are added in order.  Device pointers; out holds nimg doubles.
+ * EINVAL for null pointers, nimg outside 1 .. 65535, a side below 2, nparts
+ * outside 1 .. ny, a negative plane index or img_stride shorter than the
+ * highest plane used. */
 int lbfz_nn_phi_div_sums(const float* planes, int nimg, long img_stride, int nx, int ny,
-                         int walls, int f_phi, int f_ux, int f_uy, double* out, void* stream);
+                         int walls, int f_phi, int f_ux, int f_uy, double* parts, int nparts,
+                         double* out, void* stream);
 
 /* Wt[c][t][n] = W[n][t][c] (weights of the data-gradient convolution). */
 int lbfz_nn_transpose_w(const void* w, int N, int taps, int C, void* wt, void* stream);

@@ -1,7 +1,8 @@
-// lbfz_copy.hip -- the streaming-copy reference of the step: a device copy
-// that reads and writes every byte once, as one time step reads and writes
-// the whole solver state once.  Its bandwidth is what this memory system
-// gives a pure streaming kernel, the practical ceiling of the step.
+// lbfz_copy.hip -- the streaming references of the step: a device copy that
+// reads and writes every byte once, as one time step reads and writes the
+// whole solver state once, and the step's own plane pattern without its
+// arithmetic.  Their bandwidths are what this memory system gives a pure
+// streaming kernel and the step's access pattern, its practical ceilings.
 //
 // Form (chosen by timing 1007 MB copies on MI355X): 16-byte loads and stores,
 // one in flight per lane, a grid-stride loop over 4 blocks of 256 threads
@@ -24,7 +25,41 @@ __global__ __launch_bounds__(256) void k_stream_copy(const f4* __restrict__ src,
   for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
 }
 
+// The memory pattern of the 2D FP32 step without its arithmetic: each node
+// reads the 30 planes of a node update (24 populations, 6 previous-level
+// fields) at its own position and writes them one row down, in place or one
+// row up (y periodic) in turn, as the step's pushed populations land on the
+// rows of their targets (the step's planes are shifted along x, so a push
+// lands on the target row at the writer's own column).  All loads of a lane
+// are issued before its first store; loads and stores carry the
+// non-temporal hint.
+constexpr int kPatternPlanes = 30;
+__global__ __launch_bounds__(256) void k_stream_planes(const float* __restrict__ src,
+                                                       float* __restrict__ dst, int nx, int ny,
+                                                       long ps) {
+  const long n = (long)blockIdx.x * 256 + threadIdx.x;
+  if (n >= (long)nx * ny) return;
+  const int y = (int)(n / nx), x = (int)(n - (long)y * nx);
+  float v[kPatternPlanes];
+#pragma unroll
+  for (int k = 0; k < kPatternPlanes; ++k) v[k] = __builtin_nontemporal_load(src + k * ps + n);
+  const long rows[3] = {(long)(y == 0 ? ny - 1 : y - 1) * nx + x, (long)y * nx + x,
+                        (long)(y == ny - 1 ? 0 : y + 1) * nx + x};
+#pragma unroll
+  for (int k = 0; k < kPatternPlanes; ++k)
+    __builtin_nontemporal_store(v[k], dst + k * ps + rows[k % 3]);
+}
+
 }  // namespace
+
+extern "C" int lbfz_stream_planes(float* dst, const float* src, int nx, int ny, long plane_stride,
+                                  void* stream) {
+  if (!dst || !src || nx < 1 || ny < 1 || plane_stride < (long)nx * ny) return LBFZ_EINVAL;
+  const long n = (long)nx * ny;
+  hipLaunchKernelGGL(k_stream_planes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, src, dst, nx, ny, plane_stride);
+  return hipGetLastError() == hipSuccess ? LBFZ_OK : LBFZ_EHIP;
+}
 
 extern "C" int lbfz_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
   if (!dst || !src || bytes % 16 != 0 || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))

@@ -1026,22 +1026,22 @@ __global__ __launch_bounds__(256) void k_plane_sums(const float* __restrict__ sr
 // uses for the phase-field source (Sec. 3.1; stencil weights at the end of
 // Sec. 3.4), x periodic, y periodic or closed by no-slip walls (ghost rows
 // are the negated mirrors of the first and last rows).  Grid g's planes sit
-// at planes + g * img_stride, plane f at f * nx * ny.  One block per grid,
-// FP64 in a fixed order (per-thread strided sums, then a tree).
-__global__ __launch_bounds__(256) void k_phi_div_sums(const float* __restrict__ planes,
-                                                      long img_stride, int nx, int ny, int walls,
-                                                      int f_phi, int f_ux, int f_uy,
-                                                      double* __restrict__ out) {
+// at planes + g * img_stride, plane f at f * nx * ny.  Block (p, g) sums the
+// rows p, p + nparts, ... of grid g into part[g * nparts + p]; a second pass
+// adds a grid's parts in order (FP64 throughout, fixed order).
+__global__ __launch_bounds__(256) void k_phi_div_parts(const float* __restrict__ planes,
+                                                       long img_stride, int nx, int ny, int walls,
+                                                       int f_phi, int f_ux, int f_uy,
+                                                       double* __restrict__ part) {
   __shared__ double red[256];
+  const int nparts = gridDim.x, p = blockIdx.x, g = blockIdx.y;
   const long np = (long)nx * ny;
-  const float* base = planes + (long)blockIdx.x * img_stride;
+  const float* base = planes + (long)g * img_stride;
   const float* phi = base + (long)f_phi * np;
   const float* ux = base + (long)f_ux * np;
   const float* uy = base + (long)f_uy * np;
   double acc = 0.0;
-  for (long i = threadIdx.x; i < np; i += 256) {
-    const int y = (int)(i / nx), x = (int)(i - (long)y * nx);
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  for (int y = p; y < ny; y += nparts) {
     // the rows below / above and the sign of their velocity (a ghost row
     // beyond a no-slip wall carries -u of the row it mirrors)
     int ym = y - 1, yp = y + 1;
@@ -1055,13 +1055,16 @@ __global__ __launch_bounds__(256) void k_phi_div_sums(const float* __restrict__ 
       sp = walls ? -1.0 : 1.0;
     }
     const long rm = (long)ym * nx, r0 = (long)y * nx, rp = (long)yp * nx;
-    const double dux = (1.0 / 3.0) * ((double)ux[r0 + xp] - (double)ux[r0 + xm]) +
-                       (1.0 / 12.0) * (sp * ux[rp + xp] + sm * ux[rm + xp] - sp * ux[rp + xm] -
-                                       sm * ux[rm + xm]);
-    const double duy = (1.0 / 3.0) * (sp * uy[rp + x] - sm * uy[rm + x]) +
-                       (1.0 / 12.0) * (sp * uy[rp + xp] + sp * uy[rp + xm] - sm * uy[rm + xp] -
-                                       sm * uy[rm + xm]);
-    acc += (double)phi[i] * (dux + duy);
+    for (int x = threadIdx.x; x < nx; x += 256) {
+      const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+      const double dux = (1.0 / 3.0) * ((double)ux[r0 + xp] - (double)ux[r0 + xm]) +
+                         (1.0 / 12.0) * (sp * ux[rp + xp] + sm * ux[rm + xp] - sp * ux[rp + xm] -
+                                         sm * ux[rm + xm]);
+      const double duy = (1.0 / 3.0) * (sp * uy[rp + x] - sm * uy[rm + x]) +
+                         (1.0 / 12.0) * (sp * uy[rp + xp] + sp * uy[rp + xm] - sm * uy[rm + xp] -
+                                         sm * uy[rm + xm]);
+      acc += (double)phi[r0 + x] * (dux + duy);
+    }
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -1069,7 +1072,17 @@ __global__ __launch_bounds__(256) void k_phi_div_sums(const float* __restrict__ 
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) part[(long)g * nparts + p] = red[0];
+}
+
+// out[g] = the nparts parts of grid g added in order (one thread per grid).
+__global__ void k_sum_parts(const double* __restrict__ part, int nparts, int nimg,
+                            double* __restrict__ out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nimg) return;
+  double s = 0.0;
+  for (int p = 0; p < nparts; ++p) s += part[(long)g * nparts + p];
+  out[g] = s;
 }
 
 // Adam on FP32 master weights (bias-corrected), then the bf16 copy.
@@ -1535,14 +1548,18 @@ int lbfz_nn_plane_sums(const float* src, int nplanes, long n, long stride, doubl
 }
 
 int lbfz_nn_phi_div_sums(const float* planes, int nimg, long img_stride, int nx, int ny,
-                         int walls, int f_phi, int f_ux, int f_uy, double* out, void* stream) {
-  if (!planes || !out || nimg <= 0 || nx < 2 || ny < 2 || f_phi < 0 || f_ux < 0 || f_uy < 0)
+                         int walls, int f_phi, int f_ux, int f_uy, double* parts, int nparts,
+                         double* out, void* stream) {
+  if (!planes || !parts || !out || nimg <= 0 || nx < 2 || ny < 2 || f_phi < 0 || f_ux < 0 ||
+      f_uy < 0 || nparts < 1 || nparts > ny || nimg > 65535)
     return LBFZ_NN_EINVAL;
   const long np = (long)nx * ny;
   const int fmax = f_phi > f_ux ? (f_phi > f_uy ? f_phi : f_uy) : (f_ux > f_uy ? f_ux : f_uy);
   if (img_stride < (long)(fmax + 1) * np) return LBFZ_NN_EINVAL;
-  hipLaunchKernelGGL(k_phi_div_sums, dim3(nimg), dim3(256), 0, (hipStream_t)stream, planes,
-                     img_stride, nx, ny, walls ? 1 : 0, f_phi, f_ux, f_uy, out);
+  hipLaunchKernelGGL(k_phi_div_parts, dim3(nparts, nimg), dim3(256), 0, (hipStream_t)stream,
+                     planes, img_stride, nx, ny, walls ? 1 : 0, f_phi, f_ux, f_uy, parts);
+  hipLaunchKernelGGL(k_sum_parts, dim3((nimg + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                     parts, nparts, nimg, out);
   HCHK();
 }
 

@@ -76,6 +76,8 @@ def lib() -> ctypes.CDLL:
         L.lbfz_strerror.argtypes = [ctypes.c_int]
         L.lbfz_strerror.restype = ctypes.c_char_p
         L.lbfz_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.lbfz_stream_planes.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_long,
+                                         vp]
         ip = ctypes.POINTER(ctypes.c_int32)
         dpp = ctypes.POINTER(dp)
         L.lbfz_batch_workspace_bytes.argtypes = [ctypes.c_int32, pp,
@@ -213,6 +215,13 @@ def lbfz_restart_fields(h, planes) -> None:
 def lbfz_stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int) -> None:
     _check(lib().lbfz_stream_copy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr),
                                   int(nbytes), ctypes.c_void_p(stream_ptr)), "lbfz_stream_copy")
+
+
+def lbfz_stream_planes(dst_ptr: int, src_ptr: int, nx: int, ny: int, plane_stride: int,
+                       stream_ptr: int) -> None:
+    _check(lib().lbfz_stream_planes(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), nx, ny,
+                                    int(plane_stride), ctypes.c_void_p(stream_ptr)),
+           "lbfz_stream_planes")
 
 
 def lbfz_sync(h):

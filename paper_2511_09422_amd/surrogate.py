@@ -94,7 +94,8 @@ def nnlib():
             "lbfz_nn_fill_u32": [vp, lg, u32, vp],
             "lbfz_nn_mse": [vp, i32, vp, lg, i32, vp, vp, vp, i32, vp, vp],
             "lbfz_nn_plane_sums": [vp, i32, lg, lg, vp, vp],
-            "lbfz_nn_phi_div_sums": [vp, i32, lg, i32, i32, i32, i32, i32, i32, vp, vp],
+            "lbfz_nn_phi_div_sums": [vp, i32, lg, i32, i32, i32, i32, i32, i32, vp, i32, vp,
+                                     vp],
             "lbfz_nn_pack_images": [vp, i32, lg, i32, i32, vp, vp, vp, i32, vp],
             "lbfz_nn_apply_images": [vp, i32, vp, i32, lg, i32, i32, vp, vp, vp, vp, lg, vp],
             "lbfz_nn_adam": [vp, vp, vp, vp, vp, lg, f32, f32, f32, f32, i32, vp],
@@ -466,6 +467,7 @@ class UNet:
 # data, training and screening
 
 STRIDE = 64      # LB steps spanned by one prediction
+PHI_DIV_PARTS = 16  # row sets per grid of the check's sum phi div u (blocks per grid)
 MASS_TOL = 1e-3  # screening: largest accepted phase-field mass residual
 
 
@@ -676,6 +678,7 @@ class Screener:
         self.nsb, self.nsa = self.n * NIN, self.n * NF
         self.sums = torch.zeros(self.nsb + self.nsa + 2 * self.n, dtype=torch.float64,
                                 device=net.dev)
+        self.parts = torch.zeros(self.n * PHI_DIV_PARTS, dtype=torch.float64, device=net.dev)
         self.levels = 0  # time levels recorded so far
         self.time = 0  # LB steps screened so far (the batch's own counter only
         # moves when some grid falls back to the LB)
@@ -721,10 +724,10 @@ class Screener:
         _ck(L.lbfz_nn_plane_sums(_p(self.hist), self.n * NIN, SS, SS, _p(sb), st), "plane_sums")
         _ck(L.lbfz_nn_plane_sums(_p(self.pred), self.n * NF, SS, SS, _p(sa), st), "plane_sums")
         walls = self.walls[0]
-        _ck(L.lbfz_nn_phi_div_sums(_p(cur), self.n, NIN * SS, S, S, walls, 0, 4, 5, _p(qb), st),
-            "phi_div_sums")
-        _ck(L.lbfz_nn_phi_div_sums(_p(self.pred), self.n, NF * SS, S, S, walls, 0, 4, 5, _p(qa),
-                                   st), "phi_div_sums")
+        _ck(L.lbfz_nn_phi_div_sums(_p(cur), self.n, NIN * SS, S, S, walls, 0, 4, 5,
+                                   _p(self.parts), PHI_DIV_PARTS, _p(qb), st), "phi_div_sums")
+        _ck(L.lbfz_nn_phi_div_sums(_p(self.pred), self.n, NF * SS, S, S, walls, 0, 4, 5,
+                                   _p(self.parts), PHI_DIV_PARTS, _p(qa), st), "phi_div_sums")
         host = sums.cpu().numpy()
         hb = host[:self.nsb].reshape(self.n, NIN)[:, NEXP:]
         ha = host[self.nsb:self.nsb + self.nsa].reshape(self.n, NF)

@@ -375,16 +375,22 @@ def test_phi_div_sums_against_cpu(nx, ny, walls, nimg):
     host[:, 4:6] *= 1e-3
     dev = torch.tensor(host.reshape(-1)).cuda()
     out = torch.zeros(nimg, dtype=torch.float64).cuda()
+    parts = torch.zeros(nimg * 16, dtype=torch.float64).cuda()
     L = sg.nnlib()
     st = torch.cuda.current_stream().cuda_stream
-    assert L.lbfz_nn_phi_div_sums(sg._p(dev), nimg, stride, nx, ny, walls, 0, 4, 5, sg._p(out),
-                                  st) == 0
-    got = out.cpu().numpy()
-    for g in range(nimg):
-        t = host[g, 0].astype(np.float64) * div_d2q9(host[g, 4], host[g, 5], walls)
-        assert abs(got[g] - t.sum()) <= 1e-12 * np.abs(t).sum(), (g, got[g], t.sum())
-    # argument checks: a stride too short for the highest plane, a bad side
+    for nparts in (1, 3, 16):
+        out.zero_()
+        assert L.lbfz_nn_phi_div_sums(sg._p(dev), nimg, stride, nx, ny, walls, 0, 4, 5,
+                                      sg._p(parts), nparts, sg._p(out), st) == 0
+        got = out.cpu().numpy()
+        for g in range(nimg):
+            t = host[g, 0].astype(np.float64) * div_d2q9(host[g, 4], host[g, 5], walls)
+            assert abs(got[g] - t.sum()) <= 1e-12 * np.abs(t).sum(), (nparts, g, got[g], t.sum())
+    # argument checks: a stride too short for the highest plane, a bad side,
+    # more parts than rows
     assert L.lbfz_nn_phi_div_sums(sg._p(dev), nimg, 5 * npx, nx, ny, walls, 0, 4, 5,
-                                  sg._p(out), st) == sg.LBFZ_NN_EINVAL
+                                  sg._p(parts), 4, sg._p(out), st) == sg.LBFZ_NN_EINVAL
     assert L.lbfz_nn_phi_div_sums(sg._p(dev), nimg, stride, 1, ny, walls, 0, 4, 5,
-                                  sg._p(out), st) == sg.LBFZ_NN_EINVAL
+                                  sg._p(parts), 4, sg._p(out), st) == sg.LBFZ_NN_EINVAL
+    assert L.lbfz_nn_phi_div_sums(sg._p(dev), nimg, stride, nx, ny, walls, 0, 4, 5,
+                                  sg._p(parts), ny + 1, sg._p(out), st) == sg.LBFZ_NN_EINVAL
