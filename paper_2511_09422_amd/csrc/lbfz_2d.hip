@@ -637,10 +637,12 @@ __global__ __launch_bounds__(Geo<TY>::NT) void k_step2d(KParams P, StepArgs A) {
 
 // Batched sweep: every (case, tile) of one step of many grids in one launch.
 // Work item e = (case, tile) comes from a table built on the host (in an
-// XCD-aware order); a block processes items blockIdx.x, blockIdx.x +
-// gridDim.x, ... (persistent when the grid is smaller than the work), with
-// the case's parameters and the buffers of step parity `slot` read from the
-// case table (wave-uniform: scalar loads).
+// XCD-aware order), with the case's parameters and the buffers of step
+// parity `slot` read from the case table (wave-uniform: scalar loads).  One
+// block per item, or a persistent grid whose blocks process items
+// blockIdx.x, blockIdx.x + gridDim.x, ...: the loop holds 37 more VGPRs (122
+// against 85: 4 waves per SIMD instead of 5), so the one-item form is a
+// kernel of its own.
 template <int ST, int TY>
 __global__ __launch_bounds__(Geo<TY>::NT) void k_step2d_batch(
     const BatchCase* __restrict__ cases, const int2* __restrict__ work, int nwork, int slot) {
@@ -652,17 +654,26 @@ __global__ __launch_bounds__(Geo<TY>::NT) void k_step2d_batch(
     __syncthreads();  // LDS is reused by the next item
   }
 }
+template <int ST, int TY>
+__global__ __launch_bounds__(Geo<TY>::NT) void k_step2d_batch1(
+    const BatchCase* __restrict__ cases, const int2* __restrict__ work, int slot) {
+  const int2 w = work[blockIdx.x];
+  const int c = __builtin_amdgcn_readfirstlane(w.x);
+  const int tile = __builtin_amdgcn_readfirstlane(w.y);
+  step2d_tile<false, ST, TY>(cases[c].P, cases[c].A[slot], tile);
+}
 
 // Fields of many grids in one launch: the dry pass (the step's closure, forces
-// and velocity, no collision) over the same (case, tile) items, the fields
-// selected by `mask` (bit k: field k of lbfz_fields) written to grid c's
-// slice dst + c * case_stride, one plane of N_c values per selected field in
-// the order of the bits.
+// and velocity, no collision) over the same (case, tile) items, one block per
+// item, the fields selected by `mask` (bit k: field k of lbfz_fields) written
+// to grid c's slice dst + c * case_stride, one plane of N_c values per
+// selected field in the order of the bits.
 template <int ST, int TY>
 __global__ __launch_bounds__(Geo<TY>::NT) void k_fields2d_batch(
-    const BatchCase* __restrict__ cases, const int2* __restrict__ work, int nwork, int slot,
+    const BatchCase* __restrict__ cases, const int2* __restrict__ work, int slot,
     float* __restrict__ dst, long case_stride, uint32_t mask) {
-  for (int e = blockIdx.x; e < nwork; e += gridDim.x) {
+  {
+    const int e = blockIdx.x;
     const int2 w = work[e];
     const int c = __builtin_amdgcn_readfirstlane(w.x);
     const int tile = __builtin_amdgcn_readfirstlane(w.y);
@@ -677,7 +688,6 @@ __global__ __launch_bounds__(Geo<TY>::NT) void k_fields2d_batch(
     }
     A.tot_part = nullptr;
     step2d_tile<true, ST, TY>(cases[c].P, A, tile);
-    __syncthreads();  // LDS is reused by the next item
   }
 }
 
@@ -940,8 +950,12 @@ static void launch_step2d_st(const KParams& P, const StepArgs& A, bool dry, hipS
 template <int ST, int TY>
 static void launch_batch_st(const BatchCase* cases, const int2* work, int nwork, int grid,
                             int slot, hipStream_t st) {
-  hipLaunchKernelGGL((k_step2d_batch<ST, TY>), dim3(grid), dim3(Geo<TY>::NT), 0, st, cases,
-                     work, nwork, slot);
+  if (grid >= nwork)
+    hipLaunchKernelGGL((k_step2d_batch1<ST, TY>), dim3(nwork), dim3(Geo<TY>::NT), 0, st, cases,
+                       work, slot);
+  else
+    hipLaunchKernelGGL((k_step2d_batch<ST, TY>), dim3(grid), dim3(Geo<TY>::NT), 0, st, cases,
+                       work, nwork, slot);
 }
 
 hipError_t launch_step2d(const KParams& P, int storage, const StepArgs& A, bool dry,
@@ -974,7 +988,7 @@ template <int ST, int TY>
 static void launch_fields_batch_st(const BatchCase* cases, const int2* work, int nwork, int slot,
                                    float* dst, long case_stride, uint32_t mask, hipStream_t st) {
   hipLaunchKernelGGL((k_fields2d_batch<ST, TY>), dim3(nwork), dim3(Geo<TY>::NT), 0, st, cases,
-                     work, nwork, slot, dst, case_stride, mask);
+                     work, slot, dst, case_stride, mask);
 }
 
 hipError_t launch_fields2d_batch(int storage, int ty, const BatchCase* cases, const int2* work,
