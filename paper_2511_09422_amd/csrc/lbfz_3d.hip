@@ -567,18 +567,18 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
       }
       const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
       const float uFt = u[0] * Ft[0] + u[1] * Ft[1] + u[2] * Ft[2];
-      // G_i (Sec. 3.2); its rest component is the complement of the moving ones
-      // so that sum G = S exactly.  The moving ones are recomputed where they
-      // are used, to keep no array of them live.
+      // G_i (Sec. 3.2), computed where it is used, to keep no array of them
+      // live.  The rest component G_0 = w_0 (S - u.Ft / cs^2): with sum_i w_i c_i
+      // = 0 and sum_i w_i c_i c_i = cs^2 I it is what the moving ones leave of
+      // S (sum G = S), without evaluating them twice (the 16-bit collision
+      // is bound by instruction issue)
       auto Gi = [&](int i) -> float {
         const float cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
         const float cFt = CX[i] * Ft[0] + CY[i] * Ft[1] + CZ[i] * Ft[2];
         const float cFf = CX[i] * Ff[0] + CY[i] * Ff[1] + CZ[i] * Ff[2];
         return W19[i] * (S_ + kInvCs2 * cFf + 9.0f * (cu * cFt) - 3.0f * uFt);
       };
-      float G0 = S_;
-#pragma unroll
-      for (int i = 1; i < 19; ++i) G0 -= Gi(i);
+      const float G0 = W19[0] * (S_ - 3.0f * uFt);
       float sum_nz = 0.f;
 #pragma unroll
       for (int i = 1; i < 19; ++i) sum_nz += g[i];
