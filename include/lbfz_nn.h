@@ -199,6 +199,18 @@ int lbfz_nn_phi_div_sums(const float* planes, int nimg, long img_stride, int nx,
                          int walls, int f_phi, int f_ux, int f_uy, double* parts, int nparts,
                          double* out, void* stream);
 
+/* In place, plane `plane` of image i (n FP32 values at planes + i *
+ * img_stride + plane * n) times n / sums[i] (inverse = 0: the values over
+ * their mean, with sums[i] the plane's sum) or sums[i] / n (inverse != 0:
+ * back), for i < nimg.  The surrogate keeps a grid's solute over its mean
+ * (the step conserves the solute, Sec. 3.4, so the mean is the grid's own
+ * constant): the network then sees every grid's solute on one scale.
+ * Device pointers (sums: nimg doubles).  EINVAL for null pointers, nimg < 1,
+ * n < 1, a negative plane or, with more than one image, img_stride shorter
+ * than the planes up to `plane`. */
+int lbfz_nn_scale_planes(float* planes, int nimg, long img_stride, int plane, long n,
+                         const double* sums, int inverse, void* stream);
+
 /* Wt[c][t][n] = W[n][t][c] (weights of the data-gradient convolution). */
 int lbfz_nn_transpose_w(const void* w, int N, int taps, int C, void* wt, void* stream);
 

@@ -1085,6 +1085,22 @@ __global__ void k_sum_parts(const double* __restrict__ part, int nparts, int nim
   out[g] = s;
 }
 
+// Plane `plane` of image i (at planes + i * img_stride + plane * n) times
+// n / sums[i] (inverse = 0: the values over their mean) or sums[i] / n
+// (inverse = 1: back), in place.
+__global__ void k_scale_planes(float* __restrict__ planes, int nimg, long img_stride, int plane,
+                               long n, const double* __restrict__ sums, int inverse) {
+  const long total = (long)nimg * n;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total;
+       k += (long)gridDim.x * blockDim.x) {
+    const long i = k / n, j = k - i * n;
+    const double s = sums[i];
+    const float f = (float)(inverse ? s / (double)n : (double)n / s);
+    float* v = planes + i * img_stride + (long)plane * n + j;
+    *v = *v * f;
+  }
+}
+
 // Adam on FP32 master weights (bias-corrected), then the bf16 copy.
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, bf16* __restrict__ wb, long n, float lr, float b1,
@@ -1560,6 +1576,17 @@ int lbfz_nn_phi_div_sums(const float* planes, int nimg, long img_stride, int nx,
                      planes, img_stride, nx, ny, walls ? 1 : 0, f_phi, f_ux, f_uy, parts);
   hipLaunchKernelGGL(k_sum_parts, dim3((nimg + 255) / 256), dim3(256), 0, (hipStream_t)stream,
                      parts, nparts, nimg, out);
+  HCHK();
+}
+
+int lbfz_nn_scale_planes(float* planes, int nimg, long img_stride, int plane, long n,
+                         const double* sums, int inverse, void* stream) {
+  if (!planes || !sums || nimg <= 0 || n <= 0 || plane < 0 ||
+      (nimg > 1 && img_stride < (long)(plane + 1) * n))
+    return LBFZ_NN_EINVAL;
+  hipLaunchKernelGGL(k_scale_planes, dim3(grid_for((long)nimg * n)), dim3(256), 0,
+                     (hipStream_t)stream, planes, nimg, img_stride, plane, n, sums,
+                     inverse ? 1 : 0);
   HCHK();
 }
 

@@ -96,6 +96,7 @@ def nnlib():
             "lbfz_nn_plane_sums": [vp, i32, lg, lg, vp, vp],
             "lbfz_nn_phi_div_sums": [vp, i32, lg, i32, i32, i32, i32, i32, i32, vp, i32, vp,
                                      vp],
+            "lbfz_nn_scale_planes": [vp, i32, lg, i32, lg, vp, i32, vp],
             "lbfz_nn_pack_images": [vp, i32, lg, i32, i32, vp, vp, vp, i32, vp],
             "lbfz_nn_apply_images": [vp, i32, vp, i32, lg, i32, i32, vp, vp, vp, vp, lg, vp],
             "lbfz_nn_adam": [vp, vp, vp, vp, vp, lg, f32, f32, f32, f32, i32, vp],
@@ -467,6 +468,7 @@ class UNet:
 # data, training and screening
 
 STRIDE = 64      # LB steps spanned by one prediction
+SOLUTE_PLANE = 3  # C: the network sees a grid's solute over its mean
 PHI_DIV_PARTS = 16  # row sets per grid of the check's sum phi div u (blocks per grid)
 MASS_TOL = 1e-3  # screening: largest accepted phase-field mass residual
 
@@ -475,9 +477,11 @@ def generate_snapshots(case_ids, side: int, nsnap: int, device: int = 0, storage
     """Run the LB step (batched, on the GPU) for the sweep grids case_ids with
     their side replaced by `side`, and keep the NEXP fields every STRIDE
     steps: a device tensor [ncases][nsnap][NEXP][side][side] FP32 (snapshot 0
-    = the initial state).  Snapshots s - 1 and s of a grid are adjacent in
-    memory: together they are the network input of time level s.  Returns
-    (snapshots, params of each grid)."""
+    = the initial state), with the solute of every snapshot over its own mean
+    (SOLUTE_PLANE: the network's scale for C; the LB conserves the solute, so
+    the mean is the grid's constant).  Snapshots s - 1 and s of a grid are
+    adjacent in memory: together they are the network input of time level s.
+    Returns (snapshots, params of each grid)."""
     import torch
     from .workloads import sweep_case
     cases = [sweep_case(k, side=side) for k in case_ids]
@@ -488,11 +492,18 @@ def generate_snapshots(case_ids, side: int, nsnap: int, device: int = 0, storage
         if s:
             b.step(STRIDE)
         b.fields_all_to_device(NEXP, snaps[:, s], nsnap * NEXP * side * side)
-    torch.cuda.synchronize()
     bad = sum(b.totals(i)["nonfinite"] for i in range(len(cases)))
     b.close()
     if bad:
         raise RuntimeError("non-finite LB state while generating snapshots")
+    L, SS, nimg = nnlib(), side * side, len(cases) * nsnap
+    sums = torch.zeros(nimg, dtype=torch.float64, device=snaps.device)
+    st = ctypes.c_void_p(torch.cuda.current_stream(snaps.device).cuda_stream)
+    _ck(L.lbfz_nn_plane_sums(_p(snaps[0, 0, SOLUTE_PLANE]), nimg, SS, NEXP * SS, _p(sums), st),
+        "plane_sums")
+    _ck(L.lbfz_nn_scale_planes(_p(snaps), nimg, NEXP * SS, SOLUTE_PLANE, SS, _p(sums), 0, st),
+        "scale_planes")
+    torch.cuda.synchronize()
     return snaps, [c[0] for c in cases]
 
 
@@ -581,10 +592,8 @@ def predict(net: UNet, snaps, norm: Normaliser, pairs, out):
 
 # ---------------------------------------------------------------- screening
 # screening: largest accepted relative drift of sum C (None: not checked).  The
-# LB conserves the solute to FP32 rounding (relative drift about 1e-7 over a
-# stride), so the check rejects no LB state; the predictions it rejects are
-# mostly those of grids holding little solute, whose C the network gets
-# least right relative to its size
+# LB conserves the solute to FP32 rounding (relative drift about 1e-8 over a
+# stride), so the check rejects no LB state
 SOLUTE_TOL = 1e-3
 
 
@@ -651,7 +660,9 @@ class Screener:
     levels: observe() records the grids' state, and a prediction needs the
     state of STRIDE steps earlier recorded first (observe(), then STRIDE
     steps of the batch, then predict() or stride()).  net: a UNet of batch >=
-    the number of grids and side S."""
+    the number of grids and side S.  The recorded levels hold each grid's
+    solute over its mean (solute_before: the current level's sums of C);
+    predictions are on the grids' own scale."""
 
     def __init__(self, net: UNet, norm: Normaliser, batch, mass_tol: float = MASS_TOL,
                  solute_tol: float = SOLUTE_TOL):
@@ -676,8 +687,10 @@ class Screener:
         # now and predicted, in one buffer so that the check needs one
         # device-to-host copy
         self.nsb, self.nsa = self.n * NIN, self.n * NF
-        self.sums = torch.zeros(self.nsb + self.nsa + 2 * self.n, dtype=torch.float64,
+        # ... and the current level's solute sum (the scale of its C plane)
+        self.sums = torch.zeros(self.nsb + self.nsa + 3 * self.n, dtype=torch.float64,
                                 device=net.dev)
+        self.csum = self.sums[self.nsb + self.nsa + 2 * self.n:]
         self.parts = torch.zeros(self.n * PHI_DIV_PARTS, dtype=torch.float64, device=net.dev)
         self.levels = 0  # time levels recorded so far
         self.time = 0  # LB steps screened so far (the batch's own counter only
@@ -686,11 +699,17 @@ class Screener:
 
     def observe(self):
         """Record the grids' current state as the newer time level (the
-        previous newer one becomes the older)."""
+        previous newer one becomes the older), its solute over its mean."""
         SS = self.S * self.S
+        L, st = nnlib(), self.net.st
         if self.levels:
             self.hist[:, :NEXP].copy_(self.hist[:, NEXP:])
         self.batch.fields_all_to_device(NEXP, self.before, NIN * SS)
+        cur = self.hist[0, NEXP]
+        _ck(L.lbfz_nn_plane_sums(_p(self.hist[0, NEXP + SOLUTE_PLANE]), self.n, SS, NIN * SS,
+                                 _p(self.csum), st), "plane_sums")
+        _ck(L.lbfz_nn_scale_planes(_p(cur), self.n, NIN * SS, SOLUTE_PLANE, SS, _p(self.csum), 0,
+                                   st), "scale_planes")
         self.levels += 1
 
     def predict(self):
@@ -716,6 +735,9 @@ class Screener:
                                        S, _p(self.norm.d_shift), _p(self.norm.d_scale),
                                        _p(self.norm.resid), _p(self.pred), NF * SS, st),
                 "apply_images")
+        # the prediction's solute back on its grid's scale
+        _ck(L.lbfz_nn_scale_planes(_p(self.pred), self.n, NF * SS, SOLUTE_PLANE, SS,
+                                   _p(self.csum), 1, st), "scale_planes")
         sums = self.sums
         sb = sums[:self.nsb]
         sa = sums[self.nsb:self.nsb + self.nsa]
@@ -729,9 +751,11 @@ class Screener:
         _ck(L.lbfz_nn_phi_div_sums(_p(self.pred), self.n, NF * SS, S, S, walls, 0, 4, 5,
                                    _p(self.parts), PHI_DIV_PARTS, _p(qa), st), "phi_div_sums")
         host = sums.cpu().numpy()
-        hb = host[:self.nsb].reshape(self.n, NIN)[:, NEXP:]
+        hb = host[:self.nsb].reshape(self.n, NIN)[:, NEXP:].copy()
         ha = host[self.nsb:self.nsb + self.nsa].reshape(self.n, NF)
-        q = host[self.nsb + self.nsa:]
+        q = host[self.nsb + self.nsa:self.nsb + self.nsa + 2 * self.n]
+        hb[:, SOLUTE_PLANE] = host[self.nsb + self.nsa + 2 * self.n:]
+        self.solute_before = hb[:, SOLUTE_PLANE].copy()
         return check_all(hb, ha, SS, q[:self.n], q[self.n:], self.mass_tol, self.solute_tol)
 
     def stride(self):

@@ -66,6 +66,9 @@ def test_screening_against_the_lb_on_held_out_seeds():
     for _ in range(NSTR):
         res = scr.predict()
         before = scr.before.cpu().numpy()
+        # the recorded level holds the solute over its mean: back to the
+        # grid's scale
+        before[:, sg.SOLUTE_PLANE] *= (scr.solute_before / (S * S))[:, None, None]
         pred = scr.pred.cpu().numpy()
         ref.step(sg.STRIDE)
         for i in range(NG):

@@ -394,3 +394,37 @@ def test_phi_div_sums_against_cpu(nx, ny, walls, nimg):
                                   sg._p(parts), 4, sg._p(out), st) == sg.LBFZ_NN_EINVAL
     assert L.lbfz_nn_phi_div_sums(sg._p(dev), nimg, stride, nx, ny, walls, 0, 4, 5,
                                   sg._p(parts), ny + 1, sg._p(out), st) == sg.LBFZ_NN_EINVAL
+
+
+@pytest.mark.parametrize("nimg,n,stride,plane", [(3, 1000, 4100, 2), (5, 4096, 4 * 4096, 3)])
+def test_scale_planes_by_grid_sums(nimg, n, stride, plane):
+    """lbfz_nn_scale_planes (a grid's solute over its mean, and back): plane
+    `plane` of every image times n / sums[i], then times sums[i] / n, each
+    factor formed in FP64 and applied in FP32 -- equal to that arithmetic bit
+    for bit; the other planes untouched."""
+    import torch
+    from paper_2511_09422_amd import surrogate as sg
+    rng = np.random.default_rng(nimg + n)
+    host = rng.uniform(0.01, 0.1, size=nimg * stride).astype(np.float32)
+    sums = np.array([host[i * stride + plane * n:i * stride + (plane + 1) * n].astype(np.float64).sum()
+                     for i in range(nimg)])
+    dev = torch.tensor(host).cuda()
+    dsum = torch.tensor(sums).cuda()
+    L = sg.nnlib()
+    st = torch.cuda.current_stream().cuda_stream
+    assert L.lbfz_nn_scale_planes(sg._p(dev), nimg, stride, plane, n, sg._p(dsum), 0, st) == 0
+    got = dev.cpu().numpy()
+    want = host.copy()
+    for i in range(nimg):
+        sl = slice(i * stride + plane * n, i * stride + (plane + 1) * n)
+        want[sl] = host[sl] * np.float32(n / sums[i])
+    assert np.array_equal(got, want)
+    assert L.lbfz_nn_scale_planes(sg._p(dev), nimg, stride, plane, n, sg._p(dsum), 1, st) == 0
+    back = dev.cpu().numpy()
+    for i in range(nimg):
+        sl = slice(i * stride + plane * n, i * stride + (plane + 1) * n)
+        want[sl] = want[sl] * np.float32(sums[i] / n)
+    assert np.array_equal(back, want)
+    assert np.abs(back - host).max() <= 1e-6 * np.abs(host).max()
+    assert L.lbfz_nn_scale_planes(sg._p(dev), nimg, plane * n, plane, n, sg._p(dsum), 0,
+                                  st) == sg.LBFZ_NN_EINVAL
