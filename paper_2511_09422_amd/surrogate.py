@@ -683,11 +683,11 @@ class Screener:
         self.hist = torch.zeros((self.n, NIN, S, S), **f)
         self.before = self.hist[:, NEXP:]          # the current level (a view)
         self.pred = torch.zeros((self.n, NF, S, S), **f)
-        # per-grid sums of both levels and of the prediction, and sum phi div u
-        # now and predicted, in one buffer so that the check needs one
-        # device-to-host copy
-        self.nsb, self.nsa = self.n * NIN, self.n * NF
-        # ... and the current level's solute sum (the scale of its C plane)
+        # per-grid sums in one buffer, so that the check needs one
+        # device-to-host copy: sum phi of the current level, every field of
+        # the prediction, sum phi div u now and predicted, and the current
+        # level's solute sum (the scale of its C plane)
+        self.nsb, self.nsa = self.n, self.n * NF
         self.sums = torch.zeros(self.nsb + self.nsa + 3 * self.n, dtype=torch.float64,
                                 device=net.dev)
         self.csum = self.sums[self.nsb + self.nsa + 2 * self.n:]
@@ -742,8 +742,8 @@ class Screener:
         sb = sums[:self.nsb]
         sa = sums[self.nsb:self.nsb + self.nsa]
         qb = sums[self.nsb + self.nsa:self.nsb + self.nsa + self.n]
-        qa = sums[self.nsb + self.nsa + self.n:]
-        _ck(L.lbfz_nn_plane_sums(_p(self.hist), self.n * NIN, SS, SS, _p(sb), st), "plane_sums")
+        qa = sums[self.nsb + self.nsa + self.n:self.nsb + self.nsa + 2 * self.n]
+        _ck(L.lbfz_nn_plane_sums(_p(cur), self.n, SS, NIN * SS, _p(sb), st), "plane_sums")
         _ck(L.lbfz_nn_plane_sums(_p(self.pred), self.n * NF, SS, SS, _p(sa), st), "plane_sums")
         walls = self.walls[0]
         _ck(L.lbfz_nn_phi_div_sums(_p(cur), self.n, NIN * SS, S, S, walls, 0, 4, 5,
@@ -751,10 +751,12 @@ class Screener:
         _ck(L.lbfz_nn_phi_div_sums(_p(self.pred), self.n, NF * SS, S, S, walls, 0, 4, 5,
                                    _p(self.parts), PHI_DIV_PARTS, _p(qa), st), "phi_div_sums")
         host = sums.cpu().numpy()
-        hb = host[:self.nsb].reshape(self.n, NIN)[:, NEXP:].copy()
+        # the check reads sum phi and sum C of the state before the stride
+        hb = np.zeros((self.n, NF))
+        hb[:, 0] = host[:self.nsb]
+        hb[:, SOLUTE_PLANE] = host[self.nsb + self.nsa + 2 * self.n:]
         ha = host[self.nsb:self.nsb + self.nsa].reshape(self.n, NF)
         q = host[self.nsb + self.nsa:self.nsb + self.nsa + 2 * self.n]
-        hb[:, SOLUTE_PLANE] = host[self.nsb + self.nsa + 2 * self.n:]
         self.solute_before = hb[:, SOLUTE_PLANE].copy()
         return check_all(hb, ha, SS, q[:self.n], q[self.n:], self.mass_tol, self.solute_tol)
 
