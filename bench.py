@@ -521,7 +521,7 @@ def main():
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

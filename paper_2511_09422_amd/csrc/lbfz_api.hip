@@ -568,7 +568,7 @@ const char* lbfz_strerror(int code) {
     case LBFZ_ENOMEM: return "device workspace too small or misaligned";
     case LBFZ_EHIP: return "HIP runtime error";
     case LBFZ_ENONFINITE: return "non-finite input field";
-    case LBFZ_EUNSUPPORTED: return "configuration not supported by this build";
+    case LBFZ_EUNSUPPORTED: return "configuration not supported by this library";
     default: return "unknown error";
   }
 }

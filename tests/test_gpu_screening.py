@@ -1,5 +1,5 @@
 """The learned surrogate against the plain LB on held-out sweep seeds (its
-use: screening a sweep 64 steps at a time, with the LB as fallback and judge).
+use: screening a sweep 64 steps at a time, with the LB as fallback and referee).
 
 A network trained on the GPU by the project's own kernels (12000 iterations
 of batch 8 on the LB snapshot pairs of 160 sweep seeds, under a minute) reads
