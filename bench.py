@@ -229,6 +229,51 @@ def time_copy(nbytes: int, reps: int = 20) -> dict:
             "runtime_copy_us": ms_rt * 1e3, "runtime_copy_GBs": 8 * n / (ms_rt * 1e-3) / 1e9}
 
 
+def time_pattern3d(m: int, reps: int = 10) -> dict:
+    """The 3D FP32 step's memory pattern without its arithmetic, launch by
+    launch (lbfz_stream_planes3d on an m^3 grid: the closure launch's 22
+    planes in and 5 out, the collision launch's 50 in and 42 out, the
+    populations pushed to their D3Q19 targets), timed with HIP events on its
+    stream: what the two launches' access pattern can reach."""
+    import torch
+    from paper_2511_09422_amd.lbfz import lbfz_stream_planes3d
+    N = m * m * m
+    ps = (N + 63) // 64 * 64 + 1088
+    a = torch.ones(50 * ps, dtype=torch.float32, device="cuda")
+    b = torch.zeros(42 * ps, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    out = {}
+    for name, (nr, nw) in (("closure", (22, 5)), ("collision", (50, 42))):
+        fn = lambda: lbfz_stream_planes3d(b.data_ptr(), a.data_ptr(), m, m, m, ps, nr, nw,
+                                          st.cuda_stream)
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(st)
+        for _ in range(reps):
+            fn()
+        ev1.record(st)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        nbytes = (nr + nw) * 4 * N
+        out[name] = {"planes_in": nr, "planes_out": nw, "bytes": nbytes, "us": round(ms * 1e3, 2),
+                     "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    ok = bool(torch.equal(b[:N], a[:N]))
+    del a, b
+    torch.cuda.empty_cache()
+    if not ok:
+        print("bench: the 3D plane pattern did not move its source", file=sys.stderr)
+        sys.exit(1)
+    us = out["closure"]["us"] + out["collision"]["us"]
+    nbytes = out["closure"]["bytes"] + out["collision"]["bytes"]
+    out.update({"us": round(us, 2), "bytes_per_node": nbytes // N,
+                "GB/s": round(nbytes / (us * 1e-6) / 1e9, 1),
+                "frac_of_peak": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)})
+    return out
+
+
 def time_pattern(n: int, reps: int = 20) -> dict:
     """The step's own memory pattern without its arithmetic (lbfz_stream_planes:
     30 FP32 planes of an n x n grid read at each node and written to the rows
@@ -586,6 +631,12 @@ def main():
         droplet3d = {"workload": f"3D droplet freezing {m}^3, R={m // 4}, obstacle radius "
                                  f"{12 * m // 256}, D3Q19+3xD3Q7, FP32 arithmetic",
                      "steps": args.steps3d, "forms": forms3}
+        pat3 = time_pattern3d(m)
+        if "f32" in forms3:
+            pat3["step_vs_pattern"] = round(pat3["us"] * 1e-3 / forms3["f32"]["ms_per_step"], 4)
+        droplet3d["step_pattern"] = dict(kernel="lbfz_stream_planes3d", **pat3)
+        print(f"bench: 3D plane pattern {pat3['us']:.1f} us ({pat3['GB/s']:.0f} GB/s, "
+              f"{pat3['bytes_per_node']} B/node)", file=sys.stderr, flush=True)
         if not args.no_error_64:
             droplet3d["error_vs_oracle_64"] = copy64_errors([args.storage] + forms)
             print("bench: 3D 64^3 copy, 5000 steps, error vs oracle: " +

@@ -269,6 +269,21 @@ int lbfz_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
 int lbfz_stream_planes(float* dst, const float* src, int nx, int ny, long plane_stride,
                        void* stream);
 
+/* The memory pattern of one launch of the 3D FP32 step of an nx x ny x nz
+ * grid without its arithmetic: for every node, planes 0 .. nread - 1 of src
+ * (plane k at k * plane_stride floats) are read at the node, and planes 0 ..
+ * nwrite - 1 of dst are written: plane k < 38 at the node displaced by D3Q19
+ * direction k mod 19 (the step pushes its populations to the nodes they
+ * stream to; x, y and z periodic here), planes from 38 on in place, each
+ * with the value read from the same plane.  (nread, nwrite) is one of the
+ * step's two launches: (22, 5) for the closure launch, (50, 42) for the
+ * collision launch.  Device buffers of nread and nwrite planes, not
+ * overlapping; asynchronous on `stream`.  Errors: LBFZ_EINVAL (NULL pointer,
+ * empty grid, another (nread, nwrite), plane_stride below nx * ny * nz),
+ * LBFZ_EHIP. */
+int lbfz_stream_planes3d(float* dst, const float* src, int nx, int ny, int nz, long plane_stride,
+                         int nread, int nwrite, void* stream);
+
 /* Blocks until the handle's stream is idle. */
 int lbfz_sync(lbfz_handle* h);
 

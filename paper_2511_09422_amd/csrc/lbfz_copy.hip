@@ -50,7 +50,71 @@ __global__ __launch_bounds__(256) void k_stream_planes(const float* __restrict__
     __builtin_nontemporal_store(v[k], dst + k * ps + rows[k % 3]);
 }
 
+// The memory pattern of one launch of the 3D FP32 step without its
+// arithmetic: each node reads nread planes at its own position and writes
+// nwrite planes, plane k < 38 displaced by D3Q19 direction k mod 19 (the
+// step pushes its 38 moving and rest populations to the nodes they stream
+// to; x, y, z periodic here), the others in place.  Default cache policy,
+// as the 3D step uses.  The closure launch moves 22 planes in (f, h, l and
+// the previous velocity) and 5 out; the collision launch about 50 in and 42
+// out.
+constexpr int CX19[19] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0};
+constexpr int CY19[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1};
+constexpr int CZ19[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+// NR, NW compile-time: every load of a lane is issued before its first store,
+// with no branch between them.  The planes read but not written are summed
+// into a store guarded by `never` (NaN from the host, so it is never taken)
+// that keeps their loads in the kernel.
+template <int NR, int NW>
+__global__ __launch_bounds__(256) void k_stream_planes3d(const float* __restrict__ src,
+                                                         float* __restrict__ dst, int nx, int ny,
+                                                         int nz, long ps, float never) {
+  static_assert(NW <= NR, "each written plane is a read one");
+  const long N = (long)nx * ny * nz;
+  const long n = (long)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const int x = (int)(n % nx);
+  const long r = n / nx;
+  const int y = (int)(r % ny), z = (int)(r / ny);
+  float v[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) v[k] = src[k * ps + n];
+  const long xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+  const long ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+  const long zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    long o = n;
+    if (k < 38) {
+      const int d = k % 19;
+      o = (zs[CZ19[d] + 1] * ny + ys[CY19[d] + 1]) * nx + xs[CX19[d] + 1];
+    }
+    dst[k * ps + o] = v[k];
+  }
+  float rest = 0.0f;
+#pragma unroll
+  for (int k = NW; k < NR; ++k) rest += v[k];
+  if (rest == never) dst[n] = rest;
+}
+
 }  // namespace
+
+extern "C" int lbfz_stream_planes3d(float* dst, const float* src, int nx, int ny, int nz,
+                                    long plane_stride, int nread, int nwrite, void* stream) {
+  const bool closure = nread == 22 && nwrite == 5, collision = nread == 50 && nwrite == 42;
+  if (!dst || !src || nx < 1 || ny < 1 || nz < 1 || !(closure || collision) ||
+      plane_stride < (long)nx * ny * nz)
+    return LBFZ_EINVAL;
+  const long n = (long)nx * ny * nz;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (closure)
+    hipLaunchKernelGGL((k_stream_planes3d<22, 5>), grid, dim3(256), 0, (hipStream_t)stream, src,
+                       dst, nx, ny, nz, plane_stride, __builtin_nanf(""));
+  else
+    hipLaunchKernelGGL((k_stream_planes3d<50, 42>), grid, dim3(256), 0, (hipStream_t)stream, src,
+                       dst, nx, ny, nz, plane_stride, __builtin_nanf(""));
+  return hipGetLastError() == hipSuccess ? LBFZ_OK : LBFZ_EHIP;
+}
 
 extern "C" int lbfz_stream_planes(float* dst, const float* src, int nx, int ny, long plane_stride,
                                   void* stream) {

@@ -78,6 +78,9 @@ def lib() -> ctypes.CDLL:
         L.lbfz_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.lbfz_stream_planes.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_long,
                                          vp]
+        L.lbfz_stream_planes3d.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_long, ctypes.c_int32,
+                                           ctypes.c_int32, vp]
         ip = ctypes.POINTER(ctypes.c_int32)
         dpp = ctypes.POINTER(dp)
         L.lbfz_batch_workspace_bytes.argtypes = [ctypes.c_int32, pp,
@@ -222,6 +225,13 @@ def lbfz_stream_planes(dst_ptr: int, src_ptr: int, nx: int, ny: int, plane_strid
     _check(lib().lbfz_stream_planes(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), nx, ny,
                                     int(plane_stride), ctypes.c_void_p(stream_ptr)),
            "lbfz_stream_planes")
+
+
+def lbfz_stream_planes3d(dst_ptr: int, src_ptr: int, nx: int, ny: int, nz: int,
+                         plane_stride: int, nread: int, nwrite: int, stream_ptr: int) -> None:
+    _check(lib().lbfz_stream_planes3d(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), nx, ny,
+                                      nz, int(plane_stride), nread, nwrite,
+                                      ctypes.c_void_p(stream_ptr)), "lbfz_stream_planes3d")
 
 
 def lbfz_sync(h):
