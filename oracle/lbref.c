@@ -92,6 +92,29 @@ static void lat_init(lat_t* L, int dim, int flow) {
       for (int i = 1; i < 7; ++i) L->w[i] = 1.0 / 6.0;
     }
   }
+#ifdef LBREF_REST_WEIGHT_COMPLEMENT
+  /* Test build only (with the single-precision variant): the rest weight is
+   * the complement of the moving ones in the build's own arithmetic, so that
+   * the weights sum to one there.  Rounded to FP32, 1/3, 1/6, 1/9, 1/36 sum
+   * to 1 + O(1e-8); the equilibria then create or destroy mass at that rate
+   * every step, which is most of how far an FP32 evaluation drifts from the
+   * FP64 one.  A lattice without a rest weight (D3Q7) is left as it is. */
+  if (L->w[0] != 0.0) {
+    /* 1 - m1 w1 - m2 w2 over the distinct moving weights (m their counts):
+     * exact in FP32 for D2Q5 (1 - 4 / 6 by Sterbenz) */
+    double rest = 1.0;
+    for (int i = 1; i < L->q; ++i) {
+      int first = 1, m = 0;
+      for (int j = 1; j < i; ++j)
+        if (L->w[j] == L->w[i]) first = 0;
+      if (!first) continue;
+      for (int j = 1; j < L->q; ++j)
+        if (L->w[j] == L->w[i]) ++m;
+      rest -= m * L->w[i];
+    }
+    L->w[0] = rest;
+  }
+#endif
   for (int i = 0; i < L->q; ++i)
     for (int j = 0; j < L->q; ++j)
       if (L->c[j][0] == -L->c[i][0] && L->c[j][1] == -L->c[i][1] &&

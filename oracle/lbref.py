@@ -47,9 +47,15 @@ class LbrefParamsSingle(ctypes.Structure):
 # reading (the interface normal); "single" is the same source with every
 # double made a float (and single-precision constants), the scheme evaluated
 # in FP32 arithmetic and storage, as a measure of what FP32 alone does to a
-# trajectory.
+# trajectory; "single_cw" the same with each rest weight taken as the FP32
+# complement of the moving weights (they then sum to one in FP32, as the GPU
+# kernels' rest equilibria, the complements of the moving ones, do).
 VARIANTS = {"hard_cutoff": ["-DLBREF_HARD_NORMAL_CUTOFF"],
-            "single": ["-fsingle-precision-constant"]}
+            "single": ["-fsingle-precision-constant"],
+            "single_cw": ["-fsingle-precision-constant", "-DLBREF_REST_WEIGHT_COMPLEMENT"]}
+
+
+SINGLE = ("single", "single_cw")   # the FP32 builds (float ABI)
 
 
 def _lib_path(variant=None) -> str:
@@ -66,7 +72,7 @@ def build(force: bool = False, variant=None) -> str:
     if force or not os.path.exists(path) or (os.path.getmtime(path) < os.path.getmtime(src)):
         tmp = path + ".tmp"
         work = None
-        if variant == "single":
+        if variant in SINGLE:
             # the same source with double -> float, built in a scratch folder
             work = tempfile.mkdtemp(prefix="lbref_single_")
             for name in ("lbref.c", "lbref.h"):
@@ -97,7 +103,7 @@ def lib(variant=None):
         if variant is not None or not os.path.exists(path):
             build(variant=variant)
         L = ctypes.CDLL(path)
-        single = variant == "single"
+        single = variant in SINGLE
         dp = ctypes.POINTER(ctypes.c_float if single else (ctypes.c_float if single else ctypes.c_double))
         pp = ctypes.POINTER(LbrefParamsSingle if single else LbrefParams)
         L.lbref_create.argtypes = [pp, dp, dp, dp, ctypes.c_void_p, ctypes.c_void_p]
@@ -157,9 +163,9 @@ class Oracle:
 
     def __init__(self, cfg: dict, phi, T, C, mask=None, threads: int = 1, variant=None):
         self._L = lib(variant)
-        self._ft = np.float32 if variant == "single" else np.float64
+        self._ft = np.float32 if variant in SINGLE else np.float64
         self.cfg = dict(cfg)
-        self.P = make_params(cfg, threads, single=variant == "single")
+        self.P = make_params(cfg, threads, single=variant in SINGLE)
         self.shape = (self.P.nz, self.P.ny, self.P.nx) if self.P.dim == 3 else (self.P.ny, self.P.nx)
         self.N = self.P.nx * self.P.ny * self.P.nz
         phi = np.ascontiguousarray(phi, dtype=self._ft).reshape(-1)

@@ -327,19 +327,26 @@ def test_strict_trajectory_parity(case):
     amplification of rounding:
 
     * after 300 steps every field within 1e-4 relative L-infinity;
-    * after 1000 steps every field within the deviation of the oracle's own
-      single-precision build (the same source with every double a float)
-      from the FP64 oracle -- what evaluating this scheme in FP32 does to the
-      trajectory by itself (measured: 4e-4 on phi, 1.7e-3 on u in the
-      freezing case; the GPU path stays 2-10 times closer).  A fixed 1e-4 at
-      1000 steps is out of reach of FP32 arithmetic here: the FP64 oracle
-      with its state rounded to FP32 every step stays within 1e-5, but the
-      single-precision evaluation of the same steps drifts by 4e-4 and more."""
+    * after 1000 steps every field within 1e-4, or twice the deviation from
+      the FP64 oracle of the oracle's own FP32 build with rest weights that
+      complement the moving ones (variant "single_cw", the FP32 evaluation
+      of this scheme that the kernels' complementary rest equilibria match).
+      What drives an FP32 evaluation away from the FP64 one: the FP64 oracle
+      with only its literals rounded to FP32 drifts as far as the whole FP32
+      build (u: 1.4e-3 against 1.7e-3 in the freezing case), with its
+      lattice weights restored to FP64 by 6e-6, with the weights and c_s^2
+      restored by 2e-12 -- the FP32 weights sum to 1 + O(1e-8), so the
+      equilibria make or destroy mass every step.  With
+      complementary rest weights the FP32 build is 4-8 times closer (u 2.2e-4
+      / 6.5e-4); what remains is FP32 arithmetic in the closure and the
+      collisions (the FP32 build with those two in FP64 stays within 8.1e-5),
+      which a fixed 1e-4 at 1000 steps would need to be evaluated in FP64.
+      Measured GPU / single_cw ratios: at most 1.43 (u_y, freezing)."""
     cfg, phi, T, C = STRICT[case]()
     print(f"[strict] {case}", flush=True)
     s = _solver(cfg, phi, T, C)
     o = Oracle(cfg, phi, T, C, threads=THREADS)
-    o32 = Oracle(cfg, phi, T, C, threads=THREADS, variant="single")
+    o32 = Oracle(cfg, phi, T, C, threads=THREADS, variant="single_cw")
     s.step(300)
     o.step(300)
     got, ref = s.fields(), o.fields()
@@ -357,5 +364,5 @@ def test_strict_trajectory_parity(case):
     print(f"[strict] {case} 1000 steps gpu " + " ".join(f"{k}={v:.1e}" for k, v in errs.items())
           + " | fp32 oracle " + " ".join(f"{k}={v:.1e}" for k, v in dev32.items()), flush=True)
     for k, e in errs.items():
-        assert e <= max(1e-4, dev32[k]), (case, 1000, k, e, dev32[k])
+        assert e <= max(1e-4, 2.0 * dev32[k]), (case, 1000, k, e, dev32[k])
     assert s.totals()["nonfinite"] == 0
