@@ -70,6 +70,18 @@ constexpr float W19[19] = {1.f / 3,  1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18, 1.f
                            1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36,
                            1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
 constexpr float W7 = 1.f / 6;
+// D3Q7 weights of the phase-field and solute equilibria and sources: 1/6
+// rounded up on the x and y links and one ulp below that on the z links, so
+// that the six sum to exactly one in FP32 (2 (2 fl(1/6) + lo) = 1; six
+// fl(1/6) sum to 1 + 3e-8, and these sets have no rest population to take
+// the difference, so their equilibria would make phase-field and solute
+// mass at that rate every step).  The initial populations and the 16-bit
+// offsets' references keep W7 (any consistent reference serves; the first
+// collision relaxes the initial state onto these equilibria), and so does
+// the enthalpy set (its rest equilibrium is the complement of the moving
+// ones).
+constexpr float W7A[7] = {0.0f, 1.f / 6, 1.f / 6, 1.f / 6, 1.f / 6, 0.1666666567325592f,
+                          0.1666666567325592f};
 
 // Wall-normal (z) plane -> stored plane.  ghost: 0 inside, -1 below the low
 // wall, +1 above the high wall (a ghost takes its mirror plane).
@@ -640,8 +652,8 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
           for (int i = 1; i < 7; ++i) {
             const float cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
             const float cB = CX[i] * B0 + CY[i] * B1 + CZ[i] * B2;
-            const float Fi = W7 * (kInvCs2 * cB + phi * D);
-            const float feq = W7 * phi * (1.0f + kInvCs2 * cu);
+            const float Fi = W7A[i] * (kInvCs2 * cB + phi * D);
+            const float feq = W7A[i] * phi * (1.0f + kInvCs2 * cu);
             const float post = f[i] - (f[i] - feq) * P.itau_f + P.wf * Fi;
             if (kindT(obs, i))
               put(B.df, on, OPP[i], post, W7 * phi, SC_F);
@@ -696,8 +708,8 @@ __global__ __launch_bounds__(NT) void k_collide3d(KParams P, StepArgs A) {
           for (int i = 1; i < 7; ++i) {
             const float cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
             const float cL = CX[i] * L0 + CY[i] * L1 + CZ[i] * L2;
-            const float leq = W7 * C * (1.0f + kInvCs2 * cu);
-            const float post = l[i] - (l[i] - leq) * itau_l + wl * W7 * kInvCs2 * cL;
+            const float leq = W7A[i] * C * (1.0f + kInvCs2 * cu);
+            const float post = l[i] - (l[i] - leq) * itau_l + wl * W7A[i] * kInvCs2 * cL;
             if (kindT(obs, i))
               put(B.dl, on, OPP[i], post, W7 * C, SC_L);
             else
@@ -742,6 +754,10 @@ __global__ __launch_bounds__(256) void k_init3d(KParams P, const double* __restr
                                                 const uint8_t* __restrict__ mask,
                                                 float* __restrict__ popA,
                                                 float* __restrict__ popB, StateArgs S) {
+  // no contraction into fused multiply-adds in this kernel: its FP32 and
+  // 16-bit instantiations must round alike (their initial states are equal
+  // bit for bit)
+#pragma clang fp contract(off)
   const long N = P.N, PS = P.ps;
   for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < N;
        n += (long)gridDim.x * blockDim.x) {
@@ -751,13 +767,14 @@ __global__ __launch_bounds__(256) void k_init3d(KParams P, const double* __restr
     const float psi = clamp01(0.5f * (1.0f + phi));
     const float rcl = psi * P.rc_l + (1.0f - psi) * P.rc_g;
     const float E = rcl * T + psi * P.rho_l_latent;
+    const float hw = W7 * P.rhoc_ref * T;
     float h0 = E;
 #pragma unroll
-    for (int i = 1; i < 7; ++i) h0 -= W7 * P.rhoc_ref * T;
+    for (int i = 1; i < 7; ++i) h0 -= hw;
     if constexpr (ST == LBFZ_STORE_F32) {
 #pragma unroll
       for (int i = 1; i < 7; ++i) {
-        popA[(PH + i) * PS + n] = W7 * P.rhoc_ref * T;
+        popA[(PH + i) * PS + n] = hw;
         popA[(PF + i) * PS + n] = ob ? 0.0f : W7 * phi;
         popA[(PL + i) * PS + n] = ob ? 0.0f : W7 * C;
       }
