@@ -364,7 +364,8 @@ def copy64_errors(forms) -> dict:
     (drop radius 16, obstacle radius 3) in each storage form, against the
     FP64 oracle's fields at step 5000 stored in tests/golden (written by the
     script beside them), with the oracle's own spread under FP32-sized noise
-    from the same file: max |gpu - oracle| / max |oracle| over fluid nodes."""
+    and the deviations of its two single-precision builds from the same file:
+    max |gpu - oracle| / max |oracle| over fluid nodes."""
     from paper_2511_09422_amd.lbfz import Solver
     from paper_2511_09422_amd.workloads import droplet_3d
     ref = np.load(os.path.join(ROOT, "tests", "golden", "droplet3d_64_5000.npz"))
@@ -374,7 +375,9 @@ def copy64_errors(forms) -> dict:
     out = {"workload": "64^3 copy of the 3D droplet, R=16, obstacle radius 3, 5000 steps",
            "oracle_spread": dict(zip(names, [float(f"{v:.3g}") for v in ref["spread"]])),
            "oracle_single_precision": dict(zip(names, [float(f"{v:.3g}")
-                                                       for v in ref["dev_single"]]))}
+                                                       for v in ref["dev_single"]])),
+           "oracle_single_precision_weights_sum_to_one":
+               dict(zip(names, [float(f"{v:.3g}") for v in ref["dev_single_cw"]]))}
     for f in forms:
         s = Solver(cfg, phi, T, C, mask=mask, device=0, storage=f)
         s.step(5000)

@@ -98,8 +98,12 @@ static void lat_init(lat_t* L, int dim, int flow) {
    * the weights sum to one there.  Rounded to FP32, 1/3, 1/6, 1/9, 1/36 sum
    * to 1 + O(1e-8); the equilibria then create or destroy mass at that rate
    * every step, which is most of how far an FP32 evaluation drifts from the
-   * FP64 one.  A lattice without a rest weight (D3Q7) is left as it is. */
-  if (L->w[0] != 0.0) {
+   * FP64 one.  A lattice without a rest weight (D3Q7) takes its +-z pair as
+   * (1 - 4 w_x) / 2 instead, one ulp below fl(1/6) in FP32: every step of
+   * that expression is exact there, and the six weights sum to one. */
+  if (L->w[0] == 0.0 && L->q == 7) {
+    L->w[5] = L->w[6] = (1.0 - 4.0 * L->w[1]) / 2.0;
+  } else if (L->w[0] != 0.0) {
     /* 1 - m1 w1 - m2 w2 over the distinct moving weights (m their counts):
      * exact in FP32 for D2Q5 (1 - 4 / 6 by Sterbenz) */
     double rest = 1.0;

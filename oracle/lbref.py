@@ -47,9 +47,11 @@ class LbrefParamsSingle(ctypes.Structure):
 # reading (the interface normal); "single" is the same source with every
 # double made a float (and single-precision constants), the scheme evaluated
 # in FP32 arithmetic and storage, as a measure of what FP32 alone does to a
-# trajectory; "single_cw" the same with each rest weight taken as the FP32
-# complement of the moving weights (they then sum to one in FP32, as the GPU
-# kernels' rest equilibria, the complements of the moving ones, do).
+# trajectory; "single_cw" the same with weights that sum to one in FP32: each
+# rest weight the complement of the moving ones (as the GPU kernels' rest
+# equilibria, the complements of the moving ones, are), and the D3Q7 set,
+# which has no rest weight, with its +-z pair one ulp below fl(1/6) (as the
+# GPU's 3D phase-field and solute collisions take it).
 VARIANTS = {"hard_cutoff": ["-DLBREF_HARD_NORMAL_CUTOFF"],
             "single": ["-fsingle-precision-constant"],
             "single_cw": ["-fsingle-precision-constant", "-DLBREF_REST_WEIGHT_COMPLEMENT"]}
@@ -104,7 +106,7 @@ def lib(variant=None):
             build(variant=variant)
         L = ctypes.CDLL(path)
         single = variant in SINGLE
-        dp = ctypes.POINTER(ctypes.c_float if single else (ctypes.c_float if single else ctypes.c_double))
+        dp = ctypes.POINTER(ctypes.c_float if single else ctypes.c_double)
         pp = ctypes.POINTER(LbrefParamsSingle if single else LbrefParams)
         L.lbref_create.argtypes = [pp, dp, dp, dp, ctypes.c_void_p, ctypes.c_void_p]
         L.lbref_create.restype = ctypes.c_int

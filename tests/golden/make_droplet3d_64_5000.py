@@ -7,11 +7,13 @@ noise (uniform, 6e-8) before every step: max |noisy - clean| / max |clean|
 per field, and the deviation of the oracle's own single-precision build
 (variant "single": the same source with every double a float) from it
 after the same 5000 steps -- what evaluating the scheme in FP32 does to
-this trajectory.  It calls only the oracle and the seeded input generator.
+this trajectory -- and that of the single-precision build whose weights sum
+to one in FP32 (variant "single_cw").  It calls only the oracle and the
+seeded input generator.
 
     python tests/golden/make_droplet3d_64_5000.py [threads] [--single-only]
 
---single-only adds the single-precision deviation to an existing file.
+--single-only adds the two single-precision deviations to an existing file.
 """
 import os
 import sys
@@ -30,11 +32,12 @@ STEPS = 5000
 NOISE = 6e-8
 
 
-def single_deviation(cfg, phi, T, C, mask, ref, threads: int) -> np.ndarray:
+def single_deviation(cfg, phi, T, C, mask, ref, threads: int,
+                     variant: str = "single") -> np.ndarray:
     """max |single - FP64| / max |FP64| over fluid nodes, per field, after
-    STEPS steps of the oracle's single-precision build."""
+    STEPS steps of one of the oracle's single-precision builds."""
     fluid = mask == 0
-    o = Oracle(cfg, phi, T, C, mask=mask, threads=threads, variant="single")
+    o = Oracle(cfg, phi, T, C, mask=mask, threads=threads, variant=variant)
     o.step(STEPS)
     f = o.fields()
     return np.array([float(np.abs(f[k][fluid] - ref[k][fluid]).max() /
@@ -49,8 +52,10 @@ def main(threads: int, single_only: bool = False) -> None:
         old = dict(np.load(path))
         ref = {f: old[f].astype(np.float64) for f in FIELDS}
         old["dev_single"] = single_deviation(cfg, phi, T, C, mask, ref, threads)
+        old["dev_single_cw"] = single_deviation(cfg, phi, T, C, mask, ref, threads, "single_cw")
         np.savez_compressed(path, **old)
-        print("single " + " ".join(f"{f}={v:.2e}" for f, v in zip(FIELDS, old["dev_single"])))
+        for k in ("dev_single", "dev_single_cw"):
+            print(k + " " + " ".join(f"{f}={v:.2e}" for f, v in zip(FIELDS, old[k])))
         return
     t0 = time.time()
     o = Oracle(cfg, phi, T, C, mask=mask, threads=threads)
@@ -80,6 +85,7 @@ def main(threads: int, single_only: bool = False) -> None:
     out["totals"] = np.array([tot["sum_f"], tot["sum_l"], tot["sum_h"], tot["mpc"],
                               tot["vol_solid"], tot["vol_sl"]])
     out["dev_single"] = single_deviation(cfg, phi, T, C, mask, ref, threads)
+    out["dev_single_cw"] = single_deviation(cfg, phi, T, C, mask, ref, threads, "single_cw")
     np.savez_compressed(path, **out)
     print("spread " + " ".join(f"{f}={spread[f]:.2e}" for f in FIELDS), flush=True)
 

@@ -189,18 +189,24 @@ def test_3d_64_copy_5000_steps_against_stored_oracle(storage):
     """The 64^3 copy of the 3D workload (drop radius 16, obstacle radius 3)
     after 5000 steps against the FP64 oracle's fields at step 5000, stored by
     tests/golden/make_droplet3d_64_5000.py (which calls only the oracle),
-    with the spread of the same oracle under FP32-sized noise stored beside
-    them, and the deviation of the oracle's own single-precision build after
-    the same 5000 steps.  FP32 storage within max(1e-4, 3 x that spread, 1.25
-    x the single-precision deviation) per field: after 5000 steps the
-    trajectory's FP32 sensitivity dominates (both the GPU and the oracle's
-    single-precision build deviate by 9e-3 on phi and 0.18 on u_x); the
-    16-bit forms' per-field errors are stated (printed) and held to a guard
-    against blow-ups only."""
+    with three references stored beside them: the spread of the same oracle
+    under FP32-sized noise, and the deviations after the same 5000 steps of
+    two single-precision builds of the oracle, one with every double a float
+    (phi 9e-3, u_x 0.18) and one whose lattice weights also sum to one in
+    FP32 (rest weights the complements of the moving ones; the D3Q7 +-z pair
+    one ulp below fl(1/6), as the GPU kernels take them: phi 5.5e-3, u_x
+    1.2e-2).  After 5000 steps the trajectory's sensitivity to FP32
+    evaluation dominates, and the second build is the FP32 evaluation of
+    this scheme.  FP32 storage: within max(1e-4, 3 x the spread, 1.5 x that
+    build's deviation) per field (measured GPU / build ratios 0.93-1.00).
+    FP16 storage: within 2.5 x that build's deviation (measured at most
+    1.64, u_y).  BF16 storage (8-bit significand) is held to a guard against
+    blow-ups (measured u 0.2, phi 2.2e-2)."""
     ref = np.load(GOLDEN_5000)
     names = [str(n) for n in ref["fields"]]
     spread = dict(zip(names, ref["spread"].tolist()))
     dev32 = dict(zip(names, ref["dev_single"].tolist()))
+    dev_cw = dict(zip(names, ref["dev_single_cw"].tolist()))
     cfg, phi, T, C, mask = droplet_3d(64, R=16.0, imp_R=3.0, seed=1)
     print(f"[3d 5000] {storage}", flush=True)
     s = Solver(cfg, phi, T, C, mask=mask, storage=storage)
@@ -209,11 +215,14 @@ def test_3d_64_copy_5000_steps_against_stored_oracle(storage):
     errs = {k: rel_linf(got[k], ref[k].astype(np.float64), mask) for k in names}
     print(f"[3d 5000] {storage} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
           " | oracle spread " + " ".join(f"{k}={v:.2e}" for k, v in spread.items()) +
-          " | single-precision oracle " + " ".join(f"{k}={v:.2e}" for k, v in dev32.items()),
-          flush=True)
+          " | single-precision oracle " + " ".join(f"{k}={v:.2e}" for k, v in dev32.items()) +
+          " | the same, weights summing to one " +
+          " ".join(f"{k}={v:.2e}" for k, v in dev_cw.items()), flush=True)
     assert s.totals()["nonfinite"] == 0
     for k, e in errs.items():
         if storage == "f32":
-            assert e <= max(1e-4, 3.0 * spread[k], 1.25 * dev32[k]), (k, e, spread[k], dev32[k])
+            assert e <= max(1e-4, 3.0 * spread[k], 1.5 * dev_cw[k]), (k, e, spread[k], dev_cw[k])
+        elif storage == "f16":
+            assert e <= 2.5 * dev_cw[k], (storage, k, e, dev_cw[k])
         else:
             assert e <= 0.5, (storage, k, e)
