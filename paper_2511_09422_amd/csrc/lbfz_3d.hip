@@ -4,7 +4,8 @@
 // (bounce-back for f, g, l; h conducts through it).
 //
 // Two launches per step, each one node per thread on tiles of 64 x TY x TZ
-// nodes (FP32 storage 64 x 1 x 4, 16-bit 64 x 2 x 2; one x row per wave):
+// nodes, one x row per wave (closure: FP32 storage 64 x 4 x 4, 16-bit
+// 64 x 4 x 2; collision: 64 x 1 x 4, 64 x 2 x 2):
 //   k_close3d    the pointwise closure of every node -- phi, T, C, f_s from
 //                its f, h, l populations and div u^{n-1} from a velocity ring
 //                staged in LDS -- into the closure-field buffer of the level;
@@ -37,7 +38,8 @@ namespace lbfz {
 
 namespace {
 
-// Tile of one block: 64 x TY x TZ nodes, one x row per wave, 256 threads.
+// Tile of one block of the collide launch: 64 x TY x TZ nodes, one x row per
+// wave, 256 threads.
 // A tile that spans several z planes re-reads fewer ring planes per node
 // (2 / TZ) from beyond the L2; at 256^3 FP32 storage runs fastest with
 // 64 x 1 x 4 tiles (1.776 -> 1.734 ms per step against 64 x 4 x 1), 16-bit
@@ -52,6 +54,20 @@ struct G3 {
   static constexpr int RS = HZ * HP;              // ring slots
   static constexpr int RIT = (RS + NT - 1) / NT;  // ring slots per thread
   static_assert(TX * TY * TZ == NT, "tile shape");
+};
+// Tiles of the closure launch.  It holds few registers, so it takes larger
+// blocks (1024 / 512 threads), which re-read fewer velocity-ring slots per
+// node (2.3 / 2.6 against 4.6 / 4.1 on the collide launch's tiles): 256^3
+// step 1.750 -> 1.717 ms (FP32), 1.295 -> 1.269 ms (16-bit), results
+// bit-identical (the closure is pointwise but for the ring).
+template <int ST>
+struct GC3 {
+  static constexpr int TY = 4, TZ = ST == LBFZ_STORE_F32 ? 4 : 2;
+  static constexpr int NT = TX * TY * TZ;
+  static constexpr int HY = TY + 2, HZ = TZ + 2;
+  static constexpr int HP = HX * HY;
+  static constexpr int RS = HZ * HP;
+  static constexpr int RIT = (RS + NT - 1) / NT;
 };
 
 constexpr int PF = 0, PG = 7, PH = 26, PL = 33;  // FP32 layout
@@ -231,9 +247,9 @@ __device__ __forceinline__ Tile3 tile3(const KParams& P, bool rev) {
 // ---------------------------------------------------------------------------
 // Closure: phi, T, C, f_s and div u^{n-1} of every node (Sec. 3.1, 3.3, Eq. NS1).
 template <int ST>
-__global__ __launch_bounds__(NT) void k_close3d(KParams P, StepArgs A) {
-  using G = G3<ST>;
-  constexpr int HP = G::HP, RS = G::RS, RIT = G::RIT;
+__global__ __launch_bounds__(GC3<ST>::NT) void k_close3d(KParams P, StepArgs A) {
+  using G = GC3<ST>;
+  constexpr int HP = G::HP, RS = G::RS, RIT = G::RIT, NT = G::NT;
   __shared__ float s_u[3][RS];  // previous velocity on the tile + 1-ring
   __shared__ uint8_t s_m[RS];   // obstacle mask on the ring (ghost planes: 0)
   const Tile3 t = tile3<G::TY, G::TZ>(P, false);
@@ -881,7 +897,15 @@ int grid3(long N) { return (int)std::min<long>((N + 255) / 256, 65536); }
 
 template <int ST>
 void launch_step3d_st(const KParams& P, const StepArgs& A, bool dry, hipStream_t st) {
-  hipLaunchKernelGGL((k_close3d<ST>), dim3(P.nblk), dim3(NT), 0, st, P, A);
+  {
+    // the closure launch's own tiles: the same x columns, its own y and z blocks
+    using G = GC3<ST>;
+    KParams Pc = P;
+    Pc.nblk_y = (P.ny + G::TY - 1) / G::TY;
+    Pc.nblk_z = (P.nz + G::TZ - 1) / G::TZ;
+    Pc.nblk = Pc.nblk_x * Pc.nblk_y * Pc.nblk_z;
+    hipLaunchKernelGGL((k_close3d<ST>), dim3(Pc.nblk), dim3(G::NT), 0, st, Pc, A);
+  }
   if (dry)
     hipLaunchKernelGGL((k_collide3d<true, ST>), dim3(P.nblk), dim3(NT), 0, st, P, A);
   else
