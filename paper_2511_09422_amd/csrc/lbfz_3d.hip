@@ -5,7 +5,7 @@
 //
 // Two launches per step, each one node per thread on tiles of 64 x TY x TZ
 // nodes, one x row per wave (closure: FP32 storage 64 x 4 x 4, 16-bit
-// 64 x 4 x 2; collision: 64 x 1 x 4, 64 x 2 x 2):
+// 64 x 4 x 2; collision: 64 x 1 x 4, 64 x 4 x 1):
 //   k_close3d    the pointwise closure of every node -- phi, T, C, f_s from
 //                its f, h, l populations and div u^{n-1} from a velocity ring
 //                staged in LDS -- into the closure-field buffer of the level;
@@ -42,12 +42,13 @@ namespace {
 // wave, 256 threads.
 // A tile that spans several z planes re-reads fewer ring planes per node
 // (2 / TZ) from beyond the L2; at 256^3 FP32 storage runs fastest with
-// 64 x 1 x 4 tiles (1.776 -> 1.734 ms per step against 64 x 4 x 1), 16-bit
-// storage with 64 x 2 x 2 (1.393 -> 1.379 ms; 64 x 1 x 4: 1.424 ms).
+// 64 x 1 x 4 tiles (step 1.719 ms; 64 x 2 x 2: 1.741, 64 x 4 x 1: 1.774),
+// 16-bit storage with 64 x 4 x 1 (1.254 ms; 64 x 2 x 2: 1.268, 64 x 1 x 4:
+// 1.258), the closure launch on its own tiles in every case.
 constexpr int TX = 64, NT = 256, HX = TX + 2;
 template <int ST>
 struct G3 {
-  static constexpr int TY = ST == LBFZ_STORE_F32 ? 1 : 2;
+  static constexpr int TY = ST == LBFZ_STORE_F32 ? 1 : 4;
   static constexpr int TZ = NT / (TX * TY);
   static constexpr int HY = TY + 2, HZ = TZ + 2;  // tile + 1-ring
   static constexpr int HP = HX * HY;              // ring slots per plane
@@ -57,9 +58,10 @@ struct G3 {
 };
 // Tiles of the closure launch.  It holds few registers, so it takes larger
 // blocks (1024 / 512 threads), which re-read fewer velocity-ring slots per
-// node (2.3 / 2.6 against 4.6 / 4.1 on the collide launch's tiles): 256^3
-// step 1.750 -> 1.717 ms (FP32), 1.295 -> 1.269 ms (16-bit), results
-// bit-identical (the closure is pointwise but for the ring).
+// node (2.3 / 2.6 against 4.6 / 4.1 on 64 x 1 x 4 / 64 x 2 x 2 tiles): 256^3
+// step 1.750 -> 1.717 ms (FP32), 1.295 -> 1.269 ms (16-bit, both launches on
+// 64 x 2 x 2 before), results bit-identical (the closure is pointwise but
+// for the ring).
 template <int ST>
 struct GC3 {
   static constexpr int TY = 4, TZ = ST == LBFZ_STORE_F32 ? 4 : 2;
