@@ -28,7 +28,9 @@ def rel_linf(got, ref, mask=None):
     return float(np.abs(g - ref).max() / max(np.abs(ref).max(), 1e-30))
 
 
-def _box(nx, ny, nz, R, walls=1, seed=7, **over):
+def _box(nx, ny, nz, R, walls=1, seed=7, obstacle=None, **over):
+    """A drop of radius R on the low wall (or centred, periodic) of an
+    nx x ny x nz box; obstacle = (x, y, z, radius) adds a spherical mask."""
     cfg = base_params(dim=3, nx=nx, ny=ny, nz=nz, walls=walls, **over)
     if not walls:
         cfg["t_lo_dirichlet"] = 0
@@ -42,13 +44,21 @@ def _box(nx, ny, nz, R, walls=1, seed=7, **over):
     if not walls:
         T = T - 0.4 * np.exp(-d ** 2 / 20.0)
     C = 0.05 * np.clip((1 + phi) / 2, 0, 1)
-    return cfg, phi, T, C, None
+    mask = None
+    if obstacle is not None:
+        ox, oy, oz, orad = obstacle
+        mask = (((x - ox) ** 2 + (y - oy) ** 2 + (z - oz) ** 2) <= orad ** 2).astype(np.uint8)
+    return cfg, phi, T, C, mask
 
 
 CASES = {
     "drop16": lambda: droplet_3d(16, R=7.0, imp_R=2.0, seed=1),
     "box40x20x70": lambda: _box(40, 20, 70, R=14.0, sigma_T=-5e-4),
     "periodic": lambda: _box(24, 24, 24, R=8.0, walls=0),
+    # ragged against every tile shape of both launches (64 x {1,4} x {1,2,4})
+    # in x, y and z, with an obstacle touching a tile edge
+    "ragged70x13x11": lambda: _box(70, 13, 11, R=7.0, sigma_T=-5e-4,
+                                   obstacle=(63.5, 6.0, 3.0, 2.2)),
 }
 
 
@@ -70,7 +80,8 @@ def _oracle_from_state(cfg, st, shape, mask):
 
 
 @pytest.mark.parametrize("case,K", [("drop16", 0), ("drop16", 60), ("box40x20x70", 40),
-                                    ("periodic", 40)])
+                                    ("periodic", 40), ("ragged70x13x11", 0),
+                                    ("ragged70x13x11", 30)])
 def test_one_step_from_gpu_state_3d(case, K):
     cfg, phi, T, C, mask = CASES[case]()
     print(f"[3d one-step] {case} K={K}", flush=True)
@@ -114,7 +125,7 @@ def _noisy_spread(cfg, phi, T, C, mask, steps, ref, seeds=(1, 2)):
 
 
 @pytest.mark.parametrize("case,steps", [("drop16", 1), ("drop16", 50), ("box40x20x70", 30),
-                                        ("periodic", 30)])
+                                        ("periodic", 30), ("ragged70x13x11", 30)])
 def test_multi_step_parity_3d(case, steps):
     cfg, phi, T, C, mask = CASES[case]()
     s = _solver(cfg, phi, T, C, mask)

@@ -23,7 +23,7 @@ SETS = (("f", slice(0, 7), 0, W7), ("g", slice(7, 26), 1, W19), ("h", slice(26, 
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-@pytest.mark.parametrize("case", ["drop16", "box40x20x70"])
+@pytest.mark.parametrize("case", ["drop16", "box40x20x70", "ragged70x13x11"])
 def test_initial_state_equals_fp32_3d(storage, case):
     cfg, phi, T, C, mask = CASES[case]()
     a = Solver(cfg, phi, T, C, mask=mask, storage="f32").get_state()
@@ -33,7 +33,7 @@ def test_initial_state_equals_fp32_3d(storage, case):
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("case,K", [("drop16", 0), ("drop16", 60), ("box40x20x70", 40),
-                                    ("periodic", 40)])
+                                    ("periodic", 40), ("ragged70x13x11", 30)])
 def test_one_step_quantisation_bound_3d(storage, case, K):
     cfg, phi, T, C, mask = CASES[case]()
     print(f"[3d 16bit one-step] {storage} {case} K={K}", flush=True)
