@@ -57,3 +57,37 @@ def test_budgets_3d_with_obstacle():
     o.step(40)
     t = _check_budgets(o, t0, np.abs(phi[mask == 0]).sum(), check_h=True)
     assert t["vol_solid"] > 5 and abs(t["mpc"]) > 0.1
+
+
+def test_d3q7_fp32_weights_sum_to_one():
+    """The D3Q7 weights of the FP32 evaluations (the GPU kernels' 3D
+    phase-field and solute collisions and the oracle's single_cw build):
+    fl(1/6) on the x and y links, (1 - 4 fl(1/6)) / 2 on the z links, which
+    is one ulp below fl(1/6), every step of it exact in FP32.  The six sum to
+    exactly one as reals; six fl(1/6) do not."""
+    from fractions import Fraction
+    hi = np.float32(1.0 / 6.0)
+    lo = (np.float32(1.0) - np.float32(4.0) * hi) / np.float32(2.0)
+    assert lo.dtype == np.float32 and lo == np.nextafter(hi, np.float32(0.0))
+    assert lo == np.float32(0.1666666567325592)
+    assert 4 * Fraction(float(hi)) + 2 * Fraction(float(lo)) == 1
+    assert 6 * Fraction(float(hi)) - 1 == Fraction(1, 2 ** 25)
+
+
+def test_fp32_oracle_build_with_unit_weight_sums_conserves_mass():
+    """What the single_cw build is for: with weights summing to one in FP32
+    its phase-field and solute masses stay with the FP64 oracle's, where the
+    plain FP32 build's drift (the equilibria make mass every step).  Periodic
+    24^3 drop, 400 steps: the plain build's sum f is off by 1.4e-1 and its
+    sum l by 1.8e-3; the single_cw build's by 1.4e-3 and 1.8e-4."""
+    from tests.test_gpu_parity3d import CASES
+    cfg, phi, T, C, mask = CASES["periodic"]()
+    sums = {}
+    for v in (None, "single", "single_cw"):
+        o = Oracle(cfg, phi, T, C, mask=mask, threads=8, variant=v)
+        o.step(400)
+        sums[v] = [float(o.get_pops(w).astype(np.float64).sum()) for w in (0, 3)]
+    for k in range(2):
+        plain = abs(sums["single"][k] - sums[None][k])
+        unit = abs(sums["single_cw"][k] - sums[None][k])
+        assert unit * 5.0 < plain, (k, unit, plain)
